@@ -1,0 +1,168 @@
+/*
+ * sfd.h - batched Shifted-Fresnel reconstruction on AMD Instinct MI355X (gfx950).
+ *
+ * The operation (Shimobaba, Masuda, Ichihashi, Ito, "Real-time digital
+ * holographic microscopy observable in multi-view and multi-resolution",
+ * Section 2.1, Eqs. 1-5): a hologram u0 sampled at pitch (px0, py0) on a
+ * grid shifted by (Ox0, Oy0) is propagated over a signed distance z onto a
+ * reconstruction grid with its own size, pitch (px1, py1) and shift
+ * (Ox1, Oy1), and the intensity I = |u1|^2 is returned (Eq. 5).  A view is one
+ * such (grid, z) pair; many views of one or more holograms are computed in one
+ * call (the multi-view scheme of Section 2.2, steps 2-10, for every view).
+ *
+ * Discrete definition implemented (Eqs. 1-4 are its chirp factorisation):
+ *
+ *   u1[n1][m1] = c(z) * sum_{n0,m0} u0[n0][m0]
+ *                 * exp(i pi ((x1[m1]-x0[m0])^2 + (y1[n1]-y0[n0])^2) / (lambda z))
+ *   c(z)       = exp(i k z) * px0 * py0 / (i lambda z),   k = 2 pi / lambda
+ *   x[m]       = (m - floor(nx/2)) * px + ox,   y[n] = (n - floor(ny/2)) * py + oy
+ *
+ * i.e. centred grids with shifts in metres, the hologram's area element in
+ * c(z), and any zero padding L >= N0 + N1 - 1 per axis (the paper doubles the
+ * grid).  The intensity keeps |c|^2 = (px0 py0 / (lambda z))^2.
+ *
+ * Memory: every array argument marked "device" is device memory owned by the
+ * caller.  Images are row-major [ny][nx] (y = rows, x = columns); complex
+ * values are interleaved (re, im) float32 pairs ("complex64").  The library
+ * never allocates device memory and never synchronises the device; it
+ * enqueues work on the caller's stream.
+ *
+ * Errors: every call returns an sfd_status.  Arguments are validated on the
+ * host before any HIP call; on error nothing is enqueued and
+ * sfd_last_error() (thread-local) describes the failure.  NaN or Inf inside
+ * the data propagates, as in BLAS.
+ */
+#ifndef SFD_H
+#define SFD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SFD_OK = 0,
+  SFD_ERR_INVALID_ARG = 1, /* bad value, null or misaligned pointer */
+  SFD_ERR_UNSUPPORTED = 2, /* valid request this library does not implement (e.g. L too large) */
+  SFD_ERR_WORKSPACE = 3,   /* workspace smaller than sfd_workspace_size() */
+  SFD_ERR_HIP = 4,         /* a HIP runtime call failed; message names it */
+  SFD_ERR_INTERNAL = 5
+} sfd_status;
+
+/* A sampled plane (Section 2.1 symbol list).  nx, ny >= 1 samples along x
+ * (columns) and y (rows); pitches px, py > 0 in metres; shifts ox, oy in
+ * metres.  Sample m sits at x = (m - floor(nx/2)) * px + ox. */
+typedef struct {
+  int32_t nx, ny;
+  double px, py;
+  double ox, oy;
+} sfd_grid;
+
+/* One reconstruction view: its grid, the signed distance z != 0 from the
+ * hologram plane (metres; z < 0 back-propagates), and the index of the
+ * hologram it reads (0 <= holo < n_holo). */
+typedef struct {
+  sfd_grid out;
+  double z;
+  int32_t holo;
+} sfd_view;
+
+typedef struct sfd_plan_s* sfd_plan_t;
+
+/* Plan flags.  Exactly one input kind and at least one output kind must be
+ * set; with both output kinds, each call writes the intensities and the
+ * fields. */
+enum {
+  SFD_IN_REAL_F32 = 1u << 0,   /* holograms are float32 [n_holo][ny][nx] */
+  SFD_IN_C64 = 1u << 1,        /* holograms are complex64 fields [n_holo][ny][nx] */
+  SFD_OUT_INTENSITY = 1u << 2, /* outputs are float32 I = |u1|^2 (Eq. 5) */
+  SFD_OUT_FIELD = 1u << 3,     /* outputs are the complex64 field u1 (Eq. 1 with C1) */
+  SFD_PHASE_FP32 = 1u << 4,    /* evaluate chirp phases in FP32 instead of FP64 (comparison only) */
+  SFD_PER_VIEW_LAUNCH = 1u << 5 /* launch the kernels one view at a time (baseline for batching) */
+};
+
+/*
+ * Create a plan for n_views views of n_holo holograms that share one grid.
+ * Host only: no HIP call is made.  Chooses the padded FFT length per view and
+ * axis (smallest supported L >= N0 + N1 - 1), lays out the workspace, and
+ * precomputes the FP64 per-view scalars of Eqs. (2)-(4).
+ *   plan       [out] receives the plan handle (set to NULL on error)
+ *   wavelength lambda in metres, finite and > 0
+ *   holo_grid  grid shared by all holograms (shifts allowed)
+ *   n_holo     >= 1
+ *   views      host array of n_views >= 1 views (copied; the caller keeps ownership)
+ *   flags      SFD_IN_* | SFD_OUT_* | optional SFD_PHASE_FP32, SFD_PER_VIEW_LAUNCH
+ * Errors: SFD_ERR_INVALID_ARG for non-finite or non-positive lambda or
+ * pitches, z == 0 or non-finite, sizes < 1, holo index out of range, missing
+ * or conflicting flags; SFD_ERR_UNSUPPORTED when a padded length would exceed
+ * 8192 (the largest single-workgroup transform).
+ */
+sfd_status sfd_plan(sfd_plan_t* plan, double wavelength, const sfd_grid* holo_grid,
+                    int32_t n_holo, const sfd_view* views, int32_t n_views, uint32_t flags);
+
+/* Bytes of device workspace the plan needs for sfd_reconstruct and
+ * sfd_backward.  The workspace must stay dedicated to this plan while the plan
+ * lives (device-side descriptors are cached in it between calls). */
+sfd_status sfd_workspace_size(sfd_plan_t plan, size_t* bytes);
+
+/* Padded transform lengths chosen for view v: lx, ly (host query, for tests
+ * and benchmarks). */
+sfd_status sfd_view_lengths(sfd_plan_t plan, int32_t v, int32_t* lx, int32_t* ly);
+
+/*
+ * Reconstruct every view (Section 2.2, steps 2-10).
+ *   holo        device, n_holo x [ny][nx] float32 or complex64 (per the plan
+ *               flags), 16-byte aligned
+ *   z_or_null   host array of n_views distances overriding the plan's z (each
+ *               finite, != 0), or NULL to keep them
+ *   out         host array of n_views device pointers, each [ny][nx] of the
+ *               view's grid, float32 (intensity) or complex64 (field),
+ *               16-byte aligned; with both output flags it holds 2 n_views
+ *               pointers, the intensities first and then the fields.
+ *               Outputs must not overlap each other, the holograms or the
+ *               workspace.
+ *   workspace   device, >= sfd_workspace_size bytes, 256-byte aligned
+ *   ws_bytes    size of workspace in bytes
+ *   stream      HIP stream the work is enqueued on (0 = null stream)
+ */
+sfd_status sfd_reconstruct(sfd_plan_t plan, const void* holo, const double* z_or_null,
+                           void* const* out, void* workspace, size_t ws_bytes,
+                           hipStream_t stream);
+
+/*
+ * Gradients of a real loss through reconstruct: the adjoint (conjugate chirps
+ * and the transposed scaled convolution, A(z)^H = (px0 py0)/(px1 py1) A(-z)
+ * with the two planes swapped) and the derivative with respect to each
+ * view's z.  Requires a plan made with SFD_IN_C64.
+ *   grad_out    host array of n_views device pointers.  If field_out is NULL
+ *               each is complex64 [ny][nx]: g = dL/dRe(u1) + i dL/dIm(u1).
+ *               Otherwise each is float32 dL/dI and g = 2 (dL/dI) u1 is formed
+ *               on the device.
+ *   field_out   NULL, or host array of n_views device pointers to the complex64
+ *               fields u1 of the forward call (SFD_OUT_FIELD plan or saved)
+ *   holo        device, the forward's complex64 inputs (needed for dL/dz)
+ *   z_or_null   as in sfd_reconstruct
+ *   grad_in     device, n_holo x [ny][nx] complex64: sum over the views of each
+ *               hologram of A^H g (PyTorch's convention for complex inputs)
+ *   grad_z      device, n_views doubles receiving dL/dz, or NULL to skip the
+ *               z-derivative work
+ */
+sfd_status sfd_backward(sfd_plan_t plan, void* const* grad_out, void* const* field_out,
+                        const void* holo, const double* z_or_null, void* grad_in,
+                        double* grad_z, void* workspace, size_t ws_bytes, hipStream_t stream);
+
+/* Release the plan's host resources.  Passing NULL is allowed. */
+sfd_status sfd_destroy(sfd_plan_t plan);
+
+/* Message describing the last error on the calling thread ("" if none). */
+const char* sfd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SFD_H */

@@ -1,0 +1,83 @@
+"""ctypes view of the C-ABI in include/sfd.h (argument marshalling only)."""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libsfd.so")
+
+SFD_OK = 0
+SFD_ERR_INVALID_ARG = 1
+SFD_ERR_UNSUPPORTED = 2
+SFD_ERR_WORKSPACE = 3
+SFD_ERR_HIP = 4
+SFD_ERR_INTERNAL = 5
+STATUS_NAMES = {0: "SFD_OK", 1: "SFD_ERR_INVALID_ARG", 2: "SFD_ERR_UNSUPPORTED",
+                3: "SFD_ERR_WORKSPACE", 4: "SFD_ERR_HIP", 5: "SFD_ERR_INTERNAL"}
+
+SFD_IN_REAL_F32 = 1 << 0
+SFD_IN_C64 = 1 << 1
+SFD_OUT_INTENSITY = 1 << 2
+SFD_OUT_FIELD = 1 << 3
+SFD_PHASE_FP32 = 1 << 4
+SFD_PER_VIEW_LAUNCH = 1 << 5
+
+EXPORTED = ["sfd_plan", "sfd_workspace_size", "sfd_view_lengths", "sfd_reconstruct",
+            "sfd_backward", "sfd_destroy", "sfd_last_error"]
+
+
+class SfdGrid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("px", ctypes.c_double), ("py", ctypes.c_double),
+                ("ox", ctypes.c_double), ("oy", ctypes.c_double)]
+
+
+class SfdView(ctypes.Structure):
+    _fields_ = [("out", SfdGrid), ("z", ctypes.c_double), ("holo", ctypes.c_int32)]
+
+
+class SfdError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libsfd.so.  Raises if the library has not been built: there is no
+    fallback implementation."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing; build it with `python -m paper_1001_4309_amd.build`")
+    # Load torch first so that the library binds to the HIP runtime torch uses.
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    lib.sfd_plan.argtypes = [ctypes.POINTER(vp), ctypes.c_double, ctypes.POINTER(SfdGrid), ctypes.c_int32,
+                             ctypes.POINTER(SfdView), ctypes.c_int32, ctypes.c_uint32]
+    lib.sfd_workspace_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    lib.sfd_view_lengths.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_int32)]
+    lib.sfd_reconstruct.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(vp), vp,
+                                    ctypes.c_size_t, vp]
+    lib.sfd_backward.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp, ctypes.POINTER(ctypes.c_double),
+                                 vp, vp, vp, ctypes.c_size_t, vp]
+    lib.sfd_destroy.argtypes = [vp]
+    lib.sfd_last_error.argtypes = []
+    lib.sfd_last_error.restype = ctypes.c_char_p
+    for name in ("sfd_plan", "sfd_workspace_size", "sfd_view_lengths", "sfd_reconstruct", "sfd_backward",
+                 "sfd_destroy"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def check(status: int) -> None:
+    if status != SFD_OK:
+        raise SfdError(status, load().sfd_last_error().decode())

@@ -1,0 +1,559 @@
+// C-ABI of the batched Shifted-Fresnel library: validation, planning,
+// workspace layout and launch sequencing.  See include/sfd.h for the
+// contract of every entry point.
+#include "sfd.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "sfd_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+sfd_status fail(sfd_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define SFD_HIP_TRY(expr)                                                                 \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(SFD_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));        \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+bool grid_ok(const sfd_grid& g, std::string* why, const char* what) {
+  char buf[256];
+  if (g.nx < 1 || g.ny < 1) {
+    std::snprintf(buf, sizeof buf, "%s: sizes must be >= 1 (got %d x %d)", what, g.nx, g.ny);
+    *why = buf;
+    return false;
+  }
+  if (!finite_pos(g.px) || !finite_pos(g.py)) {
+    std::snprintf(buf, sizeof buf, "%s: pitches must be finite and > 0", what);
+    *why = buf;
+    return false;
+  }
+  if (!std::isfinite(g.ox) || !std::isfinite(g.oy)) {
+    std::snprintf(buf, sizeof buf, "%s: shifts must be finite", what);
+    *why = buf;
+    return false;
+  }
+  return true;
+}
+
+// Smallest supported padded length for a linear convolution of n0 inputs
+// onto n1 outputs (reading of steps 2 and 9: any L >= n0 + n1 - 1 is exact).
+int choose_length(int n0, int n1) {
+  const long need = (long)n0 + (long)n1 - 1;
+  for (int L = 64; L <= 8192; L *= 2)
+    if (L >= need) return L;
+  return -1;
+}
+
+// Per-axis FP64 scalars of Eqs. (2)-(4) (see sfd_internal.h).
+struct AxisScalars {
+  double a0, a1, p0, p1, inv_lz, S, c1;
+};
+
+AxisScalars axis_scalars(int n0, double p0, double o0, int n1, double p1, double o1, double lam, double z) {
+  AxisScalars a;
+  a.p0 = p0;
+  a.p1 = p1;
+  a.a0 = -(double)(n0 / 2) * p0 + o0;
+  a.a1 = -(double)(n1 / 2) * p1 + o1;
+  a.inv_lz = 1.0 / (lam * z);
+  a.S = p0 * p1 / (lam * z);
+  a.c1 = a.a1 / p1;
+  return a;
+}
+
+// c(z) = exp(i k z) px0 py0 / (i lambda z) = (px0 py0 / (lambda z)) exp(i pi (2 z / lambda - 1/2)),
+// with the half-turn count reduced in FP64 before sin/cos.
+void prefactor(double lam, double z, double px0, double py0, double* re, double* im) {
+  const double turns = 2.0 * z / lam - 0.5;  // in units of pi
+  const double r = turns - 2.0 * std::nearbyint(0.5 * turns);
+  const double mag = px0 * py0 / (lam * z);
+  *re = mag * std::cos(M_PI * r);
+  *im = mag * std::sin(M_PI * r);
+}
+
+struct ViewLayout {
+  int lx = 0, ly = 0;
+  size_t prex = 0, prey = 0, postx = 0, posty = 0, hx = 0, hy = 0, inter = 0;
+};
+
+}  // namespace
+
+struct sfd_plan_s {
+  double lam = 0;
+  sfd_grid holo{};
+  int n_holo = 0;
+  std::vector<sfd_view> views;
+  uint32_t flags = 0;
+
+  std::vector<ViewLayout> lay;
+  std::vector<int> lengths;           // distinct L values used
+  std::map<int, size_t> tw_off;       // twiddle table per L
+  size_t desc_off = 0, desc_bytes = 0;
+  size_t ws_bytes = 0;
+
+  // Descriptor upload state.
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
+  hipEvent_t upload_event = nullptr;
+  std::vector<unsigned char> last_desc;
+  void* last_ws = nullptr;
+
+  ~sfd_plan_s() {
+    if (upload_event) (void)hipEventDestroy(upload_event);
+    if (pinned) (void)hipHostFree(pinned);
+  }
+};
+
+namespace {
+
+// Host images of the device descriptors for one forward call, in the order
+// they are laid out in the workspace descriptor area.
+struct CallDescs {
+  std::vector<sfd::AxisJob> axis;      // sorted by L
+  std::vector<sfd::TwiddleJob> tw;
+  std::vector<sfd::RowJob> rows;       // pass-x jobs, then pass-y jobs
+  std::vector<int> axis_L;             // L of each axis job
+  std::vector<int> row_L;              // L of each row job
+  int n_pass_x = 0;
+  int max_len = 0;
+  int max_L = 0;
+};
+
+size_t desc_capacity(int n_views, int n_lengths) {
+  return align_up(sizeof(sfd::AxisJob) * 2 * n_views) + align_up(sizeof(sfd::TwiddleJob) * n_lengths) +
+         align_up(sizeof(sfd::RowJob) * 2 * n_views);
+}
+
+sfd_status build_descs(sfd_plan_s* P, const void* holo, const double* z, void* const* out, char* ws,
+                       CallDescs* D) {
+  const int V = (int)P->views.size();
+  const bool field = (P->flags & SFD_OUT_FIELD) != 0;
+  const bool in_real = (P->flags & SFD_IN_REAL_F32) != 0;
+  const int32_t pflags = (P->flags & SFD_PHASE_FP32) ? sfd::kPhaseFp32 : 0;
+  const sfd_grid& h = P->holo;
+  const size_t in_elem = in_real ? sizeof(float) : sizeof(float2);
+  const size_t holo_stride = (size_t)h.nx * h.ny * in_elem;
+
+  struct AxisTmp {
+    sfd::AxisJob j;
+    int L;
+  };
+  std::vector<AxisTmp> ax;
+  ax.reserve(2 * V);
+  for (int v = 0; v < V; ++v) {
+    const sfd_view& w = P->views[v];
+    const ViewLayout& L = P->lay[v];
+    const double zz = z ? z[v] : w.z;
+    AxisScalars sx = axis_scalars(h.nx, h.px, h.ox, w.out.nx, w.out.px, w.out.ox, P->lam, zz);
+    AxisScalars sy = axis_scalars(h.ny, h.py, h.oy, w.out.ny, w.out.py, w.out.oy, P->lam, zz);
+    for (int a = 0; a < 2; ++a) {
+      const AxisScalars& s = a == 0 ? sx : sy;
+      sfd::AxisJob j{};
+      j.a0 = s.a0;
+      j.a1 = s.a1;
+      j.p0 = s.p0;
+      j.p1 = s.p1;
+      j.inv_lz = s.inv_lz;
+      j.S = s.S;
+      j.c1 = s.c1;
+      j.wscale = 0.0;
+      j.pre = reinterpret_cast<float2*>(ws + (a == 0 ? L.prex : L.prey));
+      j.post = field ? reinterpret_cast<float2*>(ws + (a == 0 ? L.postx : L.posty)) : nullptr;
+      j.H = reinterpret_cast<float2*>(ws + (a == 0 ? L.hx : L.hy));
+      j.n0 = a == 0 ? h.nx : h.ny;
+      j.n1 = a == 0 ? w.out.nx : w.out.ny;
+      j.L = a == 0 ? L.lx : L.ly;
+      j.flags = pflags;
+      ax.push_back({j, j.L});
+    }
+  }
+  if (!(P->flags & SFD_PER_VIEW_LAUNCH))
+    std::stable_sort(ax.begin(), ax.end(), [](const AxisTmp& a, const AxisTmp& b) { return a.L < b.L; });
+  D->axis.clear();
+  D->axis_L.clear();
+  D->max_len = 0;
+  D->max_L = 0;
+  for (auto& a : ax) {
+    D->axis.push_back(a.j);
+    D->axis_L.push_back(a.L);
+    D->max_len = std::max(D->max_len, a.j.n0 + a.j.n1 + a.j.L);
+    D->max_L = std::max(D->max_L, a.L);
+  }
+  D->tw.clear();
+  for (int L : P->lengths) {
+    sfd::TwiddleJob t;
+    t.tw = reinterpret_cast<float2*>(ws + P->tw_off.at(L));
+    t.L = L;
+    D->tw.push_back(t);
+  }
+
+  // Pass x (rows of the hologram) then pass y (rows of the transposed
+  // intermediate), one job per view, stable-sorted by L within each pass.
+  D->rows.clear();
+  D->row_L.clear();
+  double c_re = 1, c_im = 0;
+  std::vector<std::pair<int, sfd::RowJob>> px, py;
+  for (int v = 0; v < V; ++v) {
+    const sfd_view& w = P->views[v];
+    const ViewLayout& L = P->lay[v];
+    const double zz = z ? z[v] : w.z;
+    prefactor(P->lam, zz, h.px, h.py, &c_re, &c_im);
+    sfd::RowJob jx{};
+    jx.in = static_cast<const char*>(holo) + (size_t)w.holo * holo_stride;
+    jx.out = ws + L.inter;
+    jx.pre = reinterpret_cast<const float2*>(ws + L.prex);
+    jx.H = reinterpret_cast<const float2*>(ws + L.hx);
+    jx.post = field ? reinterpret_cast<const float2*>(ws + L.postx) : nullptr;
+    jx.scale = make_float2(1.f, 0.f);
+    jx.iscale = 1.f;
+    jx.n_rows = h.ny;
+    jx.n_in = h.nx;
+    jx.n_out = w.out.nx;
+    jx.in_ld = h.nx;
+    jx.out_ld = h.ny;
+    jx.mode = (in_real ? sfd::kInReal : 0) | (field ? sfd::kUsePost : 0) | sfd::kOutField;
+    px.push_back({L.lx, jx});
+
+    sfd::RowJob jy{};
+    jy.in = ws + L.inter;
+    const bool inten = (P->flags & SFD_OUT_INTENSITY) != 0;
+    jy.out = field ? out[inten ? V + v : v] : out[v];
+    jy.out2 = (field && inten) ? static_cast<float*>(out[v]) : nullptr;
+    jy.pre = reinterpret_cast<const float2*>(ws + L.prey);
+    jy.H = reinterpret_cast<const float2*>(ws + L.hy);
+    jy.post = field ? reinterpret_cast<const float2*>(ws + L.posty) : nullptr;
+    jy.scale = make_float2((float)c_re, (float)c_im);
+    jy.iscale = (float)(c_re * c_re + c_im * c_im);
+    jy.n_rows = w.out.nx;
+    jy.n_in = h.ny;
+    jy.n_out = w.out.ny;
+    jy.in_ld = h.ny;
+    jy.out_ld = w.out.nx;
+    jy.mode = field ? (sfd::kUsePost | sfd::kUseScale | sfd::kOutField) : sfd::kOutIntensity;
+    if (field && inten) jy.mode |= sfd::kOutIntensity;
+    if (field && inten) jy.iscale = 1.f;
+    py.push_back({L.ly, jy});
+  }
+  auto by_len = [](const std::pair<int, sfd::RowJob>& a, const std::pair<int, sfd::RowJob>& b) {
+    return a.first < b.first;
+  };
+  if (!(P->flags & SFD_PER_VIEW_LAUNCH)) {
+    std::stable_sort(px.begin(), px.end(), by_len);
+    std::stable_sort(py.begin(), py.end(), by_len);
+  }
+  for (auto& p : px) {
+    D->rows.push_back(p.second);
+    D->row_L.push_back(p.first);
+  }
+  for (auto& p : py) {
+    D->rows.push_back(p.second);
+    D->row_L.push_back(p.first);
+  }
+  D->n_pass_x = (int)px.size();
+  return SFD_OK;
+}
+
+// Serialise descriptors into the workspace layout; returns the byte image.
+void pack_descs(const sfd_plan_s* P, const CallDescs& D, std::vector<unsigned char>* img, size_t* off_axis,
+                size_t* off_tw, size_t* off_rows) {
+  const int V = (int)P->views.size();
+  *off_axis = 0;
+  *off_tw = align_up(sizeof(sfd::AxisJob) * 2 * V);
+  *off_rows = *off_tw + align_up(sizeof(sfd::TwiddleJob) * P->lengths.size());
+  const size_t total = *off_rows + sizeof(sfd::RowJob) * D.rows.size();
+  img->assign(total, 0);
+  std::memcpy(img->data() + *off_axis, D.axis.data(), sizeof(sfd::AxisJob) * D.axis.size());
+  std::memcpy(img->data() + *off_tw, D.tw.data(), sizeof(sfd::TwiddleJob) * D.tw.size());
+  std::memcpy(img->data() + *off_rows, D.rows.data(), sizeof(sfd::RowJob) * D.rows.size());
+}
+
+sfd_status upload(sfd_plan_s* P, const std::vector<unsigned char>& img, char* ws, hipStream_t stream) {
+  if (P->last_ws == ws && P->last_desc == img) return SFD_OK;
+  if (!P->upload_event) SFD_HIP_TRY(hipEventCreateWithFlags(&P->upload_event, hipEventDisableTiming));
+  if (P->pinned_bytes < img.size()) {
+    if (P->pinned) {
+      SFD_HIP_TRY(hipEventSynchronize(P->upload_event));
+      SFD_HIP_TRY(hipHostFree(P->pinned));
+      P->pinned = nullptr;
+    }
+    SFD_HIP_TRY(hipHostMalloc(&P->pinned, img.size(), hipHostMallocDefault));
+    P->pinned_bytes = img.size();
+  } else {
+    // The previous upload may still be reading the staging buffer.
+    SFD_HIP_TRY(hipEventSynchronize(P->upload_event));
+  }
+  std::memcpy(P->pinned, img.data(), img.size());
+  SFD_HIP_TRY(hipMemcpyAsync(ws + P->desc_off, P->pinned, img.size(), hipMemcpyHostToDevice, stream));
+  SFD_HIP_TRY(hipEventRecord(P->upload_event, stream));
+  P->last_desc = img;
+  P->last_ws = ws;
+  return SFD_OK;
+}
+
+// Launch the passes of row jobs [first, first + count) grouped by L.
+sfd_status launch_rows(const CallDescs& D, const sfd::RowJob* d_rows, int first, int count,
+                       const sfd_plan_s* P, char* ws, hipStream_t stream) {
+  int i = first;
+  const int end = first + count;
+  while (i < end) {
+    const int L = D.row_L[i];
+    int j = i;
+    while (j < end && D.row_L[j] == L && j - i < sfd::kMaxJobsPerLaunch) ++j;
+    sfd::PassArgs a{};
+    a.jobs = d_rows + i;
+    a.njobs = j - i;
+    const int G = sfd::rows_per_tile(L);
+    int acc = 0;
+    for (int k = i; k < j; ++k) {
+      a.tile_prefix[k - i] = acc;
+      acc += (D.rows[k].n_rows + G - 1) / G;
+    }
+    a.tile_prefix[j - i] = acc;
+    a.total_tiles = acc;
+    const float2* tw = reinterpret_cast<const float2*>(ws + P->tw_off.at(L));
+    SFD_HIP_TRY(sfd::launch_pass(L, a, tw, stream));
+    i = j;
+  }
+  return SFD_OK;
+}
+
+sfd_status check_common(sfd_plan_t plan, void* workspace, size_t ws_bytes) {
+  if (!plan) return fail(SFD_ERR_INVALID_ARG, "plan is NULL");
+  if (!workspace) return fail(SFD_ERR_INVALID_ARG, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+    return fail(SFD_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (ws_bytes < plan->ws_bytes)
+    return fail(SFD_ERR_WORKSPACE, "workspace is " + std::to_string(ws_bytes) + " bytes, plan needs " +
+                                       std::to_string(plan->ws_bytes));
+  return SFD_OK;
+}
+
+sfd_status check_z(const sfd_plan_s* P, const double* z) {
+  if (!z) return SFD_OK;
+  for (size_t v = 0; v < P->views.size(); ++v)
+    if (!std::isfinite(z[v]) || z[v] == 0.0)
+      return fail(SFD_ERR_INVALID_ARG, "z[" + std::to_string(v) + "] must be finite and non-zero");
+  return SFD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sfd_last_error(void) { return g_err.c_str(); }
+
+sfd_status sfd_plan(sfd_plan_t* plan, double wavelength, const sfd_grid* holo_grid, int32_t n_holo,
+                    const sfd_view* views, int32_t n_views, uint32_t flags) {
+  g_err.clear();
+  if (!plan) return fail(SFD_ERR_INVALID_ARG, "plan output pointer is NULL");
+  *plan = nullptr;
+  if (!finite_pos(wavelength)) return fail(SFD_ERR_INVALID_ARG, "wavelength must be finite and > 0");
+  if (!holo_grid) return fail(SFD_ERR_INVALID_ARG, "holo_grid is NULL");
+  std::string why;
+  if (!grid_ok(*holo_grid, &why, "holo_grid")) return fail(SFD_ERR_INVALID_ARG, why);
+  if (n_holo < 1) return fail(SFD_ERR_INVALID_ARG, "n_holo must be >= 1");
+  if (!views) return fail(SFD_ERR_INVALID_ARG, "views is NULL");
+  if (n_views < 1) return fail(SFD_ERR_INVALID_ARG, "n_views must be >= 1");
+  if (n_views > 65536) return fail(SFD_ERR_UNSUPPORTED, "at most 65536 views per plan");
+  const uint32_t known = SFD_IN_REAL_F32 | SFD_IN_C64 | SFD_OUT_INTENSITY | SFD_OUT_FIELD | SFD_PHASE_FP32 |
+                         SFD_PER_VIEW_LAUNCH;
+  if (flags & ~known) return fail(SFD_ERR_INVALID_ARG, "unknown flag bits");
+  if (((flags & SFD_IN_REAL_F32) != 0) == ((flags & SFD_IN_C64) != 0))
+    return fail(SFD_ERR_INVALID_ARG, "exactly one of SFD_IN_REAL_F32 and SFD_IN_C64 must be set");
+  if ((flags & (SFD_OUT_INTENSITY | SFD_OUT_FIELD)) == 0)
+    return fail(SFD_ERR_INVALID_ARG, "at least one of SFD_OUT_INTENSITY and SFD_OUT_FIELD must be set");
+  const sfd_grid& h = *holo_grid;
+  if ((long)h.nx * h.ny > (1L << 28)) return fail(SFD_ERR_UNSUPPORTED, "hologram larger than 2^28 samples");
+  for (int v = 0; v < n_views; ++v) {
+    const sfd_view& w = views[v];
+    const std::string name = "views[" + std::to_string(v) + "]";
+    if (!grid_ok(w.out, &why, name.c_str())) return fail(SFD_ERR_INVALID_ARG, why);
+    if (!std::isfinite(w.z) || w.z == 0.0) return fail(SFD_ERR_INVALID_ARG, name + ".z must be finite and non-zero");
+    if (w.holo < 0 || w.holo >= n_holo) return fail(SFD_ERR_INVALID_ARG, name + ".holo out of range");
+    if (choose_length(h.nx, w.out.nx) < 0 || choose_length(h.ny, w.out.ny) < 0)
+      return fail(SFD_ERR_UNSUPPORTED, name + ": N0 + N1 - 1 exceeds 8192 on an axis");
+  }
+
+  auto* P = new (std::nothrow) sfd_plan_s;
+  if (!P) return fail(SFD_ERR_INTERNAL, "out of host memory");
+  P->lam = wavelength;
+  P->holo = h;
+  P->n_holo = n_holo;
+  P->views.assign(views, views + n_views);
+  P->flags = flags;
+  const bool field = (flags & SFD_OUT_FIELD) != 0;
+
+  std::vector<int> ls;
+  for (int v = 0; v < n_views; ++v) {
+    ls.push_back(choose_length(h.nx, views[v].out.nx));
+    ls.push_back(choose_length(h.ny, views[v].out.ny));
+  }
+  std::sort(ls.begin(), ls.end());
+  ls.erase(std::unique(ls.begin(), ls.end()), ls.end());
+  P->lengths = ls;
+
+  size_t off = 0;
+  P->desc_off = off;
+  P->desc_bytes = desc_capacity(n_views, (int)ls.size());
+  off += P->desc_bytes;
+  for (int L : ls) {
+    P->tw_off[L] = off;
+    off += align_up(sizeof(float2) * L);
+  }
+  P->lay.resize(n_views);
+  for (int v = 0; v < n_views; ++v) {
+    ViewLayout& L = P->lay[v];
+    const sfd_grid& o = views[v].out;
+    L.lx = choose_length(h.nx, o.nx);
+    L.ly = choose_length(h.ny, o.ny);
+    auto take = [&](size_t bytes) {
+      const size_t at = off;
+      off += align_up(bytes);
+      return at;
+    };
+    L.prex = take(sizeof(float2) * h.nx);
+    L.prey = take(sizeof(float2) * h.ny);
+    if (field) {
+      L.postx = take(sizeof(float2) * o.nx);
+      L.posty = take(sizeof(float2) * o.ny);
+    }
+    L.hx = take(sizeof(float2) * L.lx);
+    L.hy = take(sizeof(float2) * L.ly);
+    L.inter = take(sizeof(float2) * (size_t)o.nx * h.ny);
+  }
+  P->ws_bytes = off;
+  *plan = P;
+  return SFD_OK;
+}
+
+sfd_status sfd_workspace_size(sfd_plan_t plan, size_t* bytes) {
+  g_err.clear();
+  if (!plan || !bytes) return fail(SFD_ERR_INVALID_ARG, "NULL argument");
+  *bytes = plan->ws_bytes;
+  return SFD_OK;
+}
+
+sfd_status sfd_view_lengths(sfd_plan_t plan, int32_t v, int32_t* lx, int32_t* ly) {
+  g_err.clear();
+  if (!plan || !lx || !ly) return fail(SFD_ERR_INVALID_ARG, "NULL argument");
+  if (v < 0 || v >= (int)plan->views.size()) return fail(SFD_ERR_INVALID_ARG, "view index out of range");
+  *lx = plan->lay[v].lx;
+  *ly = plan->lay[v].ly;
+  return SFD_OK;
+}
+
+sfd_status sfd_reconstruct(sfd_plan_t plan, const void* holo, const double* z_or_null, void* const* out,
+                           void* workspace, size_t ws_bytes, hipStream_t stream) {
+  g_err.clear();
+  sfd_status st = check_common(plan, workspace, ws_bytes);
+  if (st != SFD_OK) return st;
+  if (!holo) return fail(SFD_ERR_INVALID_ARG, "holo is NULL");
+  if (reinterpret_cast<uintptr_t>(holo) % 16) return fail(SFD_ERR_INVALID_ARG, "holo must be 16-byte aligned");
+  if (!out) return fail(SFD_ERR_INVALID_ARG, "out is NULL");
+  const int V = (int)plan->views.size();
+  const int n_out = ((plan->flags & SFD_OUT_FIELD) && (plan->flags & SFD_OUT_INTENSITY)) ? 2 * V : V;
+  for (int v = 0; v < n_out; ++v) {
+    if (!out[v]) return fail(SFD_ERR_INVALID_ARG, "out[" + std::to_string(v) + "] is NULL");
+    if (reinterpret_cast<uintptr_t>(out[v]) % 16)
+      return fail(SFD_ERR_INVALID_ARG, "out[" + std::to_string(v) + "] must be 16-byte aligned");
+  }
+  if ((st = check_z(plan, z_or_null)) != SFD_OK) return st;
+
+  char* ws = static_cast<char*>(workspace);
+  CallDescs D;
+  if ((st = build_descs(plan, holo, z_or_null, out, ws, &D)) != SFD_OK) return st;
+  std::vector<unsigned char> img;
+  size_t off_axis, off_tw, off_rows;
+  pack_descs(plan, D, &img, &off_axis, &off_tw, &off_rows);
+  if ((st = upload(plan, img, ws, stream)) != SFD_OK) return st;
+  const auto* d_axis = reinterpret_cast<const sfd::AxisJob*>(ws + plan->desc_off + off_axis);
+  const auto* d_tw = reinterpret_cast<const sfd::TwiddleJob*>(ws + plan->desc_off + off_tw);
+  const auto* d_rows = reinterpret_cast<const sfd::RowJob*>(ws + plan->desc_off + off_rows);
+
+  if (plan->flags & SFD_PER_VIEW_LAUNCH) {
+    // Baseline: every stage launched for one view at a time (axis jobs stay
+    // in view order: 2v = x, 2v + 1 = y).
+    SFD_HIP_TRY(sfd::launch_tables(d_axis, 0, 0, d_tw, (int)D.tw.size(), D.max_L, stream));
+    for (int v = 0; v < V; ++v) {
+      const sfd::AxisJob* a = d_axis + 2 * v;
+      const int mx = std::max(D.axis[2 * v].n0 + D.axis[2 * v].n1 + D.axis[2 * v].L,
+                              D.axis[2 * v + 1].n0 + D.axis[2 * v + 1].n1 + D.axis[2 * v + 1].L);
+      SFD_HIP_TRY(sfd::launch_tables(a, 2, mx, d_tw, 0, 0, stream));
+      for (int k = 0; k < 2; ++k) {
+        const int L = D.axis_L[2 * v + k];
+        SFD_HIP_TRY(sfd::launch_spectra(L, d_axis, 2 * v + k, 1,
+                                        reinterpret_cast<const float2*>(ws + plan->tw_off.at(L)), stream));
+      }
+      if ((st = launch_rows(D, d_rows, v, 1, plan, ws, stream)) != SFD_OK) return st;
+      if ((st = launch_rows(D, d_rows, D.n_pass_x + v, 1, plan, ws, stream)) != SFD_OK) return st;
+    }
+    return SFD_OK;
+  }
+  SFD_HIP_TRY(sfd::launch_tables(d_axis, (int)D.axis.size(), D.max_len, d_tw, (int)D.tw.size(), D.max_L, stream));
+  // Kernel spectra, grouped by L (axis jobs are sorted by L).
+  for (size_t i = 0; i < D.axis.size();) {
+    size_t j = i;
+    while (j < D.axis.size() && D.axis_L[j] == D.axis_L[i]) ++j;
+    const int L = D.axis_L[i];
+    SFD_HIP_TRY(sfd::launch_spectra(L, d_axis, (int)i, (int)(j - i),
+                                    reinterpret_cast<const float2*>(ws + plan->tw_off.at(L)), stream));
+    i = j;
+  }
+  if ((st = launch_rows(D, d_rows, 0, D.n_pass_x, plan, ws, stream)) != SFD_OK) return st;
+  if ((st = launch_rows(D, d_rows, D.n_pass_x, (int)D.rows.size() - D.n_pass_x, plan, ws, stream)) != SFD_OK)
+    return st;
+  return SFD_OK;
+}
+
+sfd_status sfd_backward(sfd_plan_t plan, void* const* grad_out, void* const* field_out, const void* holo,
+                        const double* z_or_null, void* grad_in, double* grad_z, void* workspace,
+                        size_t ws_bytes, hipStream_t stream) {
+  g_err.clear();
+  sfd_status st = check_common(plan, workspace, ws_bytes);
+  if (st != SFD_OK) return st;
+  if (!(plan->flags & SFD_IN_C64)) return fail(SFD_ERR_INVALID_ARG, "sfd_backward needs a plan made with SFD_IN_C64");
+  if (!grad_out) return fail(SFD_ERR_INVALID_ARG, "grad_out is NULL");
+  if (!holo || reinterpret_cast<uintptr_t>(holo) % 16)
+    return fail(SFD_ERR_INVALID_ARG, "holo must be a non-NULL 16-byte aligned device pointer");
+  if (!grad_in || reinterpret_cast<uintptr_t>(grad_in) % 16)
+    return fail(SFD_ERR_INVALID_ARG, "grad_in must be a non-NULL 16-byte aligned device pointer");
+  if (grad_z && reinterpret_cast<uintptr_t>(grad_z) % 8)
+    return fail(SFD_ERR_INVALID_ARG, "grad_z must be 8-byte aligned");
+  const int V = (int)plan->views.size();
+  for (int v = 0; v < V; ++v) {
+    if (!grad_out[v] || reinterpret_cast<uintptr_t>(grad_out[v]) % 16)
+      return fail(SFD_ERR_INVALID_ARG, "grad_out[" + std::to_string(v) + "] must be non-NULL and 16-byte aligned");
+    if (field_out && (!field_out[v] || reinterpret_cast<uintptr_t>(field_out[v]) % 16))
+      return fail(SFD_ERR_INVALID_ARG, "field_out[" + std::to_string(v) + "] must be non-NULL and 16-byte aligned");
+  }
+  if ((st = check_z(plan, z_or_null)) != SFD_OK) return st;
+  (void)stream;
+  return fail(SFD_ERR_UNSUPPORTED, "sfd_backward is not available in this build");
+}
+
+sfd_status sfd_destroy(sfd_plan_t plan) {
+  g_err.clear();
+  delete plan;
+  return SFD_OK;
+}
+
+}  // extern "C"

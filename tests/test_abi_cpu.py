@@ -1,0 +1,156 @@
+"""The C-ABI library loads, exports every declared entry point, and validates
+its arguments before touching the GPU (CPU only: no compute call is made)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sfd.h")
+
+lib_mod = pytest.importorskip("paper_1001_4309_amd._lib")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(lib_mod.LIB_PATH):
+        pytest.fail("libsfd.so is not built: run `python -m paper_1001_4309_amd.build`")
+    return lib_mod.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:sfd_status|const char\*)\s+(sfd_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("sfd_plan", "sfd_workspace_size", "sfd_reconstruct", "sfd_backward", "sfd_destroy",
+              "sfd_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for n in declared_functions():
+        assert hasattr(lib, n), f"{n} declared in include/sfd.h but not exported"
+    assert sorted(declared_functions()) == sorted(lib_mod.EXPORTED)
+
+
+def _grid(nx=64, ny=48, px=4.65e-6, py=4.65e-6, ox=0.0, oy=0.0):
+    return lib_mod.SfdGrid(nx, ny, px, py, ox, oy)
+
+
+def _plan(lib, lam=632.8e-9, holo=None, n_holo=1, views=None, flags=None):
+    holo = holo or _grid()
+    if views is None:
+        views = [lib_mod.SfdView(_grid(40, 30, 2e-6, 3e-6, 1e-4, -2e-4), 0.05, 0)]
+    arr = (lib_mod.SfdView * len(views))(*views)
+    if flags is None:
+        flags = lib_mod.SFD_IN_REAL_F32 | lib_mod.SFD_OUT_INTENSITY
+    h = ctypes.c_void_p()
+    st = lib.sfd_plan(ctypes.byref(h), lam, ctypes.byref(holo), n_holo, arr, len(views), flags)
+    return st, h
+
+
+def test_valid_plan_sizes_and_lengths(lib):
+    st, h = _plan(lib)
+    assert st == lib_mod.SFD_OK
+    n = ctypes.c_size_t()
+    assert lib.sfd_workspace_size(h, ctypes.byref(n)) == lib_mod.SFD_OK
+    assert n.value > 0 and n.value % 256 == 0
+    lx, ly = ctypes.c_int32(), ctypes.c_int32()
+    assert lib.sfd_view_lengths(h, 0, ctypes.byref(lx), ctypes.byref(ly)) == lib_mod.SFD_OK
+    # Smallest supported padded length >= N0 + N1 - 1 on each axis.
+    assert lx.value == 128 and ly.value == 128
+    assert lib.sfd_view_lengths(h, 1, ctypes.byref(lx), ctypes.byref(ly)) == lib_mod.SFD_ERR_INVALID_ARG
+    assert lib.sfd_destroy(h) == lib_mod.SFD_OK
+    assert lib.sfd_destroy(None) == lib_mod.SFD_OK
+
+
+def test_paper_size_uses_doubled_grid(lib):
+    views = [lib_mod.SfdView(_grid(1024, 1024, 8e-6, 8e-6), 0.03, 0)]
+    st, h = _plan(lib, holo=_grid(1024, 1024), views=views)
+    assert st == lib_mod.SFD_OK
+    lx, ly = ctypes.c_int32(), ctypes.c_int32()
+    lib.sfd_view_lengths(h, 0, ctypes.byref(lx), ctypes.byref(ly))
+    assert (lx.value, ly.value) == (2048, 2048)
+    lib.sfd_destroy(h)
+
+
+BAD = [
+    ("wavelength zero", dict(lam=0.0)),
+    ("wavelength nan", dict(lam=float("nan"))),
+    ("holo pitch negative", dict(holo=_grid(px=-1e-6))),
+    ("holo size zero", dict(holo=_grid(nx=0))),
+    ("holo shift inf", dict(holo=_grid(ox=float("inf")))),
+    ("n_holo zero", dict(n_holo=0)),
+    ("z zero", dict(views=[lib_mod.SfdView(_grid(), 0.0, 0)])),
+    ("z nan", dict(views=[lib_mod.SfdView(_grid(), float("nan"), 0)])),
+    ("holo index", dict(views=[lib_mod.SfdView(_grid(), 0.01, 1)])),
+    ("view pitch zero", dict(views=[lib_mod.SfdView(_grid(py=0.0), 0.01, 0)])),
+    ("no input flag", dict(flags=lib_mod.SFD_OUT_INTENSITY)),
+    ("two input flags", dict(flags=lib_mod.SFD_IN_REAL_F32 | lib_mod.SFD_IN_C64 | lib_mod.SFD_OUT_FIELD)),
+    ("no output flag", dict(flags=lib_mod.SFD_IN_REAL_F32)),
+    ("unknown flag", dict(flags=lib_mod.SFD_IN_REAL_F32 | lib_mod.SFD_OUT_FIELD | (1 << 20))),
+]
+
+
+@pytest.mark.parametrize("name,kw", BAD, ids=[b[0] for b in BAD])
+def test_invalid_plans_are_rejected(lib, name, kw):
+    st, h = _plan(lib, **kw)
+    assert st == lib_mod.SFD_ERR_INVALID_ARG, name
+    assert not h.value
+    assert lib.sfd_last_error().decode()
+
+
+def test_too_large_is_unsupported(lib):
+    views = [lib_mod.SfdView(_grid(8000, 16, 1e-6, 1e-6), 0.01, 0)]
+    st, h = _plan(lib, holo=_grid(1000, 16), views=views)
+    assert st == lib_mod.SFD_ERR_UNSUPPORTED
+    assert "8192" in lib.sfd_last_error().decode()
+
+
+def test_reconstruct_validates_before_any_hip_call(lib):
+    st, h = _plan(lib)
+    assert st == lib_mod.SFD_OK
+    n = ctypes.c_size_t()
+    lib.sfd_workspace_size(h, ctypes.byref(n))
+    fake = ctypes.c_void_p(1 << 20)  # never dereferenced: every call below fails validation
+    outs = (ctypes.c_void_p * 1)(1 << 21)
+    null_outs = (ctypes.c_void_p * 1)(0)
+    assert lib.sfd_reconstruct(None, fake, None, outs, fake, n.value, None) == lib_mod.SFD_ERR_INVALID_ARG
+    assert lib.sfd_reconstruct(h, None, None, outs, fake, n.value, None) == lib_mod.SFD_ERR_INVALID_ARG
+    assert lib.sfd_reconstruct(h, fake, None, null_outs, fake, n.value, None) == lib_mod.SFD_ERR_INVALID_ARG
+    assert lib.sfd_reconstruct(h, fake, None, outs, None, n.value, None) == lib_mod.SFD_ERR_INVALID_ARG
+    assert lib.sfd_reconstruct(h, fake, None, outs, ctypes.c_void_p((1 << 20) + 8), n.value,
+                               None) == lib_mod.SFD_ERR_INVALID_ARG
+    assert lib.sfd_reconstruct(h, ctypes.c_void_p((1 << 20) + 4), None, outs, fake, n.value,
+                               None) == lib_mod.SFD_ERR_INVALID_ARG
+    assert lib.sfd_reconstruct(h, fake, None, outs, fake, n.value - 1, None) == lib_mod.SFD_ERR_WORKSPACE
+    zbad = (ctypes.c_double * 1)(0.0)
+    assert lib.sfd_reconstruct(h, fake, zbad, outs, fake, n.value, None) == lib_mod.SFD_ERR_INVALID_ARG
+    lib.sfd_destroy(h)
+
+
+def test_backward_validates_before_any_hip_call(lib):
+    st, h = _plan(lib, flags=lib_mod.SFD_IN_C64 | lib_mod.SFD_OUT_FIELD)
+    assert st == lib_mod.SFD_OK
+    n = ctypes.c_size_t()
+    lib.sfd_workspace_size(h, ctypes.byref(n))
+    fake = ctypes.c_void_p(1 << 20)
+    g = (ctypes.c_void_p * 1)(1 << 21)
+    assert lib.sfd_backward(h, g, None, fake, None, fake, None, fake, n.value - 1,
+                            None) == lib_mod.SFD_ERR_WORKSPACE
+    assert lib.sfd_backward(h, None, None, fake, None, fake, None, fake, n.value,
+                            None) == lib_mod.SFD_ERR_INVALID_ARG
+    lib.sfd_destroy(h)
+
+
+def test_last_error_is_cleared_on_success(lib):
+    _plan(lib, lam=-1.0)
+    assert lib.sfd_last_error().decode()
+    st, h = _plan(lib)
+    assert st == lib_mod.SFD_OK and lib.sfd_last_error().decode() == ""
+    lib.sfd_destroy(h)
