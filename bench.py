@@ -1,0 +1,204 @@
+#!/usr/bin/env python3
+"""Throughput of batched Shifted-Fresnel reconstruction on one MI355X.
+
+One step = one pass of the whole reconstruction path over one batch: chirp
+tables (Eqs. 2-4), kernel spectra, the fused x and y row passes, crop and
+intensity, for every view of the batch.  The default workload is the
+paper-shaped one: a 1024 x 1024 synthetic in-line hologram (1360 x 1024
+CCD-like field of 64 point scatterers, bilinearly resized), four 1024 x 1024
+views with their own depth, pitch and shift, padded length 2048.
+
+Prints ONE JSON line on stdout; everything else goes to stderr.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "views/s (1024² hologram→1024² view) + % HBM peak; batched vs per-view launch"
+HBM_PEAK_GBPS = 8000.0
+# FP32 vector peak available to these kernels: 256 CUs x 4 SIMDs x 16 lanes x
+# 2 flops (FMA) x 2.4 GHz.  Packed dual-FP32 instructions are disabled at
+# compile time, so the 157.3 TFLOP/s packed figure is out of reach by design.
+FP32_VECTOR_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def row_flops(L: int) -> float:
+    """Algorithmic flops of one padded row transform: forward and inverse FFT
+    (5 L log2 L each, the usual nominal count) plus the spectrum multiply (6 L)."""
+    return 2 * 5 * L * math.log2(L) + 6 * L
+
+
+def pass_costs(w, plan):
+    """Per-launch algorithmic bytes and flops of the x and y passes of one batch."""
+    g = w.holo_grid
+    in_elem = 8 if w.holograms.dtype.kind == "c" else 4
+    cost = {"pass_x": [0.0, 0.0], "pass_y": [0.0, 0.0]}
+    for v, view in enumerate(w.views):
+        lx, ly = plan.lengths(v)
+        n1x, n1y = view.grid.nx, view.grid.ny
+        # x pass: read the hologram rows, write the N1x x N0y intermediate.
+        cost["pass_x"][0] += g.nx * g.ny * in_elem + n1x * g.ny * 8
+        cost["pass_x"][1] += g.ny * row_flops(lx)
+        # y pass: read the intermediate, write the N1y x N1x intensity.
+        cost["pass_y"][0] += n1x * g.ny * 8 + n1x * n1y * 4
+        cost["pass_y"][1] += n1x * row_flops(ly)
+    return cost
+
+
+def cpu_baseline(w, seconds: float):
+    import numpy as np
+    import threadpoolctl
+
+    import oracle
+    from tests.helpers import ogrid
+
+    info = threadpoolctl.threadpool_info()
+    cores = max([i.get("num_threads", 1) for i in info if i.get("user_api") == "blas"] or [1])
+    src = ogrid(w.holo_grid)
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        for view in w.views:
+            u = oracle.direct(w.holograms[view.holo], src, ogrid(view.grid), w.wavelength, view.z)
+            _ = np.abs(u) ** 2
+            n += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "views/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{n} views ({n // len(w.views)} passes over the {len(w.views)} views of the workload), "
+                      f"FP64 separable direct sum (zgemm) plus |u|^2, {dt:.1f} s"}
+
+
+def time_steps(plan, holo, outs, steps: int) -> float:
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.reconstruct(holo, outs=outs)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 5])
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-per-view", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        if int(os.environ.get("RANK", "0")) == 0:
+            print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+                  "views are independent, so a multi-GPU run would split the view list without any exchange, "
+                  "and that path is not built here.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1001_4309_amd as sfd
+    import workloads
+
+    dev = torch.device("cuda:0")
+    w = workloads.CONFIGS[args.config]()
+    holo = torch.from_numpy(np.ascontiguousarray(w.holograms)).to(dev)
+    plan = sfd.Plan(w.wavelength, w.holo_grid, len(w.holograms), w.views, device=dev)
+    outs = plan.new_outputs()
+    nv = len(w.views)
+
+    for _ in range(args.warmup):
+        plan.reconstruct(holo, outs=outs)
+    sec = time_steps(plan, holo, outs, args.steps)
+    ms_per_step = sec * 1e3
+    value = nv / sec
+    log(f"batched: {ms_per_step * 1e3:.1f} us/step, {value:.0f} views/s")
+
+    # Kernel durations from HIP events on the launch stream, over a second
+    # timed region of the same steps.
+    prof_steps = max(1, min(args.steps, 100))
+    plan.profile(True)
+    for _ in range(prof_steps):
+        plan.reconstruct(holo, outs=outs)
+    torch.cuda.synchronize()
+    rep = plan.profile_report()
+    plan.profile(False)
+    costs = pass_costs(w, plan)
+    kern = {k: {"launches": n, "avg_us": (ms / n * 1e3) if n else 0.0} for k, (n, ms) in rep.items() if n}
+    log("kernels:", json.dumps(kern))
+    dom = max(("pass_x", "pass_y"), key=lambda k: rep[k][1])
+    n_launch, tot_ms = rep[dom]
+    avg_s = tot_ms / n_launch / 1e3
+    launches_per_step = n_launch / prof_steps
+    flops = costs[dom][1] / launches_per_step
+    roofline = {"bound": "alu", "achieved": flops / avg_s / 1e12, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": flops / avg_s / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
+                "traffic": None, "kernel": dom, "avg_launch_us": avg_s * 1e6,
+                "algorithmic_flops_per_launch": flops,
+                "algorithmic_bytes_per_launch": costs[dom][0] / launches_per_step}
+    step_bytes = costs["pass_x"][0] + costs["pass_y"][0]
+    hbm = {"algorithmic_bytes_per_step": step_bytes, "achieved_GBps": step_bytes / sec / 1e9,
+           "frac_of_8TBps": step_bytes / sec / 1e9 / HBM_PEAK_GBPS}
+
+    per_view = None
+    if not args.no_per_view:
+        pv = sfd.Plan(w.wavelength, w.holo_grid, len(w.holograms), w.views, device=dev, per_view_launch=True)
+        pouts = pv.new_outputs()
+        for _ in range(args.warmup):
+            pv.reconstruct(holo, outs=pouts)
+        psec = time_steps(pv, holo, pouts, args.steps)
+        per_view = {"views_per_s": nv / psec, "ms_per_step": psec * 1e3, "batched_speedup": psec / sec}
+        log(f"per-view launch: {psec * 1e6:.1f} us/step, {nv / psec:.0f} views/s")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w, args.cpu_seconds)
+        log(f"cpu oracle: {cpu['value']:.3f} views/s on {cpu['cores']} threads")
+
+    g = w.holo_grid
+    lx, ly = plan.lengths(0)
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "views/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "holograms": len(w.holograms), "views_per_step": nv,
+                   "hologram": [g.ny, g.nx], "views": [[v.grid.ny, v.grid.nx] for v in w.views],
+                   "padded_length": [lx, ly], "phase": "fp64-reduced", "output": "intensity"},
+        "roofline": roofline,
+        "hbm": hbm,
+        "per_view_launch": per_view,
+        "kernels": kern,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -155,6 +155,25 @@ sfd_status sfd_backward(sfd_plan_t plan, void* const* grad_out, void* const* fie
                         const void* holo, const double* z_or_null, void* grad_in,
                         double* grad_z, void* workspace, size_t ws_bytes, hipStream_t stream);
 
+/* Kernel kinds reported by sfd_profile_report. */
+enum {
+  SFD_KERNEL_TABLES = 0,   /* chirp and twiddle tables (Eqs. 2-4) */
+  SFD_KERNEL_SPECTRA = 1,  /* FFT of the chirp kernel h per axis (steps 5-6) */
+  SFD_KERNEL_PASS_X = 2,   /* fused row pass along x (steps 2-4, 7-8 on rows) */
+  SFD_KERNEL_PASS_Y = 3,   /* fused row pass along y, crop and |.|^2 (steps 4, 7-10) */
+  SFD_KERNEL_OTHER = 4,    /* backward-only reductions and gathers */
+  SFD_KERNEL_KINDS = 5
+};
+
+/* Benchmark timing.  While enabled, each kernel the plan launches is
+ * bracketed by two HIP events recorded on the launch stream.  Enabling (or
+ * re-enabling) clears the record.  Host only apart from the event records. */
+sfd_status sfd_profile_enable(sfd_plan_t plan, int32_t enable);
+
+/* Launch count and summed event-measured duration (milliseconds) of one
+ * kernel kind since profiling was enabled.  Waits for the recorded events. */
+sfd_status sfd_profile_report(sfd_plan_t plan, int32_t kind, int64_t* launches, double* total_ms);
+
 /* Release the plan's host resources.  Passing NULL is allowed. */
 sfd_status sfd_destroy(sfd_plan_t plan);
 

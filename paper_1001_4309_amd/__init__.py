@@ -25,7 +25,7 @@ from ._lib import (SFD_IN_C64, SFD_IN_REAL_F32, SFD_OUT_FIELD, SFD_OUT_INTENSITY
                    SFD_PER_VIEW_LAUNCH, SFD_PHASE_FP32, SfdError, SfdGrid, SfdView)
 
 __all__ = ["Plan", "SFDFunction", "sfd_plan", "sfd_workspace_size", "sfd_view_lengths", "sfd_reconstruct",
-           "sfd_backward", "sfd_destroy", "SfdError"]
+           "sfd_backward", "sfd_profile_enable", "sfd_profile_report", "sfd_destroy", "SfdError"]
 
 
 def _grid(g) -> SfdGrid:
@@ -102,6 +102,16 @@ def sfd_backward(plan, grad_out: Sequence[torch.Tensor], field_out: Optional[Seq
                                         _ptr(grad_z), _ptr(workspace),
                                         workspace.numel() * workspace.element_size(),
                                         _stream_handle(holo.device)))
+
+
+def sfd_profile_enable(plan, enable: bool) -> None:
+    _lib.check(_lib.load().sfd_profile_enable(plan, 1 if enable else 0))
+
+
+def sfd_profile_report(plan, kind: int):
+    n, ms = ctypes.c_int64(), ctypes.c_double()
+    _lib.check(_lib.load().sfd_profile_report(plan, int(kind), ctypes.byref(n), ctypes.byref(ms)))
+    return int(n.value), float(ms.value)
 
 
 def sfd_destroy(plan) -> None:
@@ -189,6 +199,14 @@ class Plan:
                      None if field_out is None else [t.contiguous() for t in field_out],
                      holo, z, grad_in, gz, self.workspace)
         return grad_in, gz
+
+    def profile(self, enable: bool = True) -> None:
+        """Start (clearing earlier records) or stop event timing of the plan's kernels."""
+        sfd_profile_enable(self.handle, enable)
+
+    def profile_report(self):
+        """{kind name: (launches, total ms)} since profiling was enabled."""
+        return {name: sfd_profile_report(self.handle, k) for k, name in _lib.KERNEL_KIND_NAMES.items()}
 
     def __del__(self):
         h = getattr(self, "handle", None)

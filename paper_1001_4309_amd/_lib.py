@@ -25,7 +25,14 @@ SFD_PHASE_FP32 = 1 << 4
 SFD_PER_VIEW_LAUNCH = 1 << 5
 
 EXPORTED = ["sfd_plan", "sfd_workspace_size", "sfd_view_lengths", "sfd_reconstruct",
-            "sfd_backward", "sfd_destroy", "sfd_last_error"]
+            "sfd_backward", "sfd_profile_enable", "sfd_profile_report", "sfd_destroy", "sfd_last_error"]
+
+SFD_KERNEL_TABLES = 0
+SFD_KERNEL_SPECTRA = 1
+SFD_KERNEL_PASS_X = 2
+SFD_KERNEL_PASS_Y = 3
+SFD_KERNEL_OTHER = 4
+KERNEL_KIND_NAMES = {0: "tables", 1: "spectra", 2: "pass_x", 3: "pass_y", 4: "other"}
 
 
 class SfdGrid(ctypes.Structure):
@@ -68,11 +75,14 @@ def load() -> ctypes.CDLL:
                                     ctypes.c_size_t, vp]
     lib.sfd_backward.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp, ctypes.POINTER(ctypes.c_double),
                                  vp, vp, vp, ctypes.c_size_t, vp]
+    lib.sfd_profile_enable.argtypes = [vp, ctypes.c_int32]
+    lib.sfd_profile_report.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(ctypes.c_double)]
     lib.sfd_destroy.argtypes = [vp]
     lib.sfd_last_error.argtypes = []
     lib.sfd_last_error.restype = ctypes.c_char_p
     for name in ("sfd_plan", "sfd_workspace_size", "sfd_view_lengths", "sfd_reconstruct", "sfd_backward",
-                 "sfd_destroy"):
+                 "sfd_profile_enable", "sfd_profile_report", "sfd_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib

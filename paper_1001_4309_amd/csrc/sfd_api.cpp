@@ -117,13 +117,65 @@ struct sfd_plan_s {
   std::vector<unsigned char> last_desc;
   void* last_ws = nullptr;
 
+  // Benchmark timing (sfd_profile_enable).
+  bool profiling = false;
+  struct Rec {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> event_pool;
+
   ~sfd_plan_s() {
+    for (auto& r : recs) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    for (auto e : event_pool) (void)hipEventDestroy(e);
     if (upload_event) (void)hipEventDestroy(upload_event);
     if (pinned) (void)hipHostFree(pinned);
   }
 };
 
 namespace {
+
+hipError_t take_event(sfd_plan_s* P, hipEvent_t* e) {
+  if (!P->event_pool.empty()) {
+    *e = P->event_pool.back();
+    P->event_pool.pop_back();
+    return hipSuccess;
+  }
+  return hipEventCreate(e);
+}
+
+// Brackets one kernel launch with events when profiling is on.
+struct KernelTimer {
+  sfd_plan_s* P;
+  int kind;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t begin() {
+    if (!P->profiling) return hipSuccess;
+    hipError_t e = take_event(P, &a);
+    if (e == hipSuccess) e = take_event(P, &b);
+    if (e == hipSuccess) e = hipEventRecord(a, s);
+    return e;
+  }
+  hipError_t end() {
+    if (!P->profiling || !a) return hipSuccess;
+    hipError_t e = hipEventRecord(b, s);
+    if (e == hipSuccess) P->recs.push_back({kind, a, b});
+    return e;
+  }
+};
+
+#define SFD_TIMED(plan, kind, stream, launch)                 \
+  do {                                                        \
+    KernelTimer kt_{(plan), (kind), (stream)};                \
+    SFD_HIP_TRY(kt_.begin());                                 \
+    SFD_HIP_TRY(launch);                                      \
+    SFD_HIP_TRY(kt_.end());                                   \
+  } while (0)
 
 // Host images of the device descriptors for one forward call, in the order
 // they are laid out in the workspace descriptor area.
@@ -311,7 +363,7 @@ sfd_status upload(sfd_plan_s* P, const std::vector<unsigned char>& img, char* ws
 
 // Launch the passes of row jobs [first, first + count) grouped by L.
 sfd_status launch_rows(const CallDescs& D, const sfd::RowJob* d_rows, int first, int count,
-                       const sfd_plan_s* P, char* ws, hipStream_t stream) {
+                       sfd_plan_s* P, char* ws, hipStream_t stream, int kind) {
   int i = first;
   const int end = first + count;
   while (i < end) {
@@ -330,7 +382,7 @@ sfd_status launch_rows(const CallDescs& D, const sfd::RowJob* d_rows, int first,
     a.tile_prefix[j - i] = acc;
     a.total_tiles = acc;
     const float2* tw = reinterpret_cast<const float2*>(ws + P->tw_off.at(L));
-    SFD_HIP_TRY(sfd::launch_pass(L, a, tw, stream));
+    SFD_TIMED(P, kind, stream, sfd::launch_pass(L, a, tw, stream));
     i = j;
   }
   return SFD_OK;
@@ -492,34 +544,40 @@ sfd_status sfd_reconstruct(sfd_plan_t plan, const void* holo, const double* z_or
   if (plan->flags & SFD_PER_VIEW_LAUNCH) {
     // Baseline: every stage launched for one view at a time (axis jobs stay
     // in view order: 2v = x, 2v + 1 = y).
-    SFD_HIP_TRY(sfd::launch_tables(d_axis, 0, 0, d_tw, (int)D.tw.size(), D.max_L, stream));
+    SFD_TIMED(plan, SFD_KERNEL_TABLES, stream,
+              sfd::launch_tables(d_axis, 0, 0, d_tw, (int)D.tw.size(), D.max_L, stream));
     for (int v = 0; v < V; ++v) {
       const sfd::AxisJob* a = d_axis + 2 * v;
       const int mx = std::max(D.axis[2 * v].n0 + D.axis[2 * v].n1 + D.axis[2 * v].L,
                               D.axis[2 * v + 1].n0 + D.axis[2 * v + 1].n1 + D.axis[2 * v + 1].L);
-      SFD_HIP_TRY(sfd::launch_tables(a, 2, mx, d_tw, 0, 0, stream));
+      SFD_TIMED(plan, SFD_KERNEL_TABLES, stream, sfd::launch_tables(a, 2, mx, d_tw, 0, 0, stream));
       for (int k = 0; k < 2; ++k) {
         const int L = D.axis_L[2 * v + k];
-        SFD_HIP_TRY(sfd::launch_spectra(L, d_axis, 2 * v + k, 1,
-                                        reinterpret_cast<const float2*>(ws + plan->tw_off.at(L)), stream));
+        SFD_TIMED(plan, SFD_KERNEL_SPECTRA, stream,
+                  sfd::launch_spectra(L, d_axis, 2 * v + k, 1,
+                                      reinterpret_cast<const float2*>(ws + plan->tw_off.at(L)), stream));
       }
-      if ((st = launch_rows(D, d_rows, v, 1, plan, ws, stream)) != SFD_OK) return st;
-      if ((st = launch_rows(D, d_rows, D.n_pass_x + v, 1, plan, ws, stream)) != SFD_OK) return st;
+      if ((st = launch_rows(D, d_rows, v, 1, plan, ws, stream, SFD_KERNEL_PASS_X)) != SFD_OK) return st;
+      if ((st = launch_rows(D, d_rows, D.n_pass_x + v, 1, plan, ws, stream, SFD_KERNEL_PASS_Y)) != SFD_OK)
+        return st;
     }
     return SFD_OK;
   }
-  SFD_HIP_TRY(sfd::launch_tables(d_axis, (int)D.axis.size(), D.max_len, d_tw, (int)D.tw.size(), D.max_L, stream));
+  SFD_TIMED(plan, SFD_KERNEL_TABLES, stream,
+            sfd::launch_tables(d_axis, (int)D.axis.size(), D.max_len, d_tw, (int)D.tw.size(), D.max_L, stream));
   // Kernel spectra, grouped by L (axis jobs are sorted by L).
   for (size_t i = 0; i < D.axis.size();) {
     size_t j = i;
     while (j < D.axis.size() && D.axis_L[j] == D.axis_L[i]) ++j;
     const int L = D.axis_L[i];
-    SFD_HIP_TRY(sfd::launch_spectra(L, d_axis, (int)i, (int)(j - i),
-                                    reinterpret_cast<const float2*>(ws + plan->tw_off.at(L)), stream));
+    SFD_TIMED(plan, SFD_KERNEL_SPECTRA, stream,
+              sfd::launch_spectra(L, d_axis, (int)i, (int)(j - i),
+                                  reinterpret_cast<const float2*>(ws + plan->tw_off.at(L)), stream));
     i = j;
   }
-  if ((st = launch_rows(D, d_rows, 0, D.n_pass_x, plan, ws, stream)) != SFD_OK) return st;
-  if ((st = launch_rows(D, d_rows, D.n_pass_x, (int)D.rows.size() - D.n_pass_x, plan, ws, stream)) != SFD_OK)
+  if ((st = launch_rows(D, d_rows, 0, D.n_pass_x, plan, ws, stream, SFD_KERNEL_PASS_X)) != SFD_OK) return st;
+  if ((st = launch_rows(D, d_rows, D.n_pass_x, (int)D.rows.size() - D.n_pass_x, plan, ws, stream,
+                        SFD_KERNEL_PASS_Y)) != SFD_OK)
     return st;
   return SFD_OK;
 }
@@ -548,6 +606,38 @@ sfd_status sfd_backward(sfd_plan_t plan, void* const* grad_out, void* const* fie
   if ((st = check_z(plan, z_or_null)) != SFD_OK) return st;
   (void)stream;
   return fail(SFD_ERR_UNSUPPORTED, "sfd_backward is not available in this build");
+}
+
+sfd_status sfd_profile_enable(sfd_plan_t plan, int32_t enable) {
+  g_err.clear();
+  if (!plan) return fail(SFD_ERR_INVALID_ARG, "plan is NULL");
+  for (auto& r : plan->recs) {
+    SFD_HIP_TRY(hipEventSynchronize(r.b));
+    plan->event_pool.push_back(r.a);
+    plan->event_pool.push_back(r.b);
+  }
+  plan->recs.clear();
+  plan->profiling = enable != 0;
+  return SFD_OK;
+}
+
+sfd_status sfd_profile_report(sfd_plan_t plan, int32_t kind, int64_t* launches, double* total_ms) {
+  g_err.clear();
+  if (!plan || !launches || !total_ms) return fail(SFD_ERR_INVALID_ARG, "NULL argument");
+  if (kind < 0 || kind >= SFD_KERNEL_KINDS) return fail(SFD_ERR_INVALID_ARG, "unknown kernel kind");
+  int64_t n = 0;
+  double ms = 0.0;
+  for (auto& r : plan->recs) {
+    if (r.kind != kind) continue;
+    SFD_HIP_TRY(hipEventSynchronize(r.b));
+    float t = 0.f;
+    SFD_HIP_TRY(hipEventElapsedTime(&t, r.a, r.b));
+    ms += t;
+    ++n;
+  }
+  *launches = n;
+  *total_ms = ms;
+  return SFD_OK;
 }
 
 sfd_status sfd_destroy(sfd_plan_t plan) {
