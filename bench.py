@@ -42,19 +42,22 @@ def row_flops(L: int) -> float:
 
 
 def pass_costs(w, plan):
-    """Per-launch algorithmic bytes and flops of the x and y passes of one batch."""
+    """Per-batch algorithmic bytes and flops of the two passes.
+
+    pass_y (column pass): read the hologram, write the N1y x N0x intermediate,
+    one length-Ly transform per hologram column.  pass_x (row pass): read the
+    intermediate, write the N1y x N1x image, one length-Lx transform per row.
+    """
     g = w.holo_grid
     in_elem = 8 if w.holograms.dtype.kind == "c" else 4
     cost = {"pass_x": [0.0, 0.0], "pass_y": [0.0, 0.0]}
     for v, view in enumerate(w.views):
         lx, ly = plan.lengths(v)
         n1x, n1y = view.grid.nx, view.grid.ny
-        # x pass: read the hologram rows, write the N1x x N0y intermediate.
-        cost["pass_x"][0] += g.nx * g.ny * in_elem + n1x * g.ny * 8
-        cost["pass_x"][1] += g.ny * row_flops(lx)
-        # y pass: read the intermediate, write the N1y x N1x intensity.
-        cost["pass_y"][0] += n1x * g.ny * 8 + n1x * n1y * 4
-        cost["pass_y"][1] += n1x * row_flops(ly)
+        cost["pass_y"][0] += g.nx * g.ny * in_elem + n1y * g.nx * 8
+        cost["pass_y"][1] += g.nx * row_flops(ly)
+        cost["pass_x"][0] += n1y * g.nx * 8 + n1x * n1y * 4
+        cost["pass_x"][1] += n1y * row_flops(lx)
     return cost
 
 
@@ -102,6 +105,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-view", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="first run one plain device-to-device copy of this many MiB (calibrates traffic counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -119,6 +124,15 @@ def main():
     import workloads
 
     dev = torch.device("cuda:0")
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.calib_copy_mib} MiB read + {args.calib_copy_mib} MiB written")
+        del a, b
     w = workloads.CONFIGS[args.config]()
     holo = torch.from_numpy(np.ascontiguousarray(w.holograms)).to(dev)
     plan = sfd.Plan(w.wavelength, w.holo_grid, len(w.holograms), w.views, device=dev)

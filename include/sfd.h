@@ -159,8 +159,8 @@ sfd_status sfd_backward(sfd_plan_t plan, void* const* grad_out, void* const* fie
 enum {
   SFD_KERNEL_TABLES = 0,   /* chirp and twiddle tables (Eqs. 2-4) */
   SFD_KERNEL_SPECTRA = 1,  /* FFT of the chirp kernel h per axis (steps 5-6) */
-  SFD_KERNEL_PASS_X = 2,   /* fused row pass along x (steps 2-4, 7-8 on rows) */
-  SFD_KERNEL_PASS_Y = 3,   /* fused row pass along y, crop and |.|^2 (steps 4, 7-10) */
+  SFD_KERNEL_PASS_X = 2,   /* fused x transforms of the rows, crop, post-chirp or |.|^2 (steps 2-4, 7-10) */
+  SFD_KERNEL_PASS_Y = 3,   /* fused y transforms of the hologram columns (steps 2-4, 7-9) */
   SFD_KERNEL_OTHER = 4,    /* backward-only reductions and gathers */
   SFD_KERNEL_KINDS = 5
 };

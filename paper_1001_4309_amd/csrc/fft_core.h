@@ -1,14 +1,17 @@
-// Register/LDS Stockham FFT for one row per group of TPR threads (gfx950).
+// Register/LDS Stockham FFT for rows held by TPR threads (gfx950).
 //
 // Layout: a length-L row is held by TPR threads, R = L / TPR values each;
 // thread t holds element t + TPR * i in register slot i.  Every stage of the
 // Stockham autosort (decimation in time) formulation reads its butterfly
 // inputs x[j + k L/r] from exactly these slots, so the first stage runs
-// straight from the values loaded from HBM, the last stage leaves the output
-// in natural order in the same slots, and an inverse transform can start
-// from a forward transform's output with no exchange in between.  Between
-// stages the values go through LDS once (write in the stage's output order,
-// read back as t + TPR * i).
+// straight from the values loaded from memory, the last stage leaves the
+// output in natural order in the same slots, and an inverse transform can
+// start from a forward transform's output with no exchange in between.
+// Between stages the values go through LDS once (written in the stage's
+// output order, read back as t + TPR * i).
+//
+// When TPR <= 64 a row lives inside one wavefront, so an exchange needs only
+// wave-level ordering of the LDS accesses, no workgroup barrier.
 //
 // Published formulation restated here: Stockham autosort FFT as in
 // C. Van Loan, "Computational Frameworks for the Fast Fourier Transform"
@@ -61,7 +64,6 @@ __device__ __forceinline__ float2 mul_w(float2 a) {
   } else if constexpr (k32 == 16) {
     return make_float2(-a.x, -a.y);
   } else if constexpr (k32 == 8 || k32 == 24) {
-    // multiply by i * s with s = +-1
     if constexpr (s > 0) return make_float2(-a.y, a.x);
     else return make_float2(a.y, -a.x);
   } else if constexpr (k32 % 8 == 4) {
@@ -115,20 +117,174 @@ __device__ __forceinline__ void dft(float2 (&a)[N]) {
   }
 }
 
-// LDS row padding: one spare slot after every 16 elements.
-__host__ __device__ constexpr int lds_pad(int p) { return p + (p >> 4); }
-__host__ __device__ constexpr int lds_row_len(int L) { return L + L / 16; }
+// ---------------------------------------------------------------------------
+// Plans and twiddle tables.
+
+template <int... Rs>
+struct Radices {
+  static constexpr int count = sizeof...(Rs);
+  static constexpr int product = (Rs * ...);
+};
+
+// A transform shape: length L held by TPR threads (R = L / TPR values each)
+// and the radix order of its stages.  TPR <= 64 keeps a row inside one
+// wavefront.
+template <int L_, int TPR_, typename Rad_>
+struct FftShape {
+  static constexpr int L = L_;
+  static constexpr int TPR = TPR_;
+  static constexpr int R = L_ / TPR_;
+  using Rad = Rad_;
+  static_assert(Rad_::product == L_, "radices must multiply to L");
+};
+
+// Shapes of the row/column passes (one row per wavefront up to L = 2048).
+template <int L>
+struct PassPlan;
+template <> struct PassPlan<64> : FftShape<64, 4, Radices<16, 4>> {};
+template <> struct PassPlan<128> : FftShape<128, 8, Radices<16, 8>> {};
+template <> struct PassPlan<256> : FftShape<256, 16, Radices<16, 16>> {};
+template <> struct PassPlan<512> : FftShape<512, 32, Radices<16, 8, 4>> {};
+template <> struct PassPlan<1024> : FftShape<1024, 64, Radices<16, 8, 8>> {};
+template <> struct PassPlan<2048> : FftShape<2048, 64, Radices<32, 8, 8>> {};
+template <> struct PassPlan<4096> : FftShape<4096, 128, Radices<32, 16, 8>> {};
+template <> struct PassPlan<8192> : FftShape<8192, 256, Radices<32, 16, 16>> {};
+
+// Shapes of the single kernel-spectrum transforms: spread over a whole
+// 256-thread workgroup so that one transform finishes quickly.
+template <int L>
+struct SpecPlan;
+template <> struct SpecPlan<64> : FftShape<64, 8, Radices<8, 8>> {};
+template <> struct SpecPlan<128> : FftShape<128, 16, Radices<8, 8, 2>> {};
+template <> struct SpecPlan<256> : FftShape<256, 32, Radices<8, 8, 4>> {};
+template <> struct SpecPlan<512> : FftShape<512, 64, Radices<8, 8, 8>> {};
+template <> struct SpecPlan<1024> : FftShape<1024, 128, Radices<8, 8, 8, 2>> {};
+template <> struct SpecPlan<2048> : FftShape<2048, 256, Radices<8, 8, 8, 4>> {};
+template <> struct SpecPlan<4096> : FftShape<4096, 256, Radices<16, 16, 16>> {};
+template <> struct SpecPlan<8192> : FftShape<8192, 256, Radices<32, 16, 16>> {};
+
+// Twiddle table of a shape: for every stage after the first (Ns > 1), the
+// entries exp(-2 pi i k jm / (Ns r)) stored as [k - 1][jm], k in [1, r),
+// jm in [0, Ns), so that consecutive butterflies read consecutive entries.
+template <typename Rad>
+struct TwInfo;
+template <int... Rs>
+struct TwInfo<Radices<Rs...>> {
+  static constexpr int S = sizeof...(Rs);
+  static constexpr int r[S] = {Rs...};
+  static constexpr int ns(int s) {
+    int n = 1;
+    for (int i = 0; i < s; ++i) n *= r[i];
+    return n;
+  }
+  static constexpr int off(int s) {
+    int o = 0;
+    for (int i = 1; i < s; ++i) o += (r[i] - 1) * ns(i);
+    return o;
+  }
+  static constexpr int total = off(S);
+};
+
+template <class P>
+constexpr int twiddle_entries() {
+  return TwInfo<typename P::Rad>::total;
+}
+
+// Global-memory access through address space 1, so that the compiler emits
+// global (not flat) instructions with a scalar base and 32-bit offsets.
+// (The host compilation pass only parses these; it never runs them.)
+template <typename T>
+__device__ __forceinline__ T gld(const T* p, unsigned i) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return ((__attribute__((address_space(1))) const T*)p)[i];
+#else
+  return p[i];
+#endif
+}
+template <typename T>
+__device__ __forceinline__ void gst(T* p, unsigned i, T v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  ((__attribute__((address_space(1))) T*)p)[i] = v;
+#else
+  p[i] = v;
+#endif
+}
+
+// Scheduling fence: the compiler may not move instructions across it.  Used
+// to bound how far loads are hoisted, which otherwise inflates register use
+// and costs occupancy.
+__device__ __forceinline__ void sched_fence() { __builtin_amdgcn_sched_barrier(0); }
+
+// ---------------------------------------------------------------------------
+// Exchanges.
+
+template <bool WAVE>
+__device__ __forceinline__ void lds_sync() {
+  if constexpr (WAVE) {
+    // LDS accesses of one wavefront are performed in order; this keeps the
+    // compiler from moving them across the exchange.
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+  // Stages are separate scheduling regions: no load of a later stage is
+  // hoisted across the exchange (that would hold its registers meanwhile).
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// LDS row padding: one spare 4-byte slot after every 32 (the LDS has 32
+// banks and serves half a wavefront per cycle; with this padding the stride-r
+// writes of a radix-32 first stage and the unit-stride reads both hit 32
+// distinct banks).  Linear, so unrolled accesses keep immediate offsets.
+__host__ __device__ constexpr int lds_pad(int p) { return p + (p >> 5); }
+__host__ __device__ constexpr int lds_row_len(int L) { return L + L / 32; }
+
+// Bytes of LDS one row needs for its exchanges.
+template <int L, bool SPLIT>
+constexpr int row_lds_bytes() {
+  return lds_row_len(L) * (SPLIT ? 4 : 8);
+}
+
+// Padded LDS index of stage output k of a butterfly, split as a runtime base
+// (per butterfly) plus a compile-time offset.  With power-of-two radices that
+// divide 32 the split is exact: pad(A + jm + k Ns) = wbase + woff(k) with
+// A = (j - jm) r (see the derivation checked in the tests of this layout).
+template <int r, int Ns>
+__device__ __forceinline__ int lds_wbase(int j) {
+  const int jm = j & (Ns - 1);
+  const int A = (j - jm) * r;
+  if constexpr (Ns % 32 == 0) return A + jm + ((A + jm) >> 5);
+  else return A + (A >> 5) + jm;
+}
+template <int r, int Ns>
+__device__ __forceinline__ constexpr int lds_woff(int k) {
+  return (Ns % 32 == 0 || (Ns * r) % 32 == 0) ? k * Ns + ((k * Ns) >> 5) : k * Ns;
+}
+// Padded LDS index of element t + TPR i (exact when TPR is a multiple of 32;
+// otherwise computed directly).
+template <int TPR>
+__device__ __forceinline__ int lds_ridx(int t, int i) {
+  if constexpr (TPR % 32 == 0) return t + (t >> 5) + TPR * i + ((TPR * i) >> 5);
+  else return lds_pad(t + TPR * i);
+}
 
 // One Stockham stage.  v[i] holds element t + TPR * i of the stage input.
-// If LAST, the stage output replaces v in natural order; otherwise it goes
-// through the row's LDS buffer and v is reloaded in the same t + TPR * i
-// layout.  ``tw`` is exp(-2 pi i e / L), e in [0, L).
-template <int L, int TPR, int r, int Ns, bool INV, bool LAST>
-__device__ __forceinline__ void fft_stage(float2 (&v)[L / TPR], float2* __restrict__ buf, int t,
+// If LAST, the output replaces v in natural order; otherwise it goes through
+// the row's LDS buffer (complex, or real and imaginary parts in turn when
+// SPLIT) and v is reloaded in the t + TPR * i layout.  ``tw`` points at this
+// stage's part of the twiddle table.
+template <int L, int TPR, int r, int Ns, bool INV, bool LAST, bool SPLIT, bool TWC = false>
+__device__ __forceinline__ void fft_stage(float2 (&v)[L / TPR], void* __restrict__ buf, int t,
                                           const float2* __restrict__ tw) {
   constexpr int R = L / TPR;
   constexpr int nb = R / r;
+  constexpr bool WAVE = TPR <= 64;
   static_assert(R % r == 0, "radix must divide the values per thread");
+  static_assert(r <= 32 && (32 % r) == 0, "radices are powers of two up to 32");
+  float2* cbuf = static_cast<float2*>(buf);
+  float* fbuf = static_cast<float*>(buf);
 #pragma unroll
   for (int q = 0; q < nb; ++q) {
     const int j = t + TPR * q;
@@ -137,68 +293,117 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[L / TPR], float2* __restri
     for (int k = 0; k < r; ++k) b[k] = v[q + k * nb];
     if constexpr (Ns > 1) {
       const int jm = j & (Ns - 1);
-      constexpr int step = L / (Ns * r);
 #pragma unroll
       for (int k = 1; k < r; ++k) {
-        const float2 w = tw[k * jm * step];
+        float2 w;
+        if constexpr (TWC) {
+          // Computed twiddle: the argument k jm / (Ns r) is exact in FP32.
+          sincospif(-2.0f * (float)(k * jm) / (float)(Ns * r), &w.y, &w.x);
+        } else {
+          w = gld(tw, (unsigned)((k - 1) * Ns + jm));
+        }
         b[k] = INV ? cmulc(b[k], w) : cmul(b[k], w);
       }
     }
     dft<r, INV>(b);
-    if constexpr (LAST) {
+    if constexpr (nb > 1) sched_fence();
+    if constexpr (LAST || SPLIT) {
 #pragma unroll
       for (int k = 0; k < r; ++k) v[q + k * nb] = b[k];
     } else {
-      const int jm = j & (Ns - 1);
-      const int base = (j - jm) * r + jm;
+      const int wb = lds_wbase<r, Ns>(j);
 #pragma unroll
-      for (int k = 0; k < r; ++k) buf[lds_pad(base + k * Ns)] = b[k];
+      for (int k = 0; k < r; ++k) cbuf[wb + lds_woff<r, Ns>(k)] = b[k];
     }
   }
   if constexpr (!LAST) {
-    __syncthreads();
+    if constexpr (!SPLIT) {
+      lds_sync<WAVE>();
 #pragma unroll
-    for (int i = 0; i < R; ++i) v[i] = buf[lds_pad(t + TPR * i)];
-    __syncthreads();
+      for (int i = 0; i < R; ++i) v[i] = cbuf[lds_ridx<TPR>(t, i)];
+      lds_sync<WAVE>();
+    } else {
+      // Real parts, then imaginary parts, through a float buffer of L slots.
+#pragma unroll
+      for (int q = 0; q < nb; ++q) {
+        const int wb = lds_wbase<r, Ns>(t + TPR * q);
+#pragma unroll
+        for (int k = 0; k < r; ++k) fbuf[wb + lds_woff<r, Ns>(k)] = v[q + k * nb].x;
+      }
+      lds_sync<WAVE>();
+      // In place: every old real part is already in LDS.
+#pragma unroll
+      for (int i = 0; i < R; ++i) v[i].x = fbuf[lds_ridx<TPR>(t, i)];
+      lds_sync<WAVE>();
+#pragma unroll
+      for (int q = 0; q < nb; ++q) {
+        const int wb = lds_wbase<r, Ns>(t + TPR * q);
+#pragma unroll
+        for (int k = 0; k < r; ++k) fbuf[wb + lds_woff<r, Ns>(k)] = v[q + k * nb].y;
+      }
+      lds_sync<WAVE>();
+#pragma unroll
+      for (int i = 0; i < R; ++i) v[i].y = fbuf[lds_ridx<TPR>(t, i)];
+      lds_sync<WAVE>();
+    }
   }
 }
 
-template <int L, int TPR, bool INV, int Ns, int r, int... rest>
-__device__ __forceinline__ void fft_stages(float2 (&v)[L / TPR], float2* __restrict__ buf, int t,
-                                           const float2* __restrict__ tw) {
+template <int L, int TPR, bool INV, bool SPLIT, bool TWC, int Ns, int OFF, int r, int... rest>
+__device__ __forceinline__ void fft_stages(float2 (&v)[L / TPR], void* buf, int t, const float2* tw) {
   constexpr bool last = sizeof...(rest) == 0;
-  fft_stage<L, TPR, r, Ns, INV, last>(v, buf, t, tw);
-  if constexpr (!last) fft_stages<L, TPR, INV, Ns * r, rest...>(v, buf, t, tw);
+  fft_stage<L, TPR, r, Ns, INV, last, SPLIT, TWC>(v, buf, t, tw + OFF);
+  if constexpr (!last) {
+    constexpr int next_off = OFF + (Ns > 1 ? (r - 1) * Ns : 0);
+    fft_stages<L, TPR, INV, SPLIT, TWC, Ns * r, next_off, rest...>(v, buf, t, tw);
+  }
+}
+
+template <class P, bool INV, bool SPLIT, bool TWC, int... Rs>
+__device__ __forceinline__ void fft_run(Radices<Rs...>, float2 (&v)[P::R], void* buf, int t, const float2* tw) {
+  fft_stages<P::L, P::TPR, INV, SPLIT, TWC, 1, 0, Rs...>(v, buf, t, tw);
+}
+
+// Forward (INV = false) or unnormalised inverse (INV = true) FFT of one row
+// of shape P.  ``buf`` is the row's LDS exchange buffer
+// (row_lds_bytes<P::L, SPLIT>() bytes).  TWC: twiddles computed in the stage
+// instead of read from ``tw`` (the table of shape P).
+template <class P, bool INV, bool SPLIT, bool TWC = false>
+__device__ __forceinline__ void fft_row(float2 (&v)[P::R], void* buf, int t, const float2* tw) {
+  fft_run<P, INV, SPLIT, TWC>(typename P::Rad{}, v, buf, t, tw);
+}
+
+// Twiddle table entry e of a shape's table (layout of TwInfo), evaluated in FP64
+// and rounded once.  Returns false past the end of the table.
+template <int Ns, int OFF, int r, int... rest>
+__device__ __forceinline__ bool twiddle_find(int e, float2* out) {
+  if constexpr (Ns > 1) {
+    constexpr int cnt = (r - 1) * Ns;
+    if (e >= OFF && e < OFF + cnt) {
+      const int rel = e - OFF;
+      const int k = rel / Ns + 1;
+      const int jm = rel - (k - 1) * Ns;
+      double sn, cs;
+      sincospi(-2.0 * (double)(k * jm) / (double)(Ns * r), &sn, &cs);
+      *out = make_float2((float)cs, (float)sn);
+      return true;
+    }
+  }
+  if constexpr (sizeof...(rest) > 0) {
+    return twiddle_find<Ns * r, OFF + (Ns > 1 ? (r - 1) * Ns : 0), rest...>(e, out);
+  } else {
+    return false;
+  }
 }
 
 template <int... Rs>
-struct Radices {
-  static constexpr int product = (Rs * ...);
-};
-
-// Transform plan per length: threads per row, values per thread, radix order.
-template <int L>
-struct FftPlan;
-template <> struct FftPlan<64> { static constexpr int TPR = 4; using Rad = Radices<16, 4>; };
-template <> struct FftPlan<128> { static constexpr int TPR = 8; using Rad = Radices<16, 8>; };
-template <> struct FftPlan<256> { static constexpr int TPR = 16; using Rad = Radices<16, 16>; };
-template <> struct FftPlan<512> { static constexpr int TPR = 32; using Rad = Radices<16, 8, 4>; };
-template <> struct FftPlan<1024> { static constexpr int TPR = 64; using Rad = Radices<16, 8, 8>; };
-template <> struct FftPlan<2048> { static constexpr int TPR = 128; using Rad = Radices<16, 16, 8>; };
-template <> struct FftPlan<4096> { static constexpr int TPR = 256; using Rad = Radices<16, 16, 16>; };
-template <> struct FftPlan<8192> { static constexpr int TPR = 256; using Rad = Radices<32, 16, 16>; };
-
-template <int L, bool INV, int... Rs>
-__device__ __forceinline__ void fft_run(Radices<Rs...>, float2 (&v)[L / FftPlan<L>::TPR], float2* buf, int t,
-                                        const float2* tw) {
-  static_assert(Radices<Rs...>::product == L, "radices must multiply to L");
-  fft_stages<L, FftPlan<L>::TPR, INV, 1, Rs...>(v, buf, t, tw);
+__device__ __forceinline__ bool twiddle_entry_r(Radices<Rs...>, int e, float2* out) {
+  return twiddle_find<1, 0, Rs...>(e, out);
 }
 
-// Forward (INV = false) or unnormalised inverse (INV = true) FFT of one row.
-template <int L, bool INV>
-__device__ __forceinline__ void fft_row(float2 (&v)[L / FftPlan<L>::TPR], float2* buf, int t, const float2* tw) {
-  fft_run<L, INV>(typename FftPlan<L>::Rad{}, v, buf, t, tw);
+template <class P>
+__device__ __forceinline__ bool twiddle_entry(int e, float2* out) {
+  return twiddle_entry_r(typename P::Rad{}, e, out);
 }
 
 }  // namespace sfd

@@ -92,8 +92,19 @@ void prefactor(double lam, double z, double px0, double py0, double* re, double*
 
 struct ViewLayout {
   int lx = 0, ly = 0;
+  int tile = -1;  // index of the hologram tile copy the column pass reads
   size_t prex = 0, prey = 0, postx = 0, posty = 0, hx = 0, hy = 0, inter = 0;
 };
+
+// One column-tile copy of a hologram (see sfd::TileJob).
+struct TileLayout {
+  int holo, G, stride;
+  size_t off;
+};
+
+// Row stride of the N1y x N0x intermediate: padded off a power of two so the
+// column pass's strided writes spread over the cache channels.
+int inter_ld(int n0x) { return (n0x + 15) / 16 * 16 + 16; }
 
 }  // namespace
 
@@ -105,8 +116,11 @@ struct sfd_plan_s {
   uint32_t flags = 0;
 
   std::vector<ViewLayout> lay;
+  std::vector<TileLayout> tiles;
   std::vector<int> lengths;           // distinct L values used
-  std::map<int, size_t> tw_off;       // twiddle table per L
+  std::map<int, size_t> tw_off;       // twiddle table of the passes' shape per L
+  std::map<int, size_t> spec_tw_off;  // twiddle table of the kernel-spectrum shape per L
+  void* tw_ready_ws = nullptr;        // workspace whose twiddle tables are current
   size_t desc_off = 0, desc_bytes = 0;
   size_t ws_bytes = 0;
 
@@ -182,17 +196,16 @@ struct KernelTimer {
 struct CallDescs {
   std::vector<sfd::AxisJob> axis;      // sorted by L
   std::vector<sfd::TwiddleJob> tw;
-  std::vector<sfd::RowJob> rows;       // pass-x jobs, then pass-y jobs
+  std::vector<sfd::TileJob> tiles;
+  std::vector<sfd::RowJob> rows;       // column-pass jobs, then row-pass jobs
   std::vector<int> axis_L;             // L of each axis job
   std::vector<int> row_L;              // L of each row job
   int n_pass_x = 0;
-  int max_len = 0;
-  int max_L = 0;
 };
 
-size_t desc_capacity(int n_views, int n_lengths) {
-  return align_up(sizeof(sfd::AxisJob) * 2 * n_views) + align_up(sizeof(sfd::TwiddleJob) * n_lengths) +
-         align_up(sizeof(sfd::RowJob) * 2 * n_views);
+size_t desc_capacity(int n_views, int n_lengths, int n_tiles) {
+  return align_up(sizeof(sfd::AxisJob) * 2 * n_views) + align_up(sizeof(sfd::TwiddleJob) * 2 * n_lengths) +
+         align_up(sizeof(sfd::TileJob) * n_tiles) + align_up(sizeof(sfd::RowJob) * 2 * n_views);
 }
 
 sfd_status build_descs(sfd_plan_s* P, const void* holo, const double* z, void* const* out, char* ws,
@@ -215,6 +228,8 @@ sfd_status build_descs(sfd_plan_s* P, const void* holo, const double* z, void* c
     const sfd_view& w = P->views[v];
     const ViewLayout& L = P->lay[v];
     const double zz = z ? z[v] : w.z;
+    double c_re, c_im;
+    prefactor(P->lam, zz, h.px, h.py, &c_re, &c_im);
     AxisScalars sx = axis_scalars(h.nx, h.px, h.ox, w.out.nx, w.out.px, w.out.ox, P->lam, zz);
     AxisScalars sy = axis_scalars(h.ny, h.py, h.oy, w.out.ny, w.out.py, w.out.oy, P->lam, zz);
     for (int a = 0; a < 2; ++a) {
@@ -228,6 +243,8 @@ sfd_status build_descs(sfd_plan_s* P, const void* holo, const double* z, void* c
       j.S = s.S;
       j.c1 = s.c1;
       j.wscale = 0.0;
+      // The prefactor c(z) rides on the x post-chirp (field output only).
+      j.post_scale = a == 0 ? make_float2((float)c_re, (float)c_im) : make_float2(1.f, 0.f);
       j.pre = reinterpret_cast<float2*>(ws + (a == 0 ? L.prex : L.prey));
       j.post = field ? reinterpret_cast<float2*>(ws + (a == 0 ? L.postx : L.posty)) : nullptr;
       j.H = reinterpret_cast<float2*>(ws + (a == 0 ? L.hx : L.hy));
@@ -242,68 +259,81 @@ sfd_status build_descs(sfd_plan_s* P, const void* holo, const double* z, void* c
     std::stable_sort(ax.begin(), ax.end(), [](const AxisTmp& a, const AxisTmp& b) { return a.L < b.L; });
   D->axis.clear();
   D->axis_L.clear();
-  D->max_len = 0;
-  D->max_L = 0;
   for (auto& a : ax) {
     D->axis.push_back(a.j);
     D->axis_L.push_back(a.L);
-    D->max_len = std::max(D->max_len, a.j.n0 + a.j.n1 + a.j.L);
-    D->max_L = std::max(D->max_L, a.L);
   }
   D->tw.clear();
   for (int L : P->lengths) {
-    sfd::TwiddleJob t;
-    t.tw = reinterpret_cast<float2*>(ws + P->tw_off.at(L));
-    t.L = L;
-    D->tw.push_back(t);
+    for (int spec = 0; spec < 2; ++spec) {
+      sfd::TwiddleJob t{};
+      t.tw = reinterpret_cast<float2*>(ws + (spec ? P->spec_tw_off.at(L) : P->tw_off.at(L)));
+      t.L = L;
+      t.count = sfd::twiddle_len(L, spec != 0);
+      t.spec = spec;
+      D->tw.push_back(t);
+    }
+  }
+  D->tiles.clear();
+  for (const TileLayout& T : P->tiles) {
+    sfd::TileJob j{};
+    j.in = static_cast<const char*>(holo) + (size_t)T.holo * holo_stride;
+    j.out = ws + T.off;
+    j.nx = h.nx;
+    j.ny = h.ny;
+    j.G = T.G;
+    j.tile_stride = T.stride;
+    j.complex_in = in_real ? 0 : 1;
+    D->tiles.push_back(j);
   }
 
-  // Pass x (rows of the hologram) then pass y (rows of the transposed
-  // intermediate), one job per view, stable-sorted by L within each pass.
+  // Column pass (y transforms of the hologram columns) then row pass (x
+  // transforms of the rows of the N1y x N0x intermediate), one job per view,
+  // stable-sorted by L within each pass.
   D->rows.clear();
   D->row_L.clear();
-  double c_re = 1, c_im = 0;
+  const bool inten = (P->flags & SFD_OUT_INTENSITY) != 0;
   std::vector<std::pair<int, sfd::RowJob>> px, py;
   for (int v = 0; v < V; ++v) {
     const sfd_view& w = P->views[v];
     const ViewLayout& L = P->lay[v];
     const double zz = z ? z[v] : w.z;
+    double c_re, c_im;
     prefactor(P->lam, zz, h.px, h.py, &c_re, &c_im);
-    sfd::RowJob jx{};
-    jx.in = static_cast<const char*>(holo) + (size_t)w.holo * holo_stride;
-    jx.out = ws + L.inter;
-    jx.pre = reinterpret_cast<const float2*>(ws + L.prex);
-    jx.H = reinterpret_cast<const float2*>(ws + L.hx);
-    jx.post = field ? reinterpret_cast<const float2*>(ws + L.postx) : nullptr;
-    jx.scale = make_float2(1.f, 0.f);
-    jx.iscale = 1.f;
-    jx.n_rows = h.ny;
-    jx.n_in = h.nx;
-    jx.n_out = w.out.nx;
-    jx.in_ld = h.nx;
-    jx.out_ld = h.ny;
-    jx.mode = (in_real ? sfd::kInReal : 0) | (field ? sfd::kUsePost : 0) | sfd::kOutField;
-    px.push_back({L.lx, jx});
 
-    sfd::RowJob jy{};
-    jy.in = ws + L.inter;
-    const bool inten = (P->flags & SFD_OUT_INTENSITY) != 0;
-    jy.out = field ? out[inten ? V + v : v] : out[v];
-    jy.out2 = (field && inten) ? static_cast<float*>(out[v]) : nullptr;
-    jy.pre = reinterpret_cast<const float2*>(ws + L.prey);
-    jy.H = reinterpret_cast<const float2*>(ws + L.hy);
-    jy.post = field ? reinterpret_cast<const float2*>(ws + L.posty) : nullptr;
-    jy.scale = make_float2((float)c_re, (float)c_im);
-    jy.iscale = (float)(c_re * c_re + c_im * c_im);
-    jy.n_rows = w.out.nx;
-    jy.n_in = h.ny;
-    jy.n_out = w.out.ny;
-    jy.in_ld = h.ny;
-    jy.out_ld = w.out.nx;
-    jy.mode = field ? (sfd::kUsePost | sfd::kUseScale | sfd::kOutField) : sfd::kOutIntensity;
-    if (field && inten) jy.mode |= sfd::kOutIntensity;
-    if (field && inten) jy.iscale = 1.f;
-    py.push_back({L.ly, jy});
+    const TileLayout& T = P->tiles[L.tile];
+    const int ldw = inter_ld(h.nx);
+    sfd::RowJob jc{};
+    jc.in = ws + T.off;
+    jc.out = ws + L.inter;
+    jc.pre = reinterpret_cast<const float2*>(ws + L.prey);
+    jc.H = reinterpret_cast<const float2*>(ws + L.hy);
+    jc.post = field ? reinterpret_cast<const float2*>(ws + L.posty) : nullptr;
+    jc.iscale = 1.f;
+    jc.n_rows = h.nx;
+    jc.n_in = h.ny;
+    jc.n_out = w.out.ny;
+    jc.in_ld = T.stride;  // column-tile stride (elements)
+    jc.out_ld = ldw;
+    jc.mode = (in_real ? sfd::kInReal : 0) | (field ? sfd::kUsePost : 0) | sfd::kOutField;
+    py.push_back({L.ly, jc});
+
+    sfd::RowJob jr{};
+    jr.in = ws + L.inter;
+    jr.out = field ? out[inten ? V + v : v] : out[v];
+    jr.out2 = (field && inten) ? static_cast<float*>(out[v]) : nullptr;
+    jr.pre = reinterpret_cast<const float2*>(ws + L.prex);
+    jr.H = reinterpret_cast<const float2*>(ws + L.hx);
+    jr.post = field ? reinterpret_cast<const float2*>(ws + L.postx) : nullptr;
+    // With the field written, |c|^2 is already inside it (c rides on post).
+    jr.iscale = field ? 1.f : (float)(c_re * c_re + c_im * c_im);
+    jr.n_rows = w.out.ny;
+    jr.n_in = h.nx;
+    jr.n_out = w.out.nx;
+    jr.in_ld = ldw;
+    jr.out_ld = w.out.nx;
+    jr.mode = (field ? (sfd::kUsePost | sfd::kOutField) : 0) | (inten ? sfd::kOutIntensity : 0);
+    px.push_back({L.lx, jr});
   }
   auto by_len = [](const std::pair<int, sfd::RowJob>& a, const std::pair<int, sfd::RowJob>& b) {
     return a.first < b.first;
@@ -312,15 +342,15 @@ sfd_status build_descs(sfd_plan_s* P, const void* holo, const double* z, void* c
     std::stable_sort(px.begin(), px.end(), by_len);
     std::stable_sort(py.begin(), py.end(), by_len);
   }
-  for (auto& p : px) {
-    D->rows.push_back(p.second);
-    D->row_L.push_back(p.first);
-  }
   for (auto& p : py) {
     D->rows.push_back(p.second);
     D->row_L.push_back(p.first);
   }
-  D->n_pass_x = (int)px.size();
+  for (auto& p : px) {
+    D->rows.push_back(p.second);
+    D->row_L.push_back(p.first);
+  }
+  D->n_pass_x = (int)py.size();  // jobs of the first (column) pass
   return SFD_OK;
 }
 
@@ -330,11 +360,13 @@ void pack_descs(const sfd_plan_s* P, const CallDescs& D, std::vector<unsigned ch
   const int V = (int)P->views.size();
   *off_axis = 0;
   *off_tw = align_up(sizeof(sfd::AxisJob) * 2 * V);
-  *off_rows = *off_tw + align_up(sizeof(sfd::TwiddleJob) * P->lengths.size());
+  const size_t off_tiles = *off_tw + align_up(sizeof(sfd::TwiddleJob) * 2 * P->lengths.size());
+  *off_rows = off_tiles + align_up(sizeof(sfd::TileJob) * P->tiles.size());
   const size_t total = *off_rows + sizeof(sfd::RowJob) * D.rows.size();
   img->assign(total, 0);
   std::memcpy(img->data() + *off_axis, D.axis.data(), sizeof(sfd::AxisJob) * D.axis.size());
   std::memcpy(img->data() + *off_tw, D.tw.data(), sizeof(sfd::TwiddleJob) * D.tw.size());
+  std::memcpy(img->data() + off_tiles, D.tiles.data(), sizeof(sfd::TileJob) * D.tiles.size());
   std::memcpy(img->data() + *off_rows, D.rows.data(), sizeof(sfd::RowJob) * D.rows.size());
 }
 
@@ -361,9 +393,66 @@ sfd_status upload(sfd_plan_s* P, const std::vector<unsigned char>& img, char* ws
   return SFD_OK;
 }
 
+// Setup launch(es) for axis jobs [a0, a0 + na), all twiddle tables if
+// ``twiddles``, and tile jobs [t0, t0 + nt).
+sfd_status launch_setup_for(sfd_plan_s* P, const CallDescs& D, char* ws, const sfd::AxisJob* d_axis,
+                            const sfd::TwiddleJob* d_tw, const sfd::TileJob* d_tiles, int a0, int na,
+                            bool twiddles, int t0, int nt, hipStream_t stream) {
+  sfd::SetupArgs A{};
+  A.axis = d_axis;
+  A.tw = d_tw;
+  A.tiles = d_tiles;
+  auto flush = [&]() -> sfd_status {
+    if (A.nroles == 0) return SFD_OK;
+    SFD_TIMED(P, SFD_KERNEL_TABLES, stream, sfd::launch_setup(A, stream));
+    A.nroles = 0;
+    A.total_blocks = 0;
+    return SFD_OK;
+  };
+  auto add = [&](sfd::SetupRole r) -> sfd_status {
+    if (r.nblocks <= 0) return SFD_OK;
+    if (A.nroles == sfd::kMaxSetupRoles) {
+      sfd_status st = flush();
+      if (st != SFD_OK) return st;
+    }
+    r.first_block = A.total_blocks;
+    A.roles[A.nroles++] = r;
+    A.total_blocks += r.nblocks;
+    return SFD_OK;
+  };
+  sfd_status st;
+  // Kernel spectra: runs of equal L.
+  for (int i = a0; i < a0 + na;) {
+    int j = i;
+    while (j < a0 + na && D.axis_L[j] == D.axis_L[i]) ++j;
+    const int L = D.axis_L[i];
+    const int per = sfd::spectra_per_block(L);
+    const float2* stw = reinterpret_cast<const float2*>(ws + P->spec_tw_off.at(L));
+    if ((st = add({sfd::kRoleSpectrum, 0, (j - i + per - 1) / per, L, i, j - i, stw})) != SFD_OK) return st;
+    i = j;
+  }
+  // Pre/post chirp tables.
+  int span = 0;
+  for (int i = a0; i < a0 + na; ++i) span = std::max(span, D.axis[i].n0 + (D.axis[i].post ? D.axis[i].n1 : 0));
+  const int chunks = (span + sfd::kSetupThreads - 1) / sfd::kSetupThreads;
+  if (na > 0 && (st = add({sfd::kRoleTables, 0, na * chunks, chunks, a0, na, nullptr})) != SFD_OK) return st;
+  if (twiddles)
+    for (int k = 0; k < (int)D.tw.size(); ++k)
+      if ((st = add({sfd::kRoleTwiddles, 0, (D.tw[k].count + sfd::kSetupThreads - 1) / sfd::kSetupThreads, k, 0,
+                     0, nullptr})) != SFD_OK)
+        return st;
+  for (int k = t0; k < t0 + nt; ++k) {
+    const int cb = (D.tiles[k].nx + sfd::kTileCols - 1) / sfd::kTileCols;
+    const int rb = (D.tiles[k].ny + sfd::kTileRows - 1) / sfd::kTileRows;
+    if ((st = add({sfd::kRoleTiles, 0, cb * rb, k, cb, 0, nullptr})) != SFD_OK) return st;
+  }
+  return flush();
+}
+
 // Launch the passes of row jobs [first, first + count) grouped by L.
 sfd_status launch_rows(const CallDescs& D, const sfd::RowJob* d_rows, int first, int count,
                        sfd_plan_s* P, char* ws, hipStream_t stream, int kind) {
+  const bool col = kind == SFD_KERNEL_PASS_Y;
   int i = first;
   const int end = first + count;
   while (i < end) {
@@ -373,7 +462,7 @@ sfd_status launch_rows(const CallDescs& D, const sfd::RowJob* d_rows, int first,
     sfd::PassArgs a{};
     a.jobs = d_rows + i;
     a.njobs = j - i;
-    const int G = sfd::rows_per_tile(L);
+    const int G = sfd::rows_per_tile(L, col);
     int acc = 0;
     for (int k = i; k < j; ++k) {
       a.tile_prefix[k - i] = acc;
@@ -382,7 +471,7 @@ sfd_status launch_rows(const CallDescs& D, const sfd::RowJob* d_rows, int first,
     a.tile_prefix[j - i] = acc;
     a.total_tiles = acc;
     const float2* tw = reinterpret_cast<const float2*>(ws + P->tw_off.at(L));
-    SFD_TIMED(P, kind, stream, sfd::launch_pass(L, a, tw, stream));
+    SFD_TIMED(P, kind, stream, sfd::launch_pass(L, col, a, tw, stream));
     i = j;
   }
   return SFD_OK;
@@ -463,15 +552,41 @@ sfd_status sfd_plan(sfd_plan_t* plan, double wavelength, const sfd_grid* holo_gr
   ls.erase(std::unique(ls.begin(), ls.end()), ls.end());
   P->lengths = ls;
 
+  // Column-tile copies: one per (hologram, tile width) the views need.
+  const size_t in_elem = (flags & SFD_IN_REAL_F32) ? sizeof(float) : sizeof(float2);
+  P->lay.resize(n_views);
+  for (int v = 0; v < n_views; ++v) {
+    const int G = sfd::rows_per_tile(choose_length(h.ny, views[v].out.ny), true);
+    int found = -1;
+    for (size_t k = 0; k < P->tiles.size(); ++k)
+      if (P->tiles[k].holo == views[v].holo && P->tiles[k].G == G) found = (int)k;
+    if (found < 0) {
+      TileLayout T;
+      T.holo = views[v].holo;
+      T.G = G;
+      T.stride = (h.ny * G + 63) / 64 * 64 + 64;  // elements, off a power of two
+      T.off = 0;
+      P->tiles.push_back(T);
+      found = (int)P->tiles.size() - 1;
+    }
+    P->lay[v].tile = found;
+  }
+
   size_t off = 0;
   P->desc_off = off;
-  P->desc_bytes = desc_capacity(n_views, (int)ls.size());
+  P->desc_bytes = desc_capacity(n_views, (int)ls.size(), (int)P->tiles.size());
   off += P->desc_bytes;
+  for (TileLayout& T : P->tiles) {
+    const size_t ntiles = (size_t)(h.nx + T.G - 1) / T.G;
+    T.off = off;
+    off += align_up(ntiles * (size_t)T.stride * in_elem);
+  }
   for (int L : ls) {
     P->tw_off[L] = off;
-    off += align_up(sizeof(float2) * L);
+    off += align_up(sizeof(float2) * std::max(1, sfd::twiddle_len(L, false)));
+    P->spec_tw_off[L] = off;
+    off += align_up(sizeof(float2) * std::max(1, sfd::twiddle_len(L, true)));
   }
-  P->lay.resize(n_views);
   for (int v = 0; v < n_views; ++v) {
     ViewLayout& L = P->lay[v];
     const sfd_grid& o = views[v].out;
@@ -490,7 +605,7 @@ sfd_status sfd_plan(sfd_plan_t* plan, double wavelength, const sfd_grid* holo_gr
     }
     L.hx = take(sizeof(float2) * L.lx);
     L.hy = take(sizeof(float2) * L.ly);
-    L.inter = take(sizeof(float2) * (size_t)o.nx * h.ny);
+    L.inter = take(sizeof(float2) * (size_t)o.ny * inter_ld(h.nx));  // N1y x N0x after the y transforms
   }
   P->ws_bytes = off;
   *plan = P;
@@ -540,44 +655,34 @@ sfd_status sfd_reconstruct(sfd_plan_t plan, const void* holo, const double* z_or
   const auto* d_axis = reinterpret_cast<const sfd::AxisJob*>(ws + plan->desc_off + off_axis);
   const auto* d_tw = reinterpret_cast<const sfd::TwiddleJob*>(ws + plan->desc_off + off_tw);
   const auto* d_rows = reinterpret_cast<const sfd::RowJob*>(ws + plan->desc_off + off_rows);
+  const auto* d_tiles = reinterpret_cast<const sfd::TileJob*>(
+      ws + plan->desc_off + off_tw + align_up(sizeof(sfd::TwiddleJob) * 2 * plan->lengths.size()));
 
+  // The twiddle tables depend only on the transform shapes: built once per
+  // workspace (which stays dedicated to the plan).
+  if (plan->tw_ready_ws != ws) {
+    if ((st = launch_setup_for(plan, D, ws, d_axis, d_tw, d_tiles, 0, 0, true, 0, 0, stream)) != SFD_OK) return st;
+    plan->tw_ready_ws = ws;
+  }
   if (plan->flags & SFD_PER_VIEW_LAUNCH) {
     // Baseline: every stage launched for one view at a time (axis jobs stay
     // in view order: 2v = x, 2v + 1 = y).
-    SFD_TIMED(plan, SFD_KERNEL_TABLES, stream,
-              sfd::launch_tables(d_axis, 0, 0, d_tw, (int)D.tw.size(), D.max_L, stream));
     for (int v = 0; v < V; ++v) {
-      const sfd::AxisJob* a = d_axis + 2 * v;
-      const int mx = std::max(D.axis[2 * v].n0 + D.axis[2 * v].n1 + D.axis[2 * v].L,
-                              D.axis[2 * v + 1].n0 + D.axis[2 * v + 1].n1 + D.axis[2 * v + 1].L);
-      SFD_TIMED(plan, SFD_KERNEL_TABLES, stream, sfd::launch_tables(a, 2, mx, d_tw, 0, 0, stream));
-      for (int k = 0; k < 2; ++k) {
-        const int L = D.axis_L[2 * v + k];
-        SFD_TIMED(plan, SFD_KERNEL_SPECTRA, stream,
-                  sfd::launch_spectra(L, d_axis, 2 * v + k, 1,
-                                      reinterpret_cast<const float2*>(ws + plan->tw_off.at(L)), stream));
-      }
-      if ((st = launch_rows(D, d_rows, v, 1, plan, ws, stream, SFD_KERNEL_PASS_X)) != SFD_OK) return st;
-      if ((st = launch_rows(D, d_rows, D.n_pass_x + v, 1, plan, ws, stream, SFD_KERNEL_PASS_Y)) != SFD_OK)
+      if ((st = launch_setup_for(plan, D, ws, d_axis, d_tw, d_tiles, 2 * v, 2, false, plan->lay[v].tile, 1, stream)) !=
+          SFD_OK)
+        return st;
+      if ((st = launch_rows(D, d_rows, v, 1, plan, ws, stream, SFD_KERNEL_PASS_Y)) != SFD_OK) return st;
+      if ((st = launch_rows(D, d_rows, D.n_pass_x + v, 1, plan, ws, stream, SFD_KERNEL_PASS_X)) != SFD_OK)
         return st;
     }
     return SFD_OK;
   }
-  SFD_TIMED(plan, SFD_KERNEL_TABLES, stream,
-            sfd::launch_tables(d_axis, (int)D.axis.size(), D.max_len, d_tw, (int)D.tw.size(), D.max_L, stream));
-  // Kernel spectra, grouped by L (axis jobs are sorted by L).
-  for (size_t i = 0; i < D.axis.size();) {
-    size_t j = i;
-    while (j < D.axis.size() && D.axis_L[j] == D.axis_L[i]) ++j;
-    const int L = D.axis_L[i];
-    SFD_TIMED(plan, SFD_KERNEL_SPECTRA, stream,
-              sfd::launch_spectra(L, d_axis, (int)i, (int)(j - i),
-                                  reinterpret_cast<const float2*>(ws + plan->tw_off.at(L)), stream));
-    i = j;
-  }
-  if ((st = launch_rows(D, d_rows, 0, D.n_pass_x, plan, ws, stream, SFD_KERNEL_PASS_X)) != SFD_OK) return st;
+  if ((st = launch_setup_for(plan, D, ws, d_axis, d_tw, d_tiles, 0, (int)D.axis.size(), false, 0,
+                             (int)D.tiles.size(), stream)) != SFD_OK)
+    return st;
+  if ((st = launch_rows(D, d_rows, 0, D.n_pass_x, plan, ws, stream, SFD_KERNEL_PASS_Y)) != SFD_OK) return st;
   if ((st = launch_rows(D, d_rows, D.n_pass_x, (int)D.rows.size() - D.n_pass_x, plan, ws, stream,
-                        SFD_KERNEL_PASS_Y)) != SFD_OK)
+                        SFD_KERNEL_PASS_X)) != SFD_OK)
     return st;
   return SFD_OK;
 }

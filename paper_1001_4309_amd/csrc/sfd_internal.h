@@ -1,8 +1,8 @@
 // Internal descriptors shared by the host planner and the HIP kernels.
 //
 // One view of the Shifted-Fresnel map (Section 2.1, Eqs. 1-4) separates into
-// an x transform applied to every hologram row and a y transform applied to
-// every column of the result, because every factor of Eqs. (2)-(4) is an
+// a y transform applied to every hologram column and an x transform applied
+// to every row of the result, because every factor of Eqs. (2)-(4) is an
 // x-only term times a y-only term.  Each 1D transform is
 //
 //   out[m1] = post[m1] * sum_{m0} h[m1 - m0] * pre[m0] * in[m0]
@@ -30,6 +30,7 @@ struct AxisJob {
   double S;        // p0 p1 / (lambda z)
   double c1;       // a1 / p1: output-grid offset in output pixels
   double wscale;   // moment weight scale (pre *= x0 * wscale when kMomentX0)
+  float2 post_scale;  // complex factor folded into post (the prefactor c on one axis)
   float2* pre;     // [n0]
   float2* post;    // [n1] or nullptr
   float2* H;       // [L]: h on input, FFT(h)/L after the spectrum kernel
@@ -39,26 +40,26 @@ struct AxisJob {
 
 enum : int32_t { kPhaseFp32 = 1, kMomentX0 = 2 };
 
-// One batched 1D transform over rows (one view, one axis).  Row r of the input
-// is in + r * in_ld (n_in elements, float32 or complex64); output element m of
-// row r goes to out[m * out_ld + r] (a transposed store, so that the next
-// axis again reads contiguous rows).
+// One batched set of 1D transforms (one view, one axis).
+// Row kernel: transform r reads in + r * in_ld (n_in elements) and writes
+// out + r * out_ld (n_out elements).  Column kernel: transform c reads
+// in[n * in_ld + c] and writes out[m * out_ld + c].  n_rows counts the
+// transforms in both cases.
 struct RowJob {
-  const void* in;
+  const void* in;      // float32 (kInReal) or complex64
   void* out;           // complex64, or float32 when only the intensity is written
   float* out2;         // float32 intensity when both outputs are written, else nullptr
   const float2* pre;   // [n_in]
   const float2* H;     // [L]
   const float2* post;  // [n_out] or nullptr
-  float2 scale;        // complex factor on the output (field mode)
   float iscale;        // intensity scale
   int32_t n_rows, n_in, n_out;
   int64_t in_ld, out_ld;
-  int32_t mode;        // kInReal | kOutIntensity | kOutField | kUsePost | kUseScale
+  int32_t mode;        // kInReal | kOutIntensity | kOutField | kUsePost
   int32_t pad_;
 };
 
-enum : int32_t { kInReal = 1, kOutIntensity = 2, kUsePost = 4, kUseScale = 8, kOutField = 16 };
+enum : int32_t { kInReal = 1, kOutIntensity = 2, kUsePost = 4, kOutField = 16 };
 
 constexpr int kMaxJobsPerLaunch = 256;
 
@@ -70,19 +71,64 @@ struct PassArgs {
 };
 
 struct TwiddleJob {
-  float2* tw;  // [L]: exp(-2 pi i e / L)
+  float2* tw;     // stage-major twiddle table of one transform shape (see fft_core.h)
   int32_t L;
+  int32_t count;  // entries
+  int32_t spec;   // 0: the passes' shape of L, 1: the kernel-spectrum shape of L
+  int32_t pad_;
 };
 
-// Host-side launchers (defined in sfd_kernels.hip).
-hipError_t launch_tables(const AxisJob* d_jobs, int njobs, int max_len, const TwiddleJob* d_tw,
-                         int ntw, int max_L, hipStream_t s);
-hipError_t launch_spectra(int L, const AxisJob* d_jobs, int first, int count, const float2* tw,
-                          hipStream_t s);
-hipError_t launch_pass(int L, const PassArgs& args, const float2* tw, hipStream_t s);
+// A hologram rewritten as column tiles for the column pass: tile c holds
+// columns [c G, c G + G) as [n][g] (n < ny, g < G, zero past nx), tiles
+// tile_stride elements apart.  The column pass then reads each workgroup's
+// G columns as one contiguous block.
+struct TileJob {
+  const void* in;  // [ny][nx] float32 or complex64
+  void* out;
+  int32_t nx, ny, G;
+  int32_t tile_stride;  // elements
+  int32_t complex_in;
+  int32_t pad_;
+};
 
-// Rows per workgroup for a transform length (the tile height of a pass).
-int rows_per_tile(int L);
+// One launch builds everything a batch needs before the passes.  Workgroups
+// take roles by index range: kernel spectra (FFT(h)/L, h evaluated in
+// registers), pre/post chirp tables, FFT twiddle tables, hologram column
+// tiles.  The roles are independent of each other.
+enum : int32_t { kRoleSpectrum = 0, kRoleTables = 1, kRoleTwiddles = 2, kRoleTiles = 3 };
+constexpr int kMaxSetupRoles = 32;
+struct SetupRole {
+  int32_t kind;
+  int32_t first_block, nblocks;
+  int32_t a, b, c;  // spectrum: L, first axis job, count; tables: chunks per job, first job, count;
+                    // twiddles: job; tiles: job, column blocks
+  const float2* tw;  // spectrum: twiddle table of the spectrum shape of L
+};
+struct SetupArgs {
+  const AxisJob* axis;
+  const TwiddleJob* tw;
+  const TileJob* tiles;
+  int32_t nroles;
+  int32_t total_blocks;
+  SetupRole roles[kMaxSetupRoles];
+};
+constexpr int kSetupThreads = 256;
+constexpr int kTileRows = 8;     // hologram rows per tile workgroup
+constexpr int kTileCols = 256;   // hologram columns per tile workgroup
+
+// Host-side launchers (defined in sfd_kernels.hip).
+hipError_t launch_setup(const SetupArgs& args, hipStream_t s);
+// Axis jobs one spectrum workgroup handles at a transform length.
+int spectra_per_block(int L);
+
+// col = true: the y transforms (column kernel); false: the x transforms.
+hipError_t launch_pass(int L, bool col, const PassArgs& args, const float2* tw, hipStream_t s);
+
+// Transforms per workgroup (the tile) of a pass at a transform length.
+int rows_per_tile(int L, bool col);
 bool supported_length(int L);
+// Entries of the twiddle table of the passes' (spec = false) or the kernel
+// spectrum's (spec = true) transform shape of length L.
+int twiddle_len(int L, bool spec);
 
 }  // namespace sfd

@@ -1,17 +1,22 @@
 // HIP kernels for batched Shifted-Fresnel reconstruction on gfx950.
 //
+// A view separates into a y transform of every hologram column followed by
+// an x transform of every row of the result (every factor of Eqs. 2-4 is an
+// x-only term times a y-only term).  Each transform is one padded 1D chirp
+// convolution: multiply by the pre-chirp (step 3 of Section 2.2), zero-pad
+// (step 2), FFT (step 4), multiply by the kernel spectrum (step 7), inverse
+// FFT (step 8), crop (step 9), then the post-chirp or |.|^2 (step 10, Eq. 5).
+//
 //  tables_kernel   chirp tables of Eqs. (2)-(4) per view and axis, phases in
 //                  FP64 reduced to [-1, 1] half-turns before sin/cos, plus the
 //                  FFT twiddle tables.
-//  spectrum_kernel FFT_L(h) / L per view and axis (steps 5-6 of Section 2.2,
-//                  done per axis because h of Eq. (4) is separable).
-//  pass_kernel     one padded 1D chirp convolution per row, fused:
-//                  load row, multiply by the pre-chirp (step 3), zero-pad
-//                  (step 2), FFT (step 4), multiply by the kernel spectrum
-//                  (step 7), inverse FFT (step 8), crop (step 9), and either
-//                  the post-chirp or |.|^2 (step 10, Eq. 5); the row's
-//                  outputs are stored transposed so the next axis again
-//                  reads contiguous rows.
+//  spectrum_kernel FFT_L(h) / L per view and axis (steps 5-6, per axis since
+//                  h of Eq. 4 is separable).
+//  col_kernel      the y transforms: G columns per workgroup, loaded and
+//                  stored through LDS staging so that global accesses are
+//                  G elements wide; writes the N1y x N0x intermediate.
+//  row_kernel      the x transforms: one row per TPR threads, contiguous
+//                  loads and stores straight from registers.
 #include <hip/hip_runtime.h>
 
 #include "fft_core.h"
@@ -59,15 +64,18 @@ __device__ __forceinline__ float2 pre_value(const AxisJob& J, int m) {
 }
 
 __device__ __forceinline__ float2 post_value(const AxisJob& J, int m) {
+  float2 v;
   if (J.flags & kPhaseFp32) {
     const float p1 = (float)J.p1, a1 = (float)J.a1, a0 = (float)J.a0, il = (float)J.inv_lz, S = (float)J.S;
     const float fm = (float)m;
     const float x1 = fm * p1 + a1;
-    return cispi_f32(x1 * x1 * il - 2.0f * a0 * x1 * il - S * fm * fm);
+    v = cispi_f32(x1 * x1 * il - 2.0f * a0 * x1 * il - S * fm * fm);
+  } else {
+    const double dm = (double)m;
+    const double x1 = dm * J.p1 + J.a1;
+    v = cispi_f64(x1 * x1 * J.inv_lz - 2.0 * J.a0 * x1 * J.inv_lz - J.S * (double)((int64_t)m * m));
   }
-  const double dm = (double)m;
-  const double x1 = dm * J.p1 + J.a1;
-  return cispi_f64(x1 * x1 * J.inv_lz - 2.0 * J.a0 * x1 * J.inv_lz - J.S * (double)((int64_t)m * m));
+  return cmul(v, J.post_scale);
 }
 
 // h of Eq. (4) at storage index i in [0, L): lag k = i for i < n1, k = i - L
@@ -82,238 +90,506 @@ __device__ __forceinline__ float2 kernel_value(const AxisJob& J, int i) {
   return cispi_f64(J.S * (double)((int64_t)k * k));
 }
 
-// grid: x covers max(n0 + n1 + L) entries per job, y = jobs then twiddle tables.
-__global__ void __launch_bounds__(256) tables_kernel(const AxisJob* __restrict__ jobs, int njobs,
-                                                     const TwiddleJob* __restrict__ tws, int ntw) {
-  const int y = blockIdx.y;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (y < njobs) {
-    const AxisJob J = jobs[y];
-    if (i < J.n0) {
-      J.pre[i] = pre_value(J, i);
-    } else if (i < J.n0 + J.n1) {
-      if (J.post) J.post[i - J.n0] = post_value(J, i - J.n0);
-    } else if (i < J.n0 + J.n1 + J.L) {
-      const int e = i - J.n0 - J.n1;
-      J.H[e] = kernel_value(J, e);
-    }
-  } else if (y - njobs < ntw) {
-    const TwiddleJob T = tws[y - njobs];
-    if (i < T.L) {
-      double s, c;
-      sincospi(-2.0 * (double)i / (double)T.L, &s, &c);
-      T.tw[i] = make_float2((float)c, (float)s);
-    }
+template <int L>
+__device__ __forceinline__ bool twiddle_l(bool spec, int e, float2* out) {
+  return spec ? twiddle_entry<SpecPlan<L>>(e, out) : twiddle_entry<PassPlan<L>>(e, out);
+}
+__device__ __forceinline__ bool twiddle_any(int L, bool spec, int e, float2* out) {
+  switch (L) {
+    case 64: return twiddle_l<64>(spec, e, out);
+    case 128: return twiddle_l<128>(spec, e, out);
+    case 256: return twiddle_l<256>(spec, e, out);
+    case 512: return twiddle_l<512>(spec, e, out);
+    case 1024: return twiddle_l<1024>(spec, e, out);
+    case 2048: return twiddle_l<2048>(spec, e, out);
+    case 4096: return twiddle_l<4096>(spec, e, out);
+    case 8192: return twiddle_l<8192>(spec, e, out);
+    default: return false;
   }
 }
 
-// One workgroup per (view, axis) job of length L: H <- FFT(h) / L in place.
 template <int L>
-__global__ void __launch_bounds__(FftPlan<L>::TPR) spectrum_kernel(const AxisJob* __restrict__ jobs, int first,
-                                                                   const float2* __restrict__ tw) {
-  constexpr int TPR = FftPlan<L>::TPR;
-  constexpr int R = L / TPR;
-  __shared__ float2 lds[lds_row_len(L)];
-  const AxisJob& J = jobs[first + blockIdx.x];
-  float2* H = J.H;
-  const int t = threadIdx.x;
+static int twiddle_len_l(bool spec) {
+  return spec ? twiddle_entries<SpecPlan<L>>() : twiddle_entries<PassPlan<L>>();
+}
+int twiddle_len(int L, bool spec) {
+  switch (L) {
+    case 64: return twiddle_len_l<64>(spec);
+    case 128: return twiddle_len_l<128>(spec);
+    case 256: return twiddle_len_l<256>(spec);
+    case 512: return twiddle_len_l<512>(spec);
+    case 1024: return twiddle_len_l<1024>(spec);
+    case 2048: return twiddle_len_l<2048>(spec);
+    case 4096: return twiddle_len_l<4096>(spec);
+    case 8192: return twiddle_len_l<8192>(spec);
+    default: return -1;
+  }
+}
+
+// Split (real/imaginary in turn) LDS exchanges halve the LDS a row needs.
+constexpr bool kSplit = true;
+
+// Setup roles ---------------------------------------------------------------
+
+// Spectrum: H = FFT_L(h) / L for GS axis jobs of length L per workgroup (one,
+// or as many as fill the workgroup when a transform needs 128+ threads).  All
+// threads first evaluate h of Eq. (4) (FP64 phase) into LDS, then the
+// transform threads run the FFT with computed twiddles; this role depends on
+// no other.
+template <int L>
+struct SpecShape {
+  using P = SpecPlan<L>;
+  static constexpr int GS = kSetupThreads / P::TPR;  // spectra per workgroup
+  static constexpr int STAGE = GS * L * 8;
+  static constexpr int EXCH = GS * row_lds_bytes<L, kSplit>();
+  static constexpr int BYTES = STAGE > EXCH ? STAGE : EXCH;
+};
+
+template <int L>
+__device__ __forceinline__ void setup_spectrum(const SetupArgs& A, const SetupRole& Ro, int rb, void* lds) {
+  using P = SpecPlan<L>;
+  constexpr int TPR = P::TPR;
+  constexpr int R = P::R;
+  constexpr int GS = SpecShape<L>::GS;
+  float2* hs = static_cast<float2*>(lds);
+  for (int e = threadIdx.x; e < GS * L; e += kSetupThreads) {
+    const int g = e / L;
+    const int k = rb * GS + g;
+    float2 h = make_float2(0.f, 0.f);
+    if (k < Ro.c) h = kernel_value(A.axis[Ro.b + k], e - g * L);
+    hs[e] = h;
+  }
+  __syncthreads();
+  const int g = threadIdx.x / TPR;
+  const int t = threadIdx.x - g * TPR;
   float2 v[R];
 #pragma unroll
-  for (int i = 0; i < R; ++i) v[i] = H[t + TPR * i];
-  fft_row<L, false>(v, lds, t, tw);
+  for (int i = 0; i < R; ++i) v[i] = hs[g * L + t + TPR * i];
+  __syncthreads();
+  fft_row<P, false, kSplit>(v, static_cast<char*>(lds) + g * row_lds_bytes<L, kSplit>(), t, Ro.tw);
+  const int k = rb * GS + g;
+  if (k >= Ro.c) return;
+  const AxisJob& J = A.axis[Ro.b + k];
   const float inv = 1.0f / (float)L;
 #pragma unroll
-  for (int i = 0; i < R; ++i) H[t + TPR * i] = make_float2(v[i].x * inv, v[i].y * inv);
+  for (int i = 0; i < R; ++i) gst(J.H, (unsigned)(t + TPR * i), make_float2(v[i].x * inv, v[i].y * inv));
+}
+
+// Hologram -> column tiles (see TileJob): full-row reads of a kTileRows x
+// kTileCols block, then per tile kTileRows * G contiguous elements.
+template <typename T>
+__device__ __forceinline__ void tile_block(const TileJob& J, int r0, int c0, T* buf) {
+  constexpr int RB = kTileRows, CB = kTileCols, SP = CB + 1;
+  const T* in = static_cast<const T*>(J.in);
+  T* out = static_cast<T*>(J.out);
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int rr = 0; rr < RB; ++rr) {
+    const int n = r0 + rr, c = c0 + tid;
+    T v{};
+    if (n < J.ny && c < J.nx) v = gld(in, (unsigned)(n * J.nx + c));
+    buf[rr * SP + tid] = v;
+  }
+  __syncthreads();
+  const int G = J.G;
+#pragma unroll
+  for (int it = 0; it < RB; ++it) {
+    const int e = tid + it * CB;
+    const int g = e % G;
+    const int rr = (e / G) % RB;
+    const int ct = e / (G * RB);
+    const int n = r0 + rr;
+    const int tile = c0 / G + ct;
+    if (n < J.ny && tile * G < J.nx)
+      gst(out, (unsigned)(tile * J.tile_stride + n * G + g), buf[rr * SP + ct * G + g]);
+  }
 }
 
 template <int L>
-struct PassShape {
-  static constexpr int TPR = FftPlan<L>::TPR;
-  static constexpr int R = L / TPR;
-  static constexpr int G = (8192 / L) * TPR <= 512 ? 8192 / L : 512 / TPR;  // rows per workgroup
-  static constexpr int THREADS = G * TPR;
+constexpr int spectrum_lds_bytes() {
+  return SpecShape<L>::BYTES;
+}
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int kSetupLds =
+    cmax(cmax(cmax(spectrum_lds_bytes<64>(), spectrum_lds_bytes<128>()),
+              cmax(spectrum_lds_bytes<256>(), spectrum_lds_bytes<512>())),
+         cmax(cmax(cmax(spectrum_lds_bytes<1024>(), spectrum_lds_bytes<2048>()),
+                   cmax(spectrum_lds_bytes<4096>(), spectrum_lds_bytes<8192>())),
+              kTileRows * (kTileCols + 1) * 8));
+
+__global__ void __launch_bounds__(kSetupThreads) setup_kernel(const SetupArgs A) {
+  __shared__ __align__(16) unsigned char lds[kSetupLds];
+  int r = 0;
+  while (r + 1 < A.nroles && (int)blockIdx.x >= A.roles[r + 1].first_block) ++r;
+  const SetupRole& Ro = A.roles[r];
+  const int rb = blockIdx.x - Ro.first_block;
+  switch (Ro.kind) {
+    case kRoleSpectrum:
+      switch (Ro.a) {
+        case 64: setup_spectrum<64>(A, Ro, rb, lds); break;
+        case 128: setup_spectrum<128>(A, Ro, rb, lds); break;
+        case 256: setup_spectrum<256>(A, Ro, rb, lds); break;
+        case 512: setup_spectrum<512>(A, Ro, rb, lds); break;
+        case 1024: setup_spectrum<1024>(A, Ro, rb, lds); break;
+        case 2048: setup_spectrum<2048>(A, Ro, rb, lds); break;
+        case 4096: setup_spectrum<4096>(A, Ro, rb, lds); break;
+        case 8192: setup_spectrum<8192>(A, Ro, rb, lds); break;
+        default: break;
+      }
+      break;
+    case kRoleTables: {
+      const int job = Ro.b + rb / Ro.a;
+      const int i = (rb % Ro.a) * kSetupThreads + threadIdx.x;
+      const AxisJob& J = A.axis[job];
+      if (i < J.n0) gst(J.pre, (unsigned)i, pre_value(J, i));
+      else if (J.post && i < J.n0 + J.n1) gst(J.post, (unsigned)(i - J.n0), post_value(J, i - J.n0));
+      break;
+    }
+    case kRoleTwiddles: {
+      const TwiddleJob& T = A.tw[Ro.a];
+      const int i = rb * kSetupThreads + threadIdx.x;
+      float2 w;
+      if (i < T.count && twiddle_any(T.L, T.spec != 0, i, &w)) gst(T.tw, (unsigned)i, w);
+      break;
+    }
+    case kRoleTiles: {
+      const TileJob& T = A.tiles[Ro.a];
+      const int c0 = (rb % Ro.b) * kTileCols;
+      const int r0 = (rb / Ro.b) * kTileRows;
+      if (T.complex_in) tile_block<float2>(T, r0, c0, reinterpret_cast<float2*>(lds));
+      else tile_block<float>(T, r0, c0, reinterpret_cast<float*>(lds));
+      break;
+    }
+    default: break;
+  }
+}
+
+// Occupancy targets (wavefronts per SIMD) handed to the register allocator.
+#ifndef SFD_ROW_WPE
+#define SFD_ROW_WPE 1
+#endif
+#ifndef SFD_COL_WPE
+#define SFD_COL_WPE 1
+#endif
+
+// Workgroup shape of the passes: NW wavefronts; G = NW * 64 / TPR rows (or
+// columns) per workgroup.
+template <int L>
+struct RowCfg {
+  static constexpr int TPR = PassPlan<L>::TPR;
+  static constexpr int NW = TPR >= 256 ? 4 : TPR >= 128 ? 2 : 2;
+  static constexpr int G = NW * 64 / TPR;
+};
+template <int L>
+struct ColCfg {
+  static constexpr int TPR = PassPlan<L>::TPR;
+  static constexpr int NW = TPR >= 128 ? 8 : TPR >= 32 ? 8 * TPR / 64 : 2;
+  static constexpr int G = NW * 64 / TPR;
 };
 
-// Map a workgroup to a tile so that consecutive tiles (which write adjacent
-// pieces of the same cache lines in the transposed store) run on the same
-// XCD: workgroups are dispatched round-robin over the 8 XCDs.
+// Map a workgroup to a tile so that consecutive tiles (which touch adjacent
+// pieces of the same cache lines) run on the same XCD: workgroups are
+// dispatched round-robin over the 8 XCDs.
 __device__ __forceinline__ int xcd_tile(int b, int total) {
   const int per = total >> 3;
   if ((total & 7) != 0 || per == 0) return b;
   return (b & 7) * per + (b >> 3);
 }
 
-template <int L>
-__global__ void __launch_bounds__(PassShape<L>::THREADS) pass_kernel(const PassArgs args,
-                                                                     const float2* __restrict__ tw) {
-  constexpr int TPR = PassShape<L>::TPR;
-  constexpr int R = PassShape<L>::R;
-  constexpr int G = PassShape<L>::G;
-  constexpr int ROWLEN = lds_row_len(L);
-  __shared__ float2 lds[G * ROWLEN];
-
-  const int tile = xcd_tile(blockIdx.x, args.total_tiles);
-  // Job containing this tile (binary search over the prefix in kernel arguments).
+__device__ __forceinline__ int find_job(const PassArgs& args, int tile) {
   int lo = 0, hi = args.njobs - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     if (args.tile_prefix[mid] <= tile) lo = mid;
     else hi = mid - 1;
   }
-  const RowJob J = args.jobs[lo];
-  const int row0 = (tile - args.tile_prefix[lo]) * G;
-  const int g = threadIdx.x / TPR;
-  const int t = threadIdx.x - g * TPR;
-  const int row = row0 + g;
-  const bool valid = row < J.n_rows;
-  float2* buf = lds + g * ROWLEN;
+  return lo;
+}
 
-  // Steps 2-3: load the row times the pre-chirp, zero beyond n_in.
+// Wave-uniform value (the compiler then keeps it, and addresses built from
+// it, in scalar registers).
+__device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// v[i] = in[t + TPR i] * pre[t + TPR i] for t + TPR i < n, zero beyond: the
+// padded, pre-chirped row (n >= 1).  The common case n = L/2 (the paper's
+// doubled grid) is straight-line code; otherwise loads go to a clamped index
+// (so they still issue back to back) and the padding is selected to zero.
+template <int TPR, int R, bool REAL>
+__device__ __forceinline__ float2 pre_times_in(const void* in, const float2* pre, unsigned m) {
+  const float2 p = gld(pre, m);
+  if constexpr (REAL) {
+    const float a = gld(static_cast<const float*>(in), m);
+    return make_float2(a * p.x, a * p.y);
+  } else {
+    return cmul(gld(static_cast<const float2*>(in), m), p);
+  }
+}
+template <int TPR, int R, bool REAL>
+__device__ __forceinline__ void load_row(float2 (&v)[R], const void* in, const float2* pre, int n, int t) {
+  if (n == TPR * R / 2) {
+#pragma unroll
+    for (int i = 0; i < R / 2; ++i) {
+      v[i] = pre_times_in<TPR, R, REAL>(in, pre, (unsigned)(t + TPR * i));
+      if ((i & 7) == 7) sched_fence();
+    }
+#pragma unroll
+    for (int i = R / 2; i < R; ++i) v[i] = make_float2(0.f, 0.f);
+    return;
+  }
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int m = t + TPR * i;
+    const float2 x = pre_times_in<TPR, R, REAL>(in, pre, (unsigned)(m < n ? m : n - 1));
+    v[i] = m < n ? x : make_float2(0.f, 0.f);
+    if ((i & 7) == 7) sched_fence();
+  }
+}
+
+// x transforms: row r of the job reads in + r * in_ld and writes
+// out + r * out_ld (contiguous), both straight from registers.
+template <int L>
+__global__ void __launch_bounds__(RowCfg<L>::NW * 64) __attribute__((amdgpu_waves_per_eu(SFD_ROW_WPE))) row_kernel(const PassArgs args, const float2* __restrict__ tw) {
+  constexpr int TPR = RowCfg<L>::TPR;
+  constexpr int R = L / TPR;
+  constexpr int G = RowCfg<L>::G;
+  constexpr int RB = row_lds_bytes<L, kSplit>();
+  __shared__ __align__(16) unsigned char lds[G * RB];
+
+  const int tile = xcd_tile(blockIdx.x, args.total_tiles);
+  const int jid = find_job(args, tile);
+  const RowJob& J = args.jobs[jid];
+  // With TPR >= 64 a row is a whole number of wavefronts: g is wave-uniform.
+  const int g = TPR >= 64 ? uniform(threadIdx.x / TPR) : threadIdx.x / TPR;
+  const int t = threadIdx.x - g * TPR;
+  const int row = (tile - args.tile_prefix[jid]) * G + g;
+  const bool valid = row < J.n_rows;
+  const int vrow = valid ? row : 0;
+  const int n_in = J.n_in;
+
+  // A row past the end of the job computes on row 0 and stores nothing.
   float2 v[R];
-  if (J.mode & kInReal) {
-    const float* in = static_cast<const float*>(J.in) + (int64_t)(valid ? row : 0) * J.in_ld;
+  if (J.mode & kInReal)
+    load_row<TPR, R, true>(v, static_cast<const float*>(J.in) + (int64_t)vrow * J.in_ld, J.pre, n_in, t);
+  else
+    load_row<TPR, R, false>(v, static_cast<const float2*>(J.in) + (int64_t)vrow * J.in_ld, J.pre, n_in, t);
+
+  void* buf = lds + g * RB;
+  fft_row<PassPlan<L>, false, kSplit>(v, buf, t, tw);
+  const float2* __restrict__ H = J.H;
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    v[i] = cmul(v[i], gld(H, (unsigned)(t + TPR * i)));
+    if ((i & 7) == 7) sched_fence();
+  }
+  fft_row<PassPlan<L>, true, kSplit>(v, buf, t, tw);
+
+  if (!valid) return;
+  const int n_out = J.n_out;
+  const int mode = J.mode;
+  if (mode & kUsePost) {
+    const float2* post = J.post;
 #pragma unroll
     for (int i = 0; i < R; ++i) {
       const int m = t + TPR * i;
-      if (valid && m < J.n_in) {
-        const float a = in[m];
-        const float2 p = J.pre[m];
-        v[i] = make_float2(a * p.x, a * p.y);
-      } else {
-        v[i] = make_float2(0.f, 0.f);
+      if (TPR * (i + 1) <= n_out || m < n_out) v[i] = cmul(v[i], gld(post, (unsigned)m));
+    }
+  }
+  if (mode & kOutField) {
+    float2* out = static_cast<float2*>(J.out) + (int64_t)row * J.out_ld;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int m = t + TPR * i;
+      if (TPR * (i + 1) <= n_out || m < n_out) gst(out, (unsigned)m, v[i]);
+    }
+  }
+  if (mode & kOutIntensity) {
+    float* out = ((mode & kOutField) ? J.out2 : static_cast<float*>(J.out)) + (int64_t)row * J.out_ld;
+    const float sc = J.iscale;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int m = t + TPR * i;
+      if (TPR * (i + 1) <= n_out || m < n_out) gst(out, (unsigned)m, (v[i].x * v[i].x + v[i].y * v[i].y) * sc);
+    }
+  }
+}
+
+// y transforms: column c of the job reads in[n * in_ld + c] for n < n_in and
+// writes out[m * out_ld + c] for m < n_out (complex).  G columns per
+// workgroup go through LDS staging in chunks of L/2 elements, so that each
+// global access covers G consecutive columns.
+template <int L>
+__global__ void __launch_bounds__(ColCfg<L>::NW * 64) __attribute__((amdgpu_waves_per_eu(SFD_COL_WPE))) col_kernel(const PassArgs args, const float2* __restrict__ tw) {
+  constexpr int TPR = ColCfg<L>::TPR;
+  constexpr int R = L / TPR;
+  constexpr int G = ColCfg<L>::G;
+  constexpr int THREADS = ColCfg<L>::NW * 64;
+  constexpr int RB = row_lds_bytes<L, kSplit>();
+  constexpr int C = L / 2;    // staging chunk along the transform
+  constexpr int SST = C + 9;  // staging stride per column (elements)
+  constexpr int STAGE_BYTES = G * SST * 8;
+  constexpr int LDS_BYTES = G * RB > STAGE_BYTES ? G * RB : STAGE_BYTES;
+  static_assert((G & (G - 1)) == 0, "columns per workgroup must be a power of two");
+  __shared__ __align__(16) unsigned char lds[LDS_BYTES];
+  float2* st = reinterpret_cast<float2*>(lds);
+  float* stf = reinterpret_cast<float*>(lds);
+
+  const int tile = xcd_tile(blockIdx.x, args.total_tiles);
+  const int jid = find_job(args, tile);
+  const RowJob& J = args.jobs[jid];
+  const int c0 = (tile - args.tile_prefix[jid]) * G;
+  const int g = TPR >= 64 ? uniform(threadIdx.x / TPR) : threadIdx.x / TPR;
+  const int t = threadIdx.x - g * TPR;
+  const int ncols = J.n_rows;
+  const int n_in = J.n_in;
+  const int in_ld = (int)J.in_ld;
+  const float2* __restrict__ pre = J.pre;
+  const bool real_in = (J.mode & kInReal) != 0;
+  // Column of the staging loop for this thread (fixed: THREADS is a multiple of G).
+  const int gs = threadIdx.x & (G - 1);
+  const bool col_ok = c0 + gs < ncols;
+
+  float2 v[R];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int n_lo = c * C;
+    if (n_lo >= n_in) {
+#pragma unroll
+      for (int i = c * (R / 2); i < (c + 1) * (R / 2); ++i) v[i] = make_float2(0.f, 0.f);
+      continue;
+    }
+    if (c > 0) __syncthreads();
+    // Element e of the chunk is column e % G, row n_lo + e / G; the input is
+    // this workgroup's column tile, so the reads are contiguous.
+    const unsigned tile_base = (unsigned)(c0 / G) * (unsigned)in_ld;
+    if (real_in) {
+      const float* in = static_cast<const float*>(J.in) + tile_base;
+      for (int e = threadIdx.x; e < G * C; e += THREADS) {
+        const int n = n_lo + e / G;
+        const float a = gld(in, (unsigned)((n < n_in ? n : n_in - 1) * G + gs));
+        stf[gs * SST + (n - n_lo)] = n < n_in ? a : 0.f;
+      }
+    } else {
+      const float2* in = static_cast<const float2*>(J.in) + tile_base;
+      for (int e = threadIdx.x; e < G * C; e += THREADS) {
+        const int n = n_lo + e / G;
+        const float2 a = gld(in, (unsigned)((n < n_in ? n : n_in - 1) * G + gs));
+        st[gs * SST + (n - n_lo)] = n < n_in ? a : make_float2(0.f, 0.f);
       }
     }
-  } else {
-    const float2* in = static_cast<const float2*>(J.in) + (int64_t)(valid ? row : 0) * J.in_ld;
+    __syncthreads();
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
+    for (int i = c * (R / 2); i < (c + 1) * (R / 2); ++i) {
       const int m = t + TPR * i;
-      v[i] = (valid && m < J.n_in) ? cmul(in[m], J.pre[m]) : make_float2(0.f, 0.f);
+      const float2 p = gld(pre, (unsigned)(m < n_in ? m : n_in - 1));
+      float2 x;
+      if (real_in) {
+        const float a = stf[g * SST + (m - n_lo)];
+        x = make_float2(a * p.x, a * p.y);
+      } else {
+        x = cmul(st[g * SST + (m - n_lo)], p);
+      }
+      v[i] = m < n_in ? x : make_float2(0.f, 0.f);
+      if ((i & 7) == 7) sched_fence();
     }
   }
+  __syncthreads();
 
-  // Step 4: forward FFT; step 7: multiply by FFT(h)/L; step 8: inverse FFT.
-  fft_row<L, false>(v, buf, t, tw);
+  void* buf = lds + g * RB;
+  fft_row<PassPlan<L>, false, kSplit>(v, buf, t, tw);
+  const float2* __restrict__ H = J.H;
 #pragma unroll
-  for (int i = 0; i < R; ++i) v[i] = cmul(v[i], J.H[t + TPR * i]);
-  fft_row<L, true>(v, buf, t, tw);
+  for (int i = 0; i < R; ++i) {
+    v[i] = cmul(v[i], gld(H, (unsigned)(t + TPR * i)));
+    if ((i & 7) == 7) sched_fence();
+  }
+  fft_row<PassPlan<L>, true, kSplit>(v, buf, t, tw);
 
-  // Steps 9-10: crop to n_out, post-chirp and/or |.|^2, transposed store
-  // staged through LDS so that G consecutive rows are written together.
   const int n_out = J.n_out;
-  const int SP = n_out + 1;  // staging stride per row (odd, against bank conflicts)
   if (J.mode & kUsePost) {
+    const float2* post = J.post;
 #pragma unroll
     for (int i = 0; i < R; ++i) {
       const int m = t + TPR * i;
-      if (m < n_out) v[i] = cmul(v[i], J.post[m]);
+      if (TPR * (i + 1) <= n_out || m < n_out) v[i] = cmul(v[i], gld(post, (unsigned)m));
     }
   }
-  if (J.mode & kUseScale) {
+  float2* out = static_cast<float2*>(J.out) + c0 + gs;
+  const int out_ld = (int)J.out_ld;
 #pragma unroll
-    for (int i = 0; i < R; ++i) v[i] = cmul(v[i], J.scale);
-  }
-  if (J.mode & kOutField) {
+  for (int c = 0; c < 2; ++c) {
+    const int m_lo = c * C;
+    if (m_lo >= n_out) break;
     __syncthreads();
-    float2* st = lds + g * SP;
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
+    for (int i = c * (R / 2); i < (c + 1) * (R / 2); ++i) {
       const int m = t + TPR * i;
-      if (m < n_out) st[m] = v[i];
+      if (TPR * (i + 1) <= n_out || m < n_out) st[g * SST + (m - m_lo)] = v[i];
     }
     __syncthreads();
-    float2* out = static_cast<float2*>(J.out);
-    for (int e = threadIdx.x; e < G * n_out; e += G * TPR) {
-      const int m = e / G;
-      const int gg = e - m * G;
-      if (row0 + gg < J.n_rows) out[(int64_t)m * J.out_ld + row0 + gg] = lds[gg * SP + m];
-    }
-  }
-  if (J.mode & kOutIntensity) {
-    __syncthreads();
-    float* st = reinterpret_cast<float*>(lds) + g * SP;
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-      const int m = t + TPR * i;
-      if (m < n_out) st[m] = (v[i].x * v[i].x + v[i].y * v[i].y) * J.iscale;
-    }
-    __syncthreads();
-    const float* sb = reinterpret_cast<const float*>(lds);
-    float* out = (J.mode & kOutField) ? J.out2 : static_cast<float*>(J.out);
-    for (int e = threadIdx.x; e < G * n_out; e += G * TPR) {
-      const int m = e / G;
-      const int gg = e - m * G;
-      if (row0 + gg < J.n_rows) out[(int64_t)m * J.out_ld + row0 + gg] = sb[gg * SP + m];
+    const int cnt = (n_out - m_lo < C ? n_out - m_lo : C) * G;
+    for (int e = threadIdx.x; e < cnt; e += THREADS) {
+      const int m = m_lo + e / G;
+      if (col_ok) gst(out, (unsigned)(m * out_ld), st[gs * SST + (m - m_lo)]);
     }
   }
 }
 
-bool supported_length(int L) {
-  switch (L) {
-    case 64: case 128: case 256: case 512: case 1024: case 2048: case 4096: case 8192: return true;
-    default: return false;
-  }
-}
+bool supported_length(int L) { return twiddle_len(L, false) >= 0; }
 
-int rows_per_tile(int L) {
+int rows_per_tile(int L, bool col) {
   switch (L) {
-    case 64: return PassShape<64>::G;
-    case 128: return PassShape<128>::G;
-    case 256: return PassShape<256>::G;
-    case 512: return PassShape<512>::G;
-    case 1024: return PassShape<1024>::G;
-    case 2048: return PassShape<2048>::G;
-    case 4096: return PassShape<4096>::G;
-    case 8192: return PassShape<8192>::G;
+    case 64: return col ? ColCfg<64>::G : RowCfg<64>::G;
+    case 128: return col ? ColCfg<128>::G : RowCfg<128>::G;
+    case 256: return col ? ColCfg<256>::G : RowCfg<256>::G;
+    case 512: return col ? ColCfg<512>::G : RowCfg<512>::G;
+    case 1024: return col ? ColCfg<1024>::G : RowCfg<1024>::G;
+    case 2048: return col ? ColCfg<2048>::G : RowCfg<2048>::G;
+    case 4096: return col ? ColCfg<4096>::G : RowCfg<4096>::G;
+    case 8192: return col ? ColCfg<8192>::G : RowCfg<8192>::G;
     default: return 0;
   }
 }
 
-hipError_t launch_tables(const AxisJob* d_jobs, int njobs, int max_len, const TwiddleJob* d_tw, int ntw,
-                         int max_L, hipStream_t s) {
-  const int span = max_len > max_L ? max_len : max_L;
-  dim3 grid((span + 255) / 256, njobs + ntw);
-  hipLaunchKernelGGL(tables_kernel, grid, dim3(256), 0, s, d_jobs, njobs, d_tw, ntw);
+hipError_t launch_setup(const SetupArgs& a, hipStream_t s) {
+  if (a.total_blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(setup_kernel, dim3(a.total_blocks), dim3(kSetupThreads), 0, s, a);
   return hipGetLastError();
 }
 
-template <int L>
-static hipError_t spectra_l(const AxisJob* d_jobs, int first, int count, const float2* tw, hipStream_t s) {
-  hipLaunchKernelGGL(spectrum_kernel<L>, dim3(count), dim3(FftPlan<L>::TPR), 0, s, d_jobs, first, tw);
-  return hipGetLastError();
-}
-
-hipError_t launch_spectra(int L, const AxisJob* d_jobs, int first, int count, const float2* tw, hipStream_t s) {
+int spectra_per_block(int L) {
   switch (L) {
-    case 64: return spectra_l<64>(d_jobs, first, count, tw, s);
-    case 128: return spectra_l<128>(d_jobs, first, count, tw, s);
-    case 256: return spectra_l<256>(d_jobs, first, count, tw, s);
-    case 512: return spectra_l<512>(d_jobs, first, count, tw, s);
-    case 1024: return spectra_l<1024>(d_jobs, first, count, tw, s);
-    case 2048: return spectra_l<2048>(d_jobs, first, count, tw, s);
-    case 4096: return spectra_l<4096>(d_jobs, first, count, tw, s);
-    case 8192: return spectra_l<8192>(d_jobs, first, count, tw, s);
-    default: return hipErrorInvalidValue;
+    case 64: return SpecShape<64>::GS;
+    case 128: return SpecShape<128>::GS;
+    case 256: return SpecShape<256>::GS;
+    case 512: return SpecShape<512>::GS;
+    case 1024: return SpecShape<1024>::GS;
+    case 2048: return SpecShape<2048>::GS;
+    case 4096: return SpecShape<4096>::GS;
+    case 8192: return SpecShape<8192>::GS;
+    default: return 0;
   }
 }
 
 template <int L>
-static hipError_t pass_l(const PassArgs& a, const float2* tw, hipStream_t s) {
-  hipLaunchKernelGGL(pass_kernel<L>, dim3(a.total_tiles), dim3(PassShape<L>::THREADS), 0, s, a, tw);
+static hipError_t pass_l(bool col, const PassArgs& a, const float2* tw, hipStream_t s) {
+  if (col)
+    hipLaunchKernelGGL(col_kernel<L>, dim3(a.total_tiles), dim3(ColCfg<L>::NW * 64), 0, s, a, tw);
+  else
+    hipLaunchKernelGGL(row_kernel<L>, dim3(a.total_tiles), dim3(RowCfg<L>::NW * 64), 0, s, a, tw);
   return hipGetLastError();
 }
 
-hipError_t launch_pass(int L, const PassArgs& a, const float2* tw, hipStream_t s) {
+hipError_t launch_pass(int L, bool col, const PassArgs& a, const float2* tw, hipStream_t s) {
   if (a.total_tiles <= 0) return hipSuccess;
   switch (L) {
-    case 64: return pass_l<64>(a, tw, s);
-    case 128: return pass_l<128>(a, tw, s);
-    case 256: return pass_l<256>(a, tw, s);
-    case 512: return pass_l<512>(a, tw, s);
-    case 1024: return pass_l<1024>(a, tw, s);
-    case 2048: return pass_l<2048>(a, tw, s);
-    case 4096: return pass_l<4096>(a, tw, s);
-    case 8192: return pass_l<8192>(a, tw, s);
+    case 64: return pass_l<64>(col, a, tw, s);
+    case 128: return pass_l<128>(col, a, tw, s);
+    case 256: return pass_l<256>(col, a, tw, s);
+    case 512: return pass_l<512>(col, a, tw, s);
+    case 1024: return pass_l<1024>(col, a, tw, s);
+    case 2048: return pass_l<2048>(col, a, tw, s);
+    case 4096: return pass_l<4096>(col, a, tw, s);
+    case 8192: return pass_l<8192>(col, a, tw, s);
     default: return hipErrorInvalidValue;
   }
 }
