@@ -233,6 +233,7 @@ class SFDFunction(torch.autograd.Function):
         nv = len(plan.views)
         ctx.plan = plan
         ctx.zl = zl
+        ctx.z_meta = (z.device, z.dtype)
         ctx.save_for_backward(fields)
         ctx.u1 = res[nv:]
         return tuple(res[:nv])
@@ -243,4 +244,5 @@ class SFDFunction(torch.autograd.Function):
         plan = ctx.plan
         gi = [g if g is not None else torch.zeros_like(u, dtype=torch.float32) for g, u in zip(grad_i, ctx.u1)]
         grad_in, gz = plan.backward([g.to(torch.float32) for g in gi], fields, ctx.zl, field_out=ctx.u1)
-        return grad_in.view_as(fields), gz.to(torch.float64), None
+        zdev, zdtype = ctx.z_meta
+        return grad_in.view_as(fields), gz.to(zdev, zdtype), None

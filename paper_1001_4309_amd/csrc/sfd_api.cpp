@@ -128,8 +128,22 @@ struct sfd_plan_s {
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
   hipEvent_t upload_event = nullptr;
-  std::vector<unsigned char> last_desc;
-  void* last_ws = nullptr;
+  std::vector<unsigned char> last_desc[2];  // forward, backward descriptor images
+  void* last_ws[2] = {nullptr, nullptr};
+
+  // Backward (adjoint and z-derivative) workspace layout, SFD_IN_C64 plans.
+  struct BwdLayout {
+    size_t prexf, preyf, postxf, postyf, prexm, preym, prexa, preya, postxa, postya;
+    size_t hxf, hyf, hxa, hya;
+    size_t gtile;
+    int gtile_stride, ga;
+    size_t wf, wm, wa, vbuf;  // vbuf = 0: adjoint written straight into grad_in
+    size_t p12, p3, p4, p5;
+    int nt_r, nt_a;           // tiles of the row passes on the view grid / hologram grid
+  };
+  std::vector<BwdLayout> blay;
+  std::vector<int> holo_views;  // views per hologram
+  size_t bwd_desc_off = 0, bwd_desc_bytes = 0;
 
   // Benchmark timing (sfd_profile_enable).
   bool profiling = false;
@@ -202,6 +216,13 @@ struct CallDescs {
   std::vector<int> row_L;              // L of each row job
   int n_pass_x = 0;
 };
+
+size_t bwd_desc_capacity(int n_views, int n_holo, int n_lengths, int n_tiles) {
+  return align_up(sizeof(sfd::AxisJob) * 6 * n_views) + align_up(sizeof(sfd::TwiddleJob) * 2 * n_lengths) +
+         align_up(sizeof(sfd::TileJob) * (n_tiles + n_views)) + align_up(sizeof(sfd::RowJob) * 7 * n_views) +
+         align_up(sizeof(sfd::GradZJob) * n_views) + align_up(sizeof(sfd::GatherJob) * n_holo) +
+         align_up(sizeof(void*) * n_views);
+}
 
 size_t desc_capacity(int n_views, int n_lengths, int n_tiles) {
   return align_up(sizeof(sfd::AxisJob) * 2 * n_views) + align_up(sizeof(sfd::TwiddleJob) * 2 * n_lengths) +
@@ -370,8 +391,11 @@ void pack_descs(const sfd_plan_s* P, const CallDescs& D, std::vector<unsigned ch
   std::memcpy(img->data() + *off_rows, D.rows.data(), sizeof(sfd::RowJob) * D.rows.size());
 }
 
-sfd_status upload(sfd_plan_s* P, const std::vector<unsigned char>& img, char* ws, hipStream_t stream) {
-  if (P->last_ws == ws && P->last_desc == img) return SFD_OK;
+// Copy a descriptor image into the workspace at ``dst_off`` (slot 0:
+// forward, 1: backward), unless the same image already sits there.
+sfd_status upload(sfd_plan_s* P, int slot, const std::vector<unsigned char>& img, char* ws, size_t dst_off,
+                  hipStream_t stream) {
+  if (P->last_ws[slot] == ws && P->last_desc[slot] == img) return SFD_OK;
   if (!P->upload_event) SFD_HIP_TRY(hipEventCreateWithFlags(&P->upload_event, hipEventDisableTiming));
   if (P->pinned_bytes < img.size()) {
     if (P->pinned) {
@@ -386,10 +410,10 @@ sfd_status upload(sfd_plan_s* P, const std::vector<unsigned char>& img, char* ws
     SFD_HIP_TRY(hipEventSynchronize(P->upload_event));
   }
   std::memcpy(P->pinned, img.data(), img.size());
-  SFD_HIP_TRY(hipMemcpyAsync(ws + P->desc_off, P->pinned, img.size(), hipMemcpyHostToDevice, stream));
+  SFD_HIP_TRY(hipMemcpyAsync(ws + dst_off, P->pinned, img.size(), hipMemcpyHostToDevice, stream));
   SFD_HIP_TRY(hipEventRecord(P->upload_event, stream));
-  P->last_desc = img;
-  P->last_ws = ws;
+  P->last_desc[slot] = img;
+  P->last_ws[slot] = ws;
   return SFD_OK;
 }
 
@@ -397,7 +421,9 @@ sfd_status upload(sfd_plan_s* P, const std::vector<unsigned char>& img, char* ws
 // ``twiddles``, and tile jobs [t0, t0 + nt).
 sfd_status launch_setup_for(sfd_plan_s* P, const CallDescs& D, char* ws, const sfd::AxisJob* d_axis,
                             const sfd::TwiddleJob* d_tw, const sfd::TileJob* d_tiles, int a0, int na,
-                            bool twiddles, int t0, int nt, hipStream_t stream) {
+                            bool twiddles, int t0, int nt, hipStream_t stream, int spec_count = -1) {
+  // Spectra for axis jobs [a0, a0 + spec_count) (default: all na), tables for [a0, a0 + na).
+  const int ns = spec_count < 0 ? na : spec_count;
   sfd::SetupArgs A{};
   A.axis = d_axis;
   A.tw = d_tw;
@@ -422,9 +448,9 @@ sfd_status launch_setup_for(sfd_plan_s* P, const CallDescs& D, char* ws, const s
   };
   sfd_status st;
   // Kernel spectra: runs of equal L.
-  for (int i = a0; i < a0 + na;) {
+  for (int i = a0; i < a0 + ns;) {
     int j = i;
-    while (j < a0 + na && D.axis_L[j] == D.axis_L[i]) ++j;
+    while (j < a0 + ns && D.axis_L[j] == D.axis_L[i]) ++j;
     const int L = D.axis_L[i];
     const int per = sfd::spectra_per_block(L);
     const float2* stw = reinterpret_cast<const float2*>(ws + P->spec_tw_off.at(L));
@@ -493,6 +519,329 @@ sfd_status check_z(const sfd_plan_s* P, const double* z) {
   for (size_t v = 0; v < P->views.size(); ++v)
     if (!std::isfinite(z[v]) || z[v] == 0.0)
       return fail(SFD_ERR_INVALID_ARG, "z[" + std::to_string(v) + "] must be finite and non-zero");
+  return SFD_OK;
+}
+
+// Backward pass (see include/sfd.h).  Per view v with u1 = A u0 and
+// g = dL/dRe(u1) + i dL/dIm(u1):
+//   grad_in[holo(v)] += A^H g, with A^H = conj(c) Ay^H (x) Ax^H: the same two
+//     passes on g with the planes swapped and z -> -z;
+//   dL/dz = Re sum conj(g) du1/dz, du1/dz = A (i k - 1/z - i pi r^2/(lambda z^2)) u0 with
+//     r^2 = x1^2 - 2 x1 x0 + x0^2 (+ y terms), i.e. (separability)
+//     dL/dz = Re[(i k - 1/z) S1 - (i pi/(lambda z^2)) (S2 - 2 S3 - 2 S4 + S5)],
+//     S1 = sum conj(g) u1, S2 = sum conj(g) (x1^2 + y1^2) u1,
+//     S3 = sum conj(g) x1 A(x0 u0), S4 = sum conj(g) y1 A(y0 u0),
+//     S5 = sum conj(A^H g) (x0^2 + y0^2) u0.
+// A(x0 u0) reuses the y pass of u0; A(y0 u0) takes one more y pass.  The
+// sums are fused into the row-pass epilogues (FP64) and finished per view.
+sfd_status run_backward(sfd_plan_s* P, void* const* grad_out, void* const* field_out, const void* holo,
+                        const double* z_or_null, void* grad_in, double* grad_z, char* ws, hipStream_t stream) {
+  const int V = (int)P->views.size();
+  const sfd_grid& h = P->holo;
+  const bool want_z = grad_z != nullptr;
+  const bool from_i = field_out != nullptr;  // grad_out holds dL/dI
+  const size_t holo_stride = (size_t)h.nx * h.ny * sizeof(float2);
+  const double k = 2.0 * M_PI / P->lam;
+  CallDescs D;
+
+  // Axis jobs: spectrum-bearing ones (fx, fy, ax, ay per view) first, sorted
+  // by L, then the moment tables (mx, my), which reuse fx/fy spectra.
+  struct AxisTmp {
+    sfd::AxisJob j;
+    int L;
+  };
+  std::vector<AxisTmp> spec, mom;
+  auto fill = [&](const AxisScalars& sc, int n0, int n1, int L, size_t pre, size_t post, size_t H, float2 ps,
+                  int32_t flags) {
+    sfd::AxisJob j{};
+    j.a0 = sc.a0;
+    j.a1 = sc.a1;
+    j.p0 = sc.p0;
+    j.p1 = sc.p1;
+    j.inv_lz = sc.inv_lz;
+    j.S = sc.S;
+    j.c1 = sc.c1;
+    j.wscale = 1.0;
+    j.post_scale = ps;
+    j.pre = reinterpret_cast<float2*>(ws + pre);
+    j.post = post ? reinterpret_cast<float2*>(ws + post) : nullptr;
+    j.H = reinterpret_cast<float2*>(ws + H);
+    j.n0 = n0;
+    j.n1 = n1;
+    j.L = L;
+    j.flags = flags;
+    return j;
+  };
+  const int32_t pflags = (P->flags & SFD_PHASE_FP32) ? sfd::kPhaseFp32 : 0;
+  for (int v = 0; v < V; ++v) {
+    const sfd_view& w = P->views[v];
+    const sfd_plan_s::BwdLayout& B = P->blay[v];
+    const ViewLayout& L = P->lay[v];
+    const double z = z_or_null ? z_or_null[v] : w.z;
+    double c_re, c_im, ca_re, ca_im;
+    prefactor(P->lam, z, h.px, h.py, &c_re, &c_im);
+    prefactor(P->lam, -z, h.px, h.py, &ca_re, &ca_im);  // conj(c(z))
+    const AxisScalars fx = axis_scalars(h.nx, h.px, h.ox, w.out.nx, w.out.px, w.out.ox, P->lam, z);
+    const AxisScalars fy = axis_scalars(h.ny, h.py, h.oy, w.out.ny, w.out.py, w.out.oy, P->lam, z);
+    const AxisScalars ax = axis_scalars(w.out.nx, w.out.px, w.out.ox, h.nx, h.px, h.ox, P->lam, -z);
+    const AxisScalars ay = axis_scalars(w.out.ny, w.out.py, w.out.oy, h.ny, h.py, h.oy, P->lam, -z);
+    const float2 one = make_float2(1.f, 0.f);
+    spec.push_back({fill(ax, w.out.nx, h.nx, L.lx, B.prexa, B.postxa, B.hxa, make_float2((float)ca_re, (float)ca_im),
+                         pflags),
+                    L.lx});
+    spec.push_back({fill(ay, w.out.ny, h.ny, L.ly, B.preya, B.postya, B.hya, one, pflags), L.ly});
+    if (want_z) {
+      spec.push_back({fill(fx, h.nx, w.out.nx, L.lx, B.prexf, B.postxf, B.hxf, make_float2((float)c_re, (float)c_im),
+                           pflags),
+                      L.lx});
+      spec.push_back({fill(fy, h.ny, w.out.ny, L.ly, B.preyf, B.postyf, B.hyf, one, pflags), L.ly});
+      mom.push_back({fill(fx, h.nx, w.out.nx, L.lx, B.prexm, 0, B.hxf, one, pflags | sfd::kMomentX0), L.lx});
+      mom.push_back({fill(fy, h.ny, w.out.ny, L.ly, B.preym, 0, B.hyf, one, pflags | sfd::kMomentX0), L.ly});
+    }
+  }
+  std::stable_sort(spec.begin(), spec.end(), [](const AxisTmp& a, const AxisTmp& b) { return a.L < b.L; });
+  for (auto& a : spec) {
+    D.axis.push_back(a.j);
+    D.axis_L.push_back(a.L);
+  }
+  const int n_spec = (int)D.axis.size();
+  for (auto& a : mom) {
+    D.axis.push_back(a.j);
+    D.axis_L.push_back(a.L);
+  }
+  for (int L : P->lengths)
+    for (int sp = 0; sp < 2; ++sp) {
+      sfd::TwiddleJob t{};
+      t.tw = reinterpret_cast<float2*>(ws + (sp ? P->spec_tw_off.at(L) : P->tw_off.at(L)));
+      t.L = L;
+      t.count = sfd::twiddle_len(L, sp != 0);
+      t.spec = sp;
+      D.tw.push_back(t);
+    }
+
+  // Tiles: the hologram's (for the z-moment passes) and each view's gradient.
+  if (want_z)
+    for (const TileLayout& T : P->tiles) {
+      sfd::TileJob j{};
+      j.in = static_cast<const char*>(holo) + (size_t)T.holo * holo_stride;
+      j.out = ws + T.off;
+      j.nx = h.nx;
+      j.ny = h.ny;
+      j.G = T.G;
+      j.tile_stride = T.stride;
+      j.complex_in = 1;
+      D.tiles.push_back(j);
+    }
+  const int gtile0 = (int)D.tiles.size();
+  for (int v = 0; v < V; ++v) {
+    const sfd_plan_s::BwdLayout& B = P->blay[v];
+    sfd::TileJob j{};
+    j.in = from_i ? field_out[v] : grad_out[v];
+    j.in2 = from_i ? static_cast<const float*>(grad_out[v]) : nullptr;
+    j.out = ws + B.gtile;
+    j.nx = P->views[v].out.nx;
+    j.ny = P->views[v].out.ny;
+    j.G = B.ga;
+    j.tile_stride = B.gtile_stride;
+    j.complex_in = 1;
+    D.tiles.push_back(j);
+  }
+
+  // Passes.  Column jobs: the adjoint's y pass of g (C3) and, for dL/dz, the
+  // forward (C1) and y-moment (C2) y passes of u0.  Row jobs: the adjoint's
+  // x pass (R4, stores A^H g, reduces S5) and, for dL/dz, R1 (S1, S2),
+  // R2 (S3), R3 (S4).
+  std::vector<std::pair<int, sfd::RowJob>> cols, rows;
+  for (int v = 0; v < V; ++v) {
+    const sfd_view& w = P->views[v];
+    const sfd_plan_s::BwdLayout& B = P->blay[v];
+    const ViewLayout& L = P->lay[v];
+    const int ldh = inter_ld(h.nx), ldo = inter_ld(w.out.nx);
+    const double z = z_or_null ? z_or_null[v] : w.z;
+    const AxisScalars fx = axis_scalars(h.nx, h.px, h.ox, w.out.nx, w.out.px, w.out.ox, P->lam, z);
+    const AxisScalars fy = axis_scalars(h.ny, h.py, h.oy, w.out.ny, w.out.py, w.out.oy, P->lam, z);
+    const char* u0 = static_cast<const char*>(holo) + (size_t)w.holo * holo_stride;
+    auto col = [&](const void* in, int in_ld, size_t out, int out_ld, size_t pre, size_t H, size_t post, int n_rows,
+                   int n_in, int n_out) {
+      sfd::RowJob j{};
+      j.in = in;
+      j.out = ws + out;
+      j.pre = reinterpret_cast<const float2*>(ws + pre);
+      j.H = reinterpret_cast<const float2*>(ws + H);
+      j.post = reinterpret_cast<const float2*>(ws + post);
+      j.iscale = 1.f;
+      j.n_rows = n_rows;
+      j.n_in = n_in;
+      j.n_out = n_out;
+      j.in_ld = in_ld;
+      j.out_ld = out_ld;
+      j.mode = sfd::kUsePost | sfd::kOutField;
+      return j;
+    };
+    cols.push_back({L.ly, col(ws + B.gtile, B.gtile_stride, B.wa, ldo, B.preya, B.hya, B.postya, w.out.nx, w.out.ny,
+                             h.ny)});
+    if (want_z) {
+      const TileLayout& T = P->tiles[L.tile];
+      cols.push_back({L.ly, col(ws + T.off, T.stride, B.wf, ldh, B.preyf, B.hyf, B.postyf, h.nx, h.ny, w.out.ny)});
+      cols.push_back({L.ly, col(ws + T.off, T.stride, B.wm, ldh, B.preym, B.hyf, B.postyf, h.nx, h.ny, w.out.ny)});
+    }
+    auto row = [&](size_t in, int in_ld, size_t pre, size_t H, size_t post, int n_rows, int n_in, int n_out,
+                   int32_t mode, size_t partial) {
+      sfd::RowJob j{};
+      j.in = ws + in;
+      j.pre = reinterpret_cast<const float2*>(ws + pre);
+      j.H = reinterpret_cast<const float2*>(ws + H);
+      j.post = reinterpret_cast<const float2*>(ws + post);
+      j.iscale = 1.f;
+      j.n_rows = n_rows;
+      j.n_in = n_in;
+      j.n_out = n_out;
+      j.in_ld = in_ld;
+      j.mode = sfd::kUsePost | mode;
+      j.partial = reinterpret_cast<double*>(ws + partial);
+      return j;
+    };
+    // R4: A^H g onto the hologram grid; S5 = sum conj(v) (x0^2 + y0^2) u0.
+    sfd::RowJob r4 = row(B.wa, ldo, B.prexa, B.hxa, B.postxa, h.ny, w.out.nx, h.nx, sfd::kOutField, B.p5);
+    r4.out = B.vbuf ? static_cast<void*>(ws + B.vbuf)
+                    : static_cast<void*>(static_cast<char*>(grad_in) + (size_t)w.holo * holo_stride);
+    r4.out_ld = h.nx;
+    if (want_z) {
+      r4.mode |= sfd::kReduce | sfd::kRedSwap;
+      r4.uref = reinterpret_cast<const float2*>(u0);
+      r4.red_ld = h.nx;
+      r4.xp = fx.p0;
+      r4.xa = fx.a0;
+      r4.yp = fy.p0;
+      r4.ya = fy.a0;
+      r4.wc[0][2] = 1.0;
+    }
+    rows.push_back({L.lx, r4});
+    if (want_z) {
+      auto gset = [&](sfd::RowJob& j) {
+        j.red_ld = w.out.nx;
+        j.xp = fx.p1;
+        j.xa = fx.a1;
+        j.yp = fy.p1;
+        j.ya = fy.a1;
+        if (from_i) {
+          j.giref = static_cast<const float*>(grad_out[v]);
+          j.uref = static_cast<const float2*>(field_out[v]);
+        } else {
+          j.gref = static_cast<const float2*>(grad_out[v]);
+        }
+      };
+      // R1: u1 itself; S1 (weight 1) and S2 (weight x1^2 + y1^2).
+      sfd::RowJob r1 = row(B.wf, ldh, B.prexf, B.hxf, B.postxf, w.out.ny, h.nx, w.out.nx,
+                           sfd::kReduce | (from_i ? sfd::kRedIntensity : 0), B.p12);
+      gset(r1);
+      r1.wc[0][3] = 1.0;
+      r1.wc[1][2] = 1.0;
+      rows.push_back({L.lx, r1});
+      // R2: A(x0 u0); S3 (weight x1).
+      sfd::RowJob r2 = row(B.wf, ldh, B.prexm, B.hxf, B.postxf, w.out.ny, h.nx, w.out.nx, sfd::kReduce, B.p3);
+      gset(r2);
+      r2.wc[0][0] = 1.0;
+      rows.push_back({L.lx, r2});
+      // R3: A(y0 u0); S4 (weight y1).
+      sfd::RowJob r3 = row(B.wm, ldh, B.prexf, B.hxf, B.postxf, w.out.ny, h.nx, w.out.nx, sfd::kReduce, B.p4);
+      gset(r3);
+      r3.wc[0][1] = 1.0;
+      rows.push_back({L.lx, r3});
+    }
+  }
+  auto by_len = [](const std::pair<int, sfd::RowJob>& a, const std::pair<int, sfd::RowJob>& b) {
+    return a.first < b.first;
+  };
+  std::stable_sort(cols.begin(), cols.end(), by_len);
+  std::stable_sort(rows.begin(), rows.end(), by_len);
+  for (auto& c : cols) {
+    D.rows.push_back(c.second);
+    D.row_L.push_back(c.first);
+  }
+  D.n_pass_x = (int)cols.size();
+  for (auto& r : rows) {
+    D.rows.push_back(r.second);
+    D.row_L.push_back(r.first);
+  }
+
+  // z-derivative and gather jobs, and the gather source lists.
+  std::vector<sfd::GradZJob> gz;
+  if (want_z)
+    for (int v = 0; v < V; ++v) {
+      const sfd_plan_s::BwdLayout& B = P->blay[v];
+      sfd::GradZJob j{};
+      j.p12 = reinterpret_cast<const double*>(ws + B.p12);
+      j.p3 = reinterpret_cast<const double*>(ws + B.p3);
+      j.p4 = reinterpret_cast<const double*>(ws + B.p4);
+      j.p5 = reinterpret_cast<const double*>(ws + B.p5);
+      j.n12 = j.n3 = j.n4 = B.nt_r;
+      j.n5 = B.nt_a;
+      j.k = k;
+      j.z = z_or_null ? z_or_null[v] : P->views[v].z;
+      j.lam = P->lam;
+      j.out = grad_z + v;
+      gz.push_back(j);
+    }
+
+  // Image: axis | twiddles | tiles | rows | gradz | gather | gather sources.
+  std::vector<unsigned char> img;
+  size_t o_axis = 0, o_tw = align_up(sizeof(sfd::AxisJob) * 6 * V);
+  size_t o_tiles = o_tw + align_up(sizeof(sfd::TwiddleJob) * 2 * P->lengths.size());
+  size_t o_rows = o_tiles + align_up(sizeof(sfd::TileJob) * (P->tiles.size() + V));
+  size_t o_gz = o_rows + align_up(sizeof(sfd::RowJob) * 7 * V);
+  size_t o_ga = o_gz + align_up(sizeof(sfd::GradZJob) * V);
+  size_t o_src = o_ga + align_up(sizeof(sfd::GatherJob) * P->n_holo);
+  const size_t total = o_src + sizeof(void*) * V;
+  if (total > P->bwd_desc_bytes) return fail(SFD_ERR_INTERNAL, "backward descriptor area too small");
+  char* dbase = ws + P->bwd_desc_off;
+  std::vector<sfd::GatherJob> ga;
+  std::vector<const float2*> srcs;
+  for (int hh = 0; hh < P->n_holo; ++hh) {
+    if (P->holo_views[hh] == 1) continue;  // written directly by its view's adjoint pass
+    sfd::GatherJob j{};
+    j.src = reinterpret_cast<const float2* const*>(dbase + o_src) + srcs.size();
+    j.dst = reinterpret_cast<float2*>(static_cast<char*>(grad_in) + (size_t)hh * holo_stride);
+    j.n = h.nx * h.ny;
+    for (int v = 0; v < V; ++v)
+      if (P->views[v].holo == hh) srcs.push_back(reinterpret_cast<const float2*>(ws + P->blay[v].vbuf));
+    j.nsrc = (int)srcs.size() - (int)(j.src - reinterpret_cast<const float2* const*>(dbase + o_src));
+    ga.push_back(j);
+  }
+  img.assign(total, 0);
+  std::memcpy(img.data() + o_axis, D.axis.data(), sizeof(sfd::AxisJob) * D.axis.size());
+  std::memcpy(img.data() + o_tw, D.tw.data(), sizeof(sfd::TwiddleJob) * D.tw.size());
+  std::memcpy(img.data() + o_tiles, D.tiles.data(), sizeof(sfd::TileJob) * D.tiles.size());
+  std::memcpy(img.data() + o_rows, D.rows.data(), sizeof(sfd::RowJob) * D.rows.size());
+  if (!gz.empty()) std::memcpy(img.data() + o_gz, gz.data(), sizeof(sfd::GradZJob) * gz.size());
+  if (!ga.empty()) std::memcpy(img.data() + o_ga, ga.data(), sizeof(sfd::GatherJob) * ga.size());
+  if (!srcs.empty()) std::memcpy(img.data() + o_src, srcs.data(), sizeof(void*) * srcs.size());
+  sfd_status st = upload(P, 1, img, ws, P->bwd_desc_off, stream);
+  if (st != SFD_OK) return st;
+  const auto* d_axis = reinterpret_cast<const sfd::AxisJob*>(dbase + o_axis);
+  const auto* d_tw = reinterpret_cast<const sfd::TwiddleJob*>(dbase + o_tw);
+  const auto* d_tiles = reinterpret_cast<const sfd::TileJob*>(dbase + o_tiles);
+  const auto* d_rows = reinterpret_cast<const sfd::RowJob*>(dbase + o_rows);
+
+  if (P->tw_ready_ws != ws) {
+    if ((st = launch_setup_for(P, D, ws, d_axis, d_tw, d_tiles, 0, 0, true, 0, 0, stream)) != SFD_OK) return st;
+    P->tw_ready_ws = ws;
+  }
+  if ((st = launch_setup_for(P, D, ws, d_axis, d_tw, d_tiles, 0, (int)D.axis.size(), false, 0, (int)D.tiles.size(),
+                             stream, n_spec)) != SFD_OK)
+    return st;
+  (void)gtile0;
+  if ((st = launch_rows(D, d_rows, 0, D.n_pass_x, P, ws, stream, SFD_KERNEL_PASS_Y)) != SFD_OK) return st;
+  if ((st = launch_rows(D, d_rows, D.n_pass_x, (int)D.rows.size() - D.n_pass_x, P, ws, stream,
+                        SFD_KERNEL_PASS_X)) != SFD_OK)
+    return st;
+  if (want_z)
+    SFD_TIMED(P, SFD_KERNEL_OTHER, stream,
+              sfd::launch_gradz(reinterpret_cast<const sfd::GradZJob*>(dbase + o_gz), V, stream));
+  if (!ga.empty())
+    SFD_TIMED(P, SFD_KERNEL_OTHER, stream,
+              sfd::launch_gather(reinterpret_cast<const sfd::GatherJob*>(dbase + o_ga), (int)ga.size(),
+                                 h.nx * h.ny, stream));
   return SFD_OK;
 }
 
@@ -607,6 +956,56 @@ sfd_status sfd_plan(sfd_plan_t* plan, double wavelength, const sfd_grid* holo_gr
     L.hy = take(sizeof(float2) * L.ly);
     L.inter = take(sizeof(float2) * (size_t)o.ny * inter_ld(h.nx));  // N1y x N0x after the y transforms
   }
+  if (flags & SFD_IN_C64) {
+    // Backward: per view its own forward, moment and adjoint tables, the
+    // gradient's column tiles, three intermediates, an adjoint buffer when
+    // the hologram has several views, and the reduction partials.
+    auto take = [&](size_t bytes) {
+      const size_t at = off;
+      off += align_up(bytes);
+      return at;
+    };
+    P->holo_views.assign(n_holo, 0);
+    for (int v = 0; v < n_views; ++v) P->holo_views[views[v].holo]++;
+    P->bwd_desc_off = off;
+    P->bwd_desc_bytes = bwd_desc_capacity(n_views, n_holo, (int)ls.size(), (int)P->tiles.size());
+    off += P->bwd_desc_bytes;
+    P->blay.resize(n_views);
+    const size_t c8 = sizeof(float2);
+    for (int v = 0; v < n_views; ++v) {
+      sfd_plan_s::BwdLayout& B = P->blay[v];
+      const sfd_grid& o = views[v].out;
+      const int lx = P->lay[v].lx, ly = P->lay[v].ly;
+      B.prexf = take(c8 * h.nx);
+      B.preyf = take(c8 * h.ny);
+      B.postxf = take(c8 * o.nx);
+      B.postyf = take(c8 * o.ny);
+      B.prexm = take(c8 * h.nx);
+      B.preym = take(c8 * h.ny);
+      B.prexa = take(c8 * o.nx);
+      B.preya = take(c8 * o.ny);
+      B.postxa = take(c8 * h.nx);
+      B.postya = take(c8 * h.ny);
+      B.hxf = take(c8 * lx);
+      B.hyf = take(c8 * ly);
+      B.hxa = take(c8 * lx);
+      B.hya = take(c8 * ly);
+      B.ga = sfd::rows_per_tile(ly, true);
+      B.gtile_stride = (o.ny * B.ga + 63) / 64 * 64 + 64;
+      B.gtile = take(c8 * (size_t)((o.nx + B.ga - 1) / B.ga) * B.gtile_stride);
+      B.wf = take(c8 * (size_t)o.ny * inter_ld(h.nx));
+      B.wm = take(c8 * (size_t)o.ny * inter_ld(h.nx));
+      B.wa = take(c8 * (size_t)h.ny * inter_ld(o.nx));
+      B.vbuf = P->holo_views[views[v].holo] > 1 ? take(c8 * (size_t)h.nx * h.ny) : 0;
+      const int gr = sfd::rows_per_tile(lx, false);
+      B.nt_r = (o.ny + gr - 1) / gr;
+      B.nt_a = (h.ny + gr - 1) / gr;
+      B.p12 = take(4 * sizeof(double) * B.nt_r);
+      B.p3 = take(4 * sizeof(double) * B.nt_r);
+      B.p4 = take(4 * sizeof(double) * B.nt_r);
+      B.p5 = take(4 * sizeof(double) * B.nt_a);
+    }
+  }
   P->ws_bytes = off;
   *plan = P;
   return SFD_OK;
@@ -651,7 +1050,7 @@ sfd_status sfd_reconstruct(sfd_plan_t plan, const void* holo, const double* z_or
   std::vector<unsigned char> img;
   size_t off_axis, off_tw, off_rows;
   pack_descs(plan, D, &img, &off_axis, &off_tw, &off_rows);
-  if ((st = upload(plan, img, ws, stream)) != SFD_OK) return st;
+  if ((st = upload(plan, 0, img, ws, plan->desc_off, stream)) != SFD_OK) return st;
   const auto* d_axis = reinterpret_cast<const sfd::AxisJob*>(ws + plan->desc_off + off_axis);
   const auto* d_tw = reinterpret_cast<const sfd::TwiddleJob*>(ws + plan->desc_off + off_tw);
   const auto* d_rows = reinterpret_cast<const sfd::RowJob*>(ws + plan->desc_off + off_rows);
@@ -709,8 +1108,8 @@ sfd_status sfd_backward(sfd_plan_t plan, void* const* grad_out, void* const* fie
       return fail(SFD_ERR_INVALID_ARG, "field_out[" + std::to_string(v) + "] must be non-NULL and 16-byte aligned");
   }
   if ((st = check_z(plan, z_or_null)) != SFD_OK) return st;
-  (void)stream;
-  return fail(SFD_ERR_UNSUPPORTED, "sfd_backward is not available in this build");
+  return run_backward(plan, grad_out, field_out, holo, z_or_null, grad_in, grad_z, static_cast<char*>(workspace),
+                      stream);
 }
 
 sfd_status sfd_profile_enable(sfd_plan_t plan, int32_t enable) {

@@ -55,11 +55,34 @@ struct RowJob {
   float iscale;        // intensity scale
   int32_t n_rows, n_in, n_out;
   int64_t in_ld, out_ld;
-  int32_t mode;        // kInReal | kOutIntensity | kOutField | kUsePost
+  int32_t mode;        // kInReal | kOutIntensity | kOutField | kUsePost | kReduce ...
   int32_t pad_;
+
+  // Epilogue reductions (row kernel, kReduce): over the row's outputs V(m),
+  //   acc_k += conj(G) * w_k * V,  w_k = wc[k][0] X + wc[k][1] Y + wc[k][2] (X^2 + Y^2) + wc[k][3],
+  // X = m xp + xa, Y = row yp + ya (coordinates of the output grid), with
+  // G = gref[row][m] or, when giref is set, G = 2 giref[row][m] uref[row][m]
+  // (kRedIntensity: G = 2 giref V, so conj(G) V = 2 giref |V|^2 exactly).
+  // kRedSwap instead takes G = V and V = uref[row][m].  Each tile writes its
+  // two complex FP64 sums to partial[tile * 4 .. + 4].
+  const float2* gref;
+  const float* giref;
+  const float2* uref;
+  double* partial;
+  int64_t red_ld;
+  double xp, xa, yp, ya;
+  double wc[2][4];
 };
 
-enum : int32_t { kInReal = 1, kOutIntensity = 2, kUsePost = 4, kOutField = 16 };
+enum : int32_t {
+  kInReal = 1,
+  kOutIntensity = 2,
+  kUsePost = 4,
+  kOutField = 16,
+  kReduce = 32,
+  kRedSwap = 64,
+  kRedIntensity = 128,
+};
 
 constexpr int kMaxJobsPerLaunch = 256;
 
@@ -83,12 +106,36 @@ struct TwiddleJob {
 // tile_stride elements apart.  The column pass then reads each workgroup's
 // G columns as one contiguous block.
 struct TileJob {
-  const void* in;  // [ny][nx] float32 or complex64
+  const void* in;   // [ny][nx] float32 or complex64
+  const float* in2; // complex input only: if set, the tile holds 2 in2 * in (a gradient
+                    // with respect to the field formed from dL/dI and the field)
   void* out;
   int32_t nx, ny, G;
   int32_t tile_stride;  // elements
   int32_t complex_in;
   int32_t pad_;
+};
+
+// z-derivative of one view from the reduction partials (see sfd_backward):
+//   dL/dz = Re[(i k - 1/z) S1 - (i pi / (lambda z^2)) (S2 - 2 S3 - 2 S4 + S5)]
+// with S1, S2 from the first accumulators of p12 (acc 0 and 1), S3, S4, S5
+// from acc 0 of p3, p4, p5.
+struct GradZJob {
+  const double* p12;
+  const double* p3;
+  const double* p4;
+  const double* p5;
+  int32_t n12, n3, n4, n5;  // tiles
+  double k, z, lam;
+  double* out;
+};
+
+// Sum of per-view adjoint results into a hologram's gradient.
+struct GatherJob {
+  const float2* const* src;  // device array of nsrc pointers
+  float2* dst;
+  int32_t nsrc;
+  int32_t n;
 };
 
 // One launch builds everything a batch needs before the passes.  Workgroups
@@ -123,6 +170,9 @@ int spectra_per_block(int L);
 
 // col = true: the y transforms (column kernel); false: the x transforms.
 hipError_t launch_pass(int L, bool col, const PassArgs& args, const float2* tw, hipStream_t s);
+
+hipError_t launch_gradz(const GradZJob* d_jobs, int njobs, hipStream_t s);
+hipError_t launch_gather(const GatherJob* d_jobs, int njobs, int max_n, hipStream_t s);
 
 // Transforms per workgroup (the tile) of a pass at a transform length.
 int rows_per_tile(int L, bool col);

@@ -187,7 +187,15 @@ __device__ __forceinline__ void tile_block(const TileJob& J, int r0, int c0, T* 
   for (int rr = 0; rr < RB; ++rr) {
     const int n = r0 + rr, c = c0 + tid;
     T v{};
-    if (n < J.ny && c < J.nx) v = gld(in, (unsigned)(n * J.nx + c));
+    if (n < J.ny && c < J.nx) {
+      v = gld(in, (unsigned)(n * J.nx + c));
+      if constexpr (sizeof(T) == 8) {
+        if (J.in2) {
+          const float a = 2.0f * gld(J.in2, (unsigned)(n * J.nx + c));
+          v = make_float2(a * v.x, a * v.y);
+        }
+      }
+    }
     buf[rr * SP + tid] = v;
   }
   __syncthreads();
@@ -345,6 +353,78 @@ __device__ __forceinline__ void load_row(float2 (&v)[R], const void* in, const f
   }
 }
 
+// Epilogue reduction of the row kernel (see RowJob): FP64 per thread, then
+// across the wavefront and the workgroup in a fixed order, one complex pair
+// per tile into J.partial.
+template <int TPR, int R, int NW>
+__device__ __forceinline__ void row_reduce(const RowJob& J, const float2 (&v)[R], int row, bool valid, int t, int tile,
+                                           double* sbuf) {
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  if (valid) {
+    const int n_out = J.n_out;
+    const int mode = J.mode;
+    const double Y = row * J.yp + J.ya;
+    const int64_t base = (int64_t)row * J.red_ld;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int m = t + TPR * i;
+      if (m < n_out) {
+        float2 G, V;
+        if (mode & kRedSwap) {
+          G = v[i];
+          V = gld(J.uref + base, (unsigned)m);
+        } else if (mode & kRedIntensity) {
+          const float gi = 2.0f * gld(J.giref + base, (unsigned)m);
+          G = make_float2(gi * v[i].x, gi * v[i].y);
+          V = v[i];
+        } else if (J.giref) {
+          const float gi = 2.0f * gld(J.giref + base, (unsigned)m);
+          const float2 u = gld(J.uref + base, (unsigned)m);
+          G = make_float2(gi * u.x, gi * u.y);
+          V = v[i];
+        } else {
+          G = gld(J.gref + base, (unsigned)m);
+          V = v[i];
+        }
+        double pr, pi;
+        if (mode & kRedIntensity) {
+          // conj(2 gi V) V = 2 gi |V|^2: real by construction.
+          pr = (double)G.x * V.x + (double)G.y * V.y;
+          pi = 0.0;
+        } else {
+          pr = (double)G.x * V.x + (double)G.y * V.y;
+          pi = (double)G.x * V.y - (double)G.y * V.x;
+        }
+        const double X = m * J.xp + J.xa;
+        const double r2 = X * X + Y * Y;
+        const double w0 = J.wc[0][0] * X + J.wc[0][1] * Y + J.wc[0][2] * r2 + J.wc[0][3];
+        const double w1 = J.wc[1][0] * X + J.wc[1][1] * Y + J.wc[1][2] * r2 + J.wc[1][3];
+        a[0] += w0 * pr;
+        a[1] += w0 * pi;
+        a[2] += w1 * pr;
+        a[3] += w1 * pi;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) a[k] += __shfl_xor(a[k], off, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sbuf[wave * 4 + k] = a[k];
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) s += sbuf[w * 4 + threadIdx.x];
+    gst(J.partial, (unsigned)(tile * 4 + threadIdx.x), s);
+  }
+}
+
 // x transforms: row r of the job reads in + r * in_ld and writes
 // out + r * out_ld (contiguous), both straight from registers.
 template <int L>
@@ -353,7 +433,8 @@ __global__ void __launch_bounds__(RowCfg<L>::NW * 64) __attribute__((amdgpu_wave
   constexpr int R = L / TPR;
   constexpr int G = RowCfg<L>::G;
   constexpr int RB = row_lds_bytes<L, kSplit>();
-  __shared__ __align__(16) unsigned char lds[G * RB];
+  // Exchange buffers, then room for the epilogue reduction (4 doubles per wavefront).
+  __shared__ __align__(16) unsigned char lds[G * RB + RowCfg<L>::NW * 32];
 
   const int tile = xcd_tile(blockIdx.x, args.total_tiles);
   const int jid = find_job(args, tile);
@@ -376,14 +457,15 @@ __global__ void __launch_bounds__(RowCfg<L>::NW * 64) __attribute__((amdgpu_wave
   void* buf = lds + g * RB;
   fft_row<PassPlan<L>, false, kSplit>(v, buf, t, tw);
   const float2* __restrict__ H = J.H;
+  sched_fence();
 #pragma unroll
   for (int i = 0; i < R; ++i) {
     v[i] = cmul(v[i], gld(H, (unsigned)(t + TPR * i)));
     if ((i & 7) == 7) sched_fence();
   }
+  sched_fence();
   fft_row<PassPlan<L>, true, kSplit>(v, buf, t, tw);
 
-  if (!valid) return;
   const int n_out = J.n_out;
   const int mode = J.mode;
   if (mode & kUsePost) {
@@ -394,7 +476,7 @@ __global__ void __launch_bounds__(RowCfg<L>::NW * 64) __attribute__((amdgpu_wave
       if (TPR * (i + 1) <= n_out || m < n_out) v[i] = cmul(v[i], gld(post, (unsigned)m));
     }
   }
-  if (mode & kOutField) {
+  if (valid && (mode & kOutField)) {
     float2* out = static_cast<float2*>(J.out) + (int64_t)row * J.out_ld;
 #pragma unroll
     for (int i = 0; i < R; ++i) {
@@ -402,7 +484,7 @@ __global__ void __launch_bounds__(RowCfg<L>::NW * 64) __attribute__((amdgpu_wave
       if (TPR * (i + 1) <= n_out || m < n_out) gst(out, (unsigned)m, v[i]);
     }
   }
-  if (mode & kOutIntensity) {
+  if (valid && (mode & kOutIntensity)) {
     float* out = ((mode & kOutField) ? J.out2 : static_cast<float*>(J.out)) + (int64_t)row * J.out_ld;
     const float sc = J.iscale;
 #pragma unroll
@@ -411,6 +493,8 @@ __global__ void __launch_bounds__(RowCfg<L>::NW * 64) __attribute__((amdgpu_wave
       if (TPR * (i + 1) <= n_out || m < n_out) gst(out, (unsigned)m, (v[i].x * v[i].x + v[i].y * v[i].y) * sc);
     }
   }
+  if (mode & kReduce) row_reduce<TPR, R, RowCfg<L>::NW>(J, v, row, valid, t, tile - args.tile_prefix[jid],
+                                                         reinterpret_cast<double*>(lds + G * RB));
 }
 
 // y transforms: column c of the job reads in[n * in_ld + c] for n < n_in and
@@ -497,11 +581,13 @@ __global__ void __launch_bounds__(ColCfg<L>::NW * 64) __attribute__((amdgpu_wave
   void* buf = lds + g * RB;
   fft_row<PassPlan<L>, false, kSplit>(v, buf, t, tw);
   const float2* __restrict__ H = J.H;
+  sched_fence();
 #pragma unroll
   for (int i = 0; i < R; ++i) {
     v[i] = cmul(v[i], gld(H, (unsigned)(t + TPR * i)));
     if ((i & 7) == 7) sched_fence();
   }
+  sched_fence();
   fft_row<PassPlan<L>, true, kSplit>(v, buf, t, tw);
 
   const int n_out = J.n_out;
@@ -548,6 +634,70 @@ int rows_per_tile(int L, bool col) {
     case 8192: return col ? ColCfg<8192>::G : RowCfg<8192>::G;
     default: return 0;
   }
+}
+
+// Sum of a tile-partial array (acc index k) in a fixed order.
+__device__ __forceinline__ void sum_partials(const double* p, int n, int k, double* re, double* im, double* sh) {
+  double r = 0.0, i = 0.0;
+  for (int t = threadIdx.x; t < n; t += 256) {
+    r += p[t * 4 + 2 * k];
+    i += p[t * 4 + 2 * k + 1];
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    r += __shfl_xor(r, off, 64);
+    i += __shfl_xor(i, off, 64);
+  }
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    sh[(threadIdx.x >> 6) * 2] = r;
+    sh[(threadIdx.x >> 6) * 2 + 1] = i;
+  }
+  __syncthreads();
+  *re = sh[0] + sh[2] + sh[4] + sh[6];
+  *im = sh[1] + sh[3] + sh[5] + sh[7];
+}
+
+__global__ void __launch_bounds__(256) gradz_kernel(const GradZJob* __restrict__ jobs) {
+  __shared__ double sh[8];
+  const GradZJob& J = jobs[blockIdx.x];
+  double s1r, s1i, s2r, s2i, s3r, s3i, s4r, s4i, s5r, s5i;
+  sum_partials(J.p12, J.n12, 0, &s1r, &s1i, sh);
+  sum_partials(J.p12, J.n12, 1, &s2r, &s2i, sh);
+  sum_partials(J.p3, J.n3, 0, &s3r, &s3i, sh);
+  sum_partials(J.p4, J.n4, 0, &s4r, &s4i, sh);
+  sum_partials(J.p5, J.n5, 0, &s5r, &s5i, sh);
+  if (threadIdx.x == 0) {
+    // Re[(i k - 1/z) S1] = -k Im S1 - Re S1 / z;  Re[-i a X] = a Im X.
+    const double xi = s2i - 2.0 * s3i - 2.0 * s4i + s5i;
+    const double a = M_PI / (J.lam * J.z * J.z);
+    *J.out = -J.k * s1i - s1r / J.z + a * xi;
+  }
+}
+
+// grid: x covers the largest gradient, y = jobs.
+__global__ void __launch_bounds__(256) gather_kernel(const GatherJob* __restrict__ jobs) {
+  const GatherJob& J = jobs[blockIdx.y];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= J.n) return;
+  float2 acc = make_float2(0.f, 0.f);
+  for (int k = 0; k < J.nsrc; ++k) {
+    const float2 x = gld(J.src[k], (unsigned)i);
+    acc = cadd(acc, x);
+  }
+  gst(J.dst, (unsigned)i, acc);
+}
+
+hipError_t launch_gradz(const GradZJob* d_jobs, int njobs, hipStream_t s) {
+  if (njobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gradz_kernel, dim3(njobs), dim3(256), 0, s, d_jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const GatherJob* d_jobs, int njobs, int max_n, hipStream_t s) {
+  if (njobs <= 0 || max_n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_kernel, dim3((max_n + 255) / 256, njobs), dim3(256), 0, s, d_jobs);
+  return hipGetLastError();
 }
 
 hipError_t launch_setup(const SetupArgs& a, hipStream_t s) {
