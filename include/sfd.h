@@ -82,7 +82,9 @@ enum {
   SFD_OUT_INTENSITY = 1u << 2, /* outputs are float32 I = |u1|^2 (Eq. 5) */
   SFD_OUT_FIELD = 1u << 3,     /* outputs are the complex64 field u1 (Eq. 1 with C1) */
   SFD_PHASE_FP32 = 1u << 4,    /* evaluate chirp phases in FP32 instead of FP64 (comparison only) */
-  SFD_PER_VIEW_LAUNCH = 1u << 5 /* launch the kernels one view at a time (baseline for batching) */
+  SFD_PER_VIEW_LAUNCH = 1u << 5, /* launch the kernels one view at a time (baseline for batching) */
+  SFD_EAGER = 1u << 6            /* batched calls launch their kernels directly instead of replaying
+                                    the plan's HIP graph */
 };
 
 /*
@@ -95,7 +97,8 @@ enum {
  *   holo_grid  grid shared by all holograms (shifts allowed)
  *   n_holo     >= 1
  *   views      host array of n_views >= 1 views (copied; the caller keeps ownership)
- *   flags      SFD_IN_* | SFD_OUT_* | optional SFD_PHASE_FP32, SFD_PER_VIEW_LAUNCH
+ *   flags      SFD_IN_* | SFD_OUT_* | optional SFD_PHASE_FP32, SFD_PER_VIEW_LAUNCH,
+ *              SFD_EAGER
  * Errors: SFD_ERR_INVALID_ARG for non-finite or non-positive lambda or
  * pitches, z == 0 or non-finite, sizes < 1, holo index out of range, missing
  * or conflicting flags; SFD_ERR_UNSUPPORTED when a padded length would exceed
@@ -128,6 +131,13 @@ sfd_status sfd_view_lengths(sfd_plan_t plan, int32_t v, int32_t* lx, int32_t* ly
  *   workspace   device, >= sfd_workspace_size bytes, 256-byte aligned
  *   ws_bytes    size of workspace in bytes
  *   stream      HIP stream the work is enqueued on (0 = null stream)
+ * Batched plans (no SFD_PER_VIEW_LAUNCH, no SFD_EAGER) record their kernel
+ * sequence once per workspace into a HIP graph owned by the plan and replay
+ * it on every later call; the kernels read the call's pointers and distances
+ * from descriptors that each call copies into the workspace first (on
+ * ``stream``, only when they changed), so one graph serves every call.  When
+ * ``stream`` is being captured by the caller, or kernel timing is on, the
+ * kernels are launched directly instead.
  */
 sfd_status sfd_reconstruct(sfd_plan_t plan, const void* holo, const double* z_or_null,
                            void* const* out, void* workspace, size_t ws_bytes,

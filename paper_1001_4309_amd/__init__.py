@@ -21,7 +21,7 @@ from typing import Optional, Sequence
 import torch
 
 from . import _lib
-from ._lib import (SFD_IN_C64, SFD_IN_REAL_F32, SFD_OUT_FIELD, SFD_OUT_INTENSITY,  # noqa: F401
+from ._lib import (SFD_EAGER, SFD_IN_C64, SFD_IN_REAL_F32, SFD_OUT_FIELD, SFD_OUT_INTENSITY,  # noqa: F401
                    SFD_PER_VIEW_LAUNCH, SFD_PHASE_FP32, SfdError, SfdGrid, SfdView)
 
 __all__ = ["Plan", "SFDFunction", "sfd_plan", "sfd_workspace_size", "sfd_view_lengths", "sfd_reconstruct",
@@ -130,7 +130,7 @@ class Plan:
 
     def __init__(self, wavelength: float, holo_grid, n_holo: int, views: Sequence, *,
                  outputs: str = "intensity", complex_input: bool = False, phase_fp32: bool = False,
-                 per_view_launch: bool = False, device=None):
+                 per_view_launch: bool = False, eager: bool = False, device=None):
         if outputs not in ("intensity", "field", "both"):
             raise ValueError("outputs must be 'intensity', 'field' or 'both'")
         self.device = torch.device(device if device is not None else "cuda")
@@ -147,6 +147,8 @@ class Plan:
             flags |= SFD_PHASE_FP32
         if per_view_launch:
             flags |= SFD_PER_VIEW_LAUNCH
+        if eager:
+            flags |= SFD_EAGER
         self.flags = flags
         self.handle = None
         self.handle = sfd_plan(wavelength, holo_grid, n_holo, self.views, flags)

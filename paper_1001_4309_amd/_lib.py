@@ -23,6 +23,7 @@ SFD_OUT_INTENSITY = 1 << 2
 SFD_OUT_FIELD = 1 << 3
 SFD_PHASE_FP32 = 1 << 4
 SFD_PER_VIEW_LAUNCH = 1 << 5
+SFD_EAGER = 1 << 6
 
 EXPORTED = ["sfd_plan", "sfd_workspace_size", "sfd_view_lengths", "sfd_reconstruct",
             "sfd_backward", "sfd_profile_enable", "sfd_profile_report", "sfd_destroy", "sfd_last_error"]
@@ -32,6 +33,7 @@ SFD_KERNEL_SPECTRA = 1
 SFD_KERNEL_PASS_X = 2
 SFD_KERNEL_PASS_Y = 3
 SFD_KERNEL_OTHER = 4
+SFD_KERNEL_KINDS = 5
 KERNEL_KIND_NAMES = {0: "tables", 1: "spectra", 2: "pass_x", 3: "pass_y", 4: "other"}
 
 

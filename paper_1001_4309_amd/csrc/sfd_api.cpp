@@ -154,7 +154,23 @@ struct sfd_plan_s {
   std::vector<Rec> recs;
   std::vector<hipEvent_t> event_pool;
 
+  // Recorded forward launch sequence (batched plans): valid for graph_ws.
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  void* graph_ws = nullptr;
+
+  void drop_graph() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+    graph_ws = nullptr;
+  }
+
   ~sfd_plan_s() {
+    drop_graph();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (auto& r : recs) {
       (void)hipEventDestroy(r.a);
       (void)hipEventDestroy(r.b);
@@ -433,6 +449,7 @@ sfd_status launch_setup_for(sfd_plan_s* P, const CallDescs& D, char* ws, const s
     SFD_TIMED(P, SFD_KERNEL_TABLES, stream, sfd::launch_setup(A, stream));
     A.nroles = 0;
     A.total_blocks = 0;
+    A.max_l = 0;
     return SFD_OK;
   };
   auto add = [&](sfd::SetupRole r) -> sfd_status {
@@ -442,6 +459,7 @@ sfd_status launch_setup_for(sfd_plan_s* P, const CallDescs& D, char* ws, const s
       if (st != SFD_OK) return st;
     }
     r.first_block = A.total_blocks;
+    if (r.kind == sfd::kRoleSpectrum) A.max_l = std::max(A.max_l, r.a);
     A.roles[A.nroles++] = r;
     A.total_blocks += r.nblocks;
     return SFD_OK;
@@ -501,6 +519,19 @@ sfd_status launch_rows(const CallDescs& D, const sfd::RowJob* d_rows, int first,
     i = j;
   }
   return SFD_OK;
+}
+
+// The batched forward sequence: every view's tables, spectra and hologram
+// tiles, then all column passes, then all row passes.
+sfd_status launch_forward(sfd_plan_s* P, const CallDescs& D, char* ws, const sfd::AxisJob* d_axis,
+                          const sfd::TwiddleJob* d_tw, const sfd::TileJob* d_tiles, const sfd::RowJob* d_rows,
+                          hipStream_t stream) {
+  sfd_status st;
+  if ((st = launch_setup_for(P, D, ws, d_axis, d_tw, d_tiles, 0, (int)D.axis.size(), false, 0, (int)D.tiles.size(),
+                             stream)) != SFD_OK)
+    return st;
+  if ((st = launch_rows(D, d_rows, 0, D.n_pass_x, P, ws, stream, SFD_KERNEL_PASS_Y)) != SFD_OK) return st;
+  return launch_rows(D, d_rows, D.n_pass_x, (int)D.rows.size() - D.n_pass_x, P, ws, stream, SFD_KERNEL_PASS_X);
 }
 
 sfd_status check_common(sfd_plan_t plan, void* workspace, size_t ws_bytes) {
@@ -865,7 +896,7 @@ sfd_status sfd_plan(sfd_plan_t* plan, double wavelength, const sfd_grid* holo_gr
   if (n_views < 1) return fail(SFD_ERR_INVALID_ARG, "n_views must be >= 1");
   if (n_views > 65536) return fail(SFD_ERR_UNSUPPORTED, "at most 65536 views per plan");
   const uint32_t known = SFD_IN_REAL_F32 | SFD_IN_C64 | SFD_OUT_INTENSITY | SFD_OUT_FIELD | SFD_PHASE_FP32 |
-                         SFD_PER_VIEW_LAUNCH;
+                         SFD_PER_VIEW_LAUNCH | SFD_EAGER;
   if (flags & ~known) return fail(SFD_ERR_INVALID_ARG, "unknown flag bits");
   if (((flags & SFD_IN_REAL_F32) != 0) == ((flags & SFD_IN_C64) != 0))
     return fail(SFD_ERR_INVALID_ARG, "exactly one of SFD_IN_REAL_F32 and SFD_IN_C64 must be set");
@@ -1076,14 +1107,33 @@ sfd_status sfd_reconstruct(sfd_plan_t plan, const void* holo, const double* z_or
     }
     return SFD_OK;
   }
-  if ((st = launch_setup_for(plan, D, ws, d_axis, d_tw, d_tiles, 0, (int)D.axis.size(), false, 0,
-                             (int)D.tiles.size(), stream)) != SFD_OK)
-    return st;
-  if ((st = launch_rows(D, d_rows, 0, D.n_pass_x, plan, ws, stream, SFD_KERNEL_PASS_Y)) != SFD_OK) return st;
-  if ((st = launch_rows(D, d_rows, D.n_pass_x, (int)D.rows.size() - D.n_pass_x, plan, ws, stream,
-                        SFD_KERNEL_PASS_X)) != SFD_OK)
-    return st;
-  return SFD_OK;
+  const bool use_graph = !(plan->flags & SFD_EAGER) && !plan->profiling;
+  if (use_graph) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    SFD_HIP_TRY(hipStreamIsCapturing(stream, &cs));
+    if (cs == hipStreamCaptureStatusNone) {
+      if (plan->graph_ws != ws) {
+        // Record on a private stream: the caller's stream is never put in
+        // capture mode.
+        plan->drop_graph();
+        if (!plan->cap_stream) SFD_HIP_TRY(hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking));
+        SFD_HIP_TRY(hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal));
+        st = launch_forward(plan, D, ws, d_axis, d_tw, d_tiles, d_rows, plan->cap_stream);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(plan->cap_stream, &g);
+        if (st != SFD_OK || e != hipSuccess) {
+          if (g) (void)hipGraphDestroy(g);
+          return st != SFD_OK ? st : fail(SFD_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+        }
+        plan->graph = g;
+        SFD_HIP_TRY(hipGraphInstantiate(&plan->gexec, g, nullptr, nullptr, 0));
+        plan->graph_ws = ws;
+      }
+      SFD_HIP_TRY(hipGraphLaunch(plan->gexec, stream));
+      return SFD_OK;
+    }
+  }
+  return launch_forward(plan, D, ws, d_axis, d_tw, d_tiles, d_rows, stream);
 }
 
 sfd_status sfd_backward(sfd_plan_t plan, void* const* grad_out, void* const* field_out, const void* holo,

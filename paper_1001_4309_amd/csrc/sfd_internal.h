@@ -157,6 +157,7 @@ struct SetupArgs {
   const TileJob* tiles;
   int32_t nroles;
   int32_t total_blocks;
+  int32_t max_l;  // longest spectrum of the launch (0 if none)
   SetupRole roles[kMaxSetupRoles];
 };
 constexpr int kSetupThreads = 256;

@@ -218,15 +218,26 @@ constexpr int spectrum_lds_bytes() {
   return SpecShape<L>::BYTES;
 }
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
-constexpr int kSetupLds =
-    cmax(cmax(cmax(spectrum_lds_bytes<64>(), spectrum_lds_bytes<128>()),
-              cmax(spectrum_lds_bytes<256>(), spectrum_lds_bytes<512>())),
-         cmax(cmax(cmax(spectrum_lds_bytes<1024>(), spectrum_lds_bytes<2048>()),
-                   cmax(spectrum_lds_bytes<4096>(), spectrum_lds_bytes<8192>())),
-              kTileRows * (kTileCols + 1) * 8));
+// LDS of a setup launch whose spectra have lengths <= MAXL.
+template <int MAXL>
+constexpr int setup_lds_bytes() {
+  int b = kTileRows * (kTileCols + 1) * 8;
+  if (MAXL >= 64) b = cmax(b, spectrum_lds_bytes<64>());
+  if (MAXL >= 128) b = cmax(b, spectrum_lds_bytes<128>());
+  if (MAXL >= 256) b = cmax(b, spectrum_lds_bytes<256>());
+  if (MAXL >= 512) b = cmax(b, spectrum_lds_bytes<512>());
+  if (MAXL >= 1024) b = cmax(b, spectrum_lds_bytes<1024>());
+  if (MAXL >= 2048) b = cmax(b, spectrum_lds_bytes<2048>());
+  if (MAXL >= 4096) b = cmax(b, spectrum_lds_bytes<4096>());
+  if (MAXL >= 8192) b = cmax(b, spectrum_lds_bytes<8192>());
+  return b;
+}
 
+// One kernel for all setup roles; MAXL bounds the spectrum lengths of the
+// launch so that LDS (and with it occupancy) follows the plan's lengths.
+template <int MAXL>
 __global__ void __launch_bounds__(kSetupThreads) setup_kernel(const SetupArgs A) {
-  __shared__ __align__(16) unsigned char lds[kSetupLds];
+  __shared__ __align__(16) unsigned char lds[setup_lds_bytes<MAXL>()];
   int r = 0;
   while (r + 1 < A.nroles && (int)blockIdx.x >= A.roles[r + 1].first_block) ++r;
   const SetupRole& Ro = A.roles[r];
@@ -240,8 +251,12 @@ __global__ void __launch_bounds__(kSetupThreads) setup_kernel(const SetupArgs A)
         case 512: setup_spectrum<512>(A, Ro, rb, lds); break;
         case 1024: setup_spectrum<1024>(A, Ro, rb, lds); break;
         case 2048: setup_spectrum<2048>(A, Ro, rb, lds); break;
-        case 4096: setup_spectrum<4096>(A, Ro, rb, lds); break;
-        case 8192: setup_spectrum<8192>(A, Ro, rb, lds); break;
+        case 4096:
+          if constexpr (MAXL >= 4096) setup_spectrum<4096>(A, Ro, rb, lds);
+          break;
+        case 8192:
+          if constexpr (MAXL >= 8192) setup_spectrum<8192>(A, Ro, rb, lds);
+          break;
         default: break;
       }
       break;
@@ -702,7 +717,11 @@ hipError_t launch_gather(const GatherJob* d_jobs, int njobs, int max_n, hipStrea
 
 hipError_t launch_setup(const SetupArgs& a, hipStream_t s) {
   if (a.total_blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(setup_kernel, dim3(a.total_blocks), dim3(kSetupThreads), 0, s, a);
+  if (a.max_l > 8192) return hipErrorInvalidValue;
+  if (a.max_l <= 2048)
+    hipLaunchKernelGGL(setup_kernel<2048>, dim3(a.total_blocks), dim3(kSetupThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL(setup_kernel<8192>, dim3(a.total_blocks), dim3(kSetupThreads), 0, s, a);
   return hipGetLastError();
 }
 

@@ -32,6 +32,18 @@ def test_header_declares_the_boundary():
         assert n in names
 
 
+def test_binding_flag_values_match_the_header():
+    text = open(HEADER).read()
+    flags = dict(re.findall(r"^\s*(SFD_[A-Z0-9_]+)\s*=\s*1u\s*<<\s*(\d+)", text, re.M))
+    assert {"SFD_IN_REAL_F32", "SFD_IN_C64", "SFD_OUT_INTENSITY", "SFD_OUT_FIELD", "SFD_PHASE_FP32",
+            "SFD_PER_VIEW_LAUNCH", "SFD_EAGER"} <= set(flags)
+    for name, shift in flags.items():
+        assert getattr(lib_mod, name) == 1 << int(shift), name
+    kinds = dict(re.findall(r"^\s*(SFD_KERNEL_[A-Z_]+)\s*=\s*(\d+)", text, re.M))
+    for name, value in kinds.items():
+        assert getattr(lib_mod, name) == int(value), name
+
+
 def test_library_exports_every_declared_symbol(lib):
     for n in declared_functions():
         assert hasattr(lib, n), f"{n} declared in include/sfd.h but not exported"
