@@ -105,6 +105,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-view", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default tile widths")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (calibrates traffic counters)")
     args = ap.parse_args()
@@ -138,6 +139,10 @@ def main():
     plan = sfd.Plan(w.wavelength, w.holo_grid, len(w.holograms), w.views, device=dev)
     outs = plan.new_outputs()
     nv = len(w.views)
+    if not args.no_autotune:
+        plan.autotune(holo, reps=10, outs=outs)
+    schedule = {f"{k[0]}{k[1]}": g for k, g in sorted(plan.schedule().items())}
+    log("schedule (tile widths):", schedule)
 
     for _ in range(args.warmup):
         plan.reconstruct(holo, outs=outs)
@@ -204,7 +209,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "holograms": len(w.holograms), "views_per_step": nv,
                    "hologram": [g.ny, g.nx], "views": [[v.grid.ny, v.grid.nx] for v in w.views],
-                   "padded_length": [lx, ly], "phase": "fp64-reduced", "output": "intensity"},
+                   "padded_length": [lx, ly], "phase": "fp64-reduced", "output": "intensity",
+                   "schedule": schedule, "launch": "hip-graph replay"},
         "roofline": roofline,
         "hbm": hbm,
         "per_view_launch": per_view,

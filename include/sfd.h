@@ -165,6 +165,31 @@ sfd_status sfd_backward(sfd_plan_t plan, void* const* grad_out, void* const* fie
                         const void* holo, const double* z_or_null, void* grad_in,
                         double* grad_z, void* workspace, size_t ws_bytes, hipStream_t stream);
 
+/*
+ * Schedule autotuner.  Times every tile width (transforms per workgroup) the
+ * column (y) and row (x) passes support at each of the plan's transform
+ * lengths, one pass and length at a time with the others fixed, by running
+ * the plan's whole batched forward ``reps`` times per candidate on the
+ * caller's data; keeps the fastest in the plan and in a process-wide table
+ * that later plans with the same hologram grid, view sizes and flags start
+ * from.  Arguments as in sfd_reconstruct; outputs are overwritten.
+ * Synchronises ``stream``.  The workspace layout does not change, so the same
+ * workspace stays valid.
+ *   reps   timed forwards per candidate, 1..1000
+ */
+sfd_status sfd_autotune(sfd_plan_t plan, const void* holo, void* const* out, void* workspace,
+                        size_t ws_bytes, int32_t reps, hipStream_t stream);
+
+/* Tile width the plan uses for the column (col != 0) or row (col == 0) pass
+ * at transform length L (host query). */
+sfd_status sfd_schedule(sfd_plan_t plan, int32_t L, int32_t col, int32_t* tile_width);
+
+/* Set that tile width by hand (host only).  Errors: SFD_ERR_INVALID_ARG if
+ * the plan has no transforms of length L or the pass has no kernel of that
+ * tile width at L.  Results do not depend on the tile width: every transform
+ * is computed the same way whatever workgroup holds it. */
+sfd_status sfd_set_schedule(sfd_plan_t plan, int32_t L, int32_t col, int32_t tile_width);
+
 /* Kernel kinds reported by sfd_profile_report. */
 enum {
   SFD_KERNEL_TABLES = 0,   /* chirp and twiddle tables (Eqs. 2-4) */

@@ -25,7 +25,8 @@ from ._lib import (SFD_EAGER, SFD_IN_C64, SFD_IN_REAL_F32, SFD_OUT_FIELD, SFD_OU
                    SFD_PER_VIEW_LAUNCH, SFD_PHASE_FP32, SfdError, SfdGrid, SfdView)
 
 __all__ = ["Plan", "SFDFunction", "sfd_plan", "sfd_workspace_size", "sfd_view_lengths", "sfd_reconstruct",
-           "sfd_backward", "sfd_profile_enable", "sfd_profile_report", "sfd_destroy", "SfdError"]
+           "sfd_backward", "sfd_autotune", "sfd_schedule", "sfd_set_schedule", "sfd_profile_enable",
+           "sfd_profile_report", "sfd_destroy", "SfdError"]
 
 
 def _grid(g) -> SfdGrid:
@@ -104,6 +105,23 @@ def sfd_backward(plan, grad_out: Sequence[torch.Tensor], field_out: Optional[Seq
                                         _stream_handle(holo.device)))
 
 
+def sfd_autotune(plan, holo: torch.Tensor, outs: Sequence[torch.Tensor], workspace: torch.Tensor,
+                 reps: int = 5) -> None:
+    _lib.check(_lib.load().sfd_autotune(plan, _ptr(holo), _ptr_array(outs), _ptr(workspace),
+                                        workspace.numel() * workspace.element_size(), int(reps),
+                                        _stream_handle(holo.device)))
+
+
+def sfd_schedule(plan, L: int, col: bool) -> int:
+    g = ctypes.c_int32()
+    _lib.check(_lib.load().sfd_schedule(plan, int(L), 1 if col else 0, ctypes.byref(g)))
+    return int(g.value)
+
+
+def sfd_set_schedule(plan, L: int, col: bool, tile_width: int) -> None:
+    _lib.check(_lib.load().sfd_set_schedule(plan, int(L), 1 if col else 0, int(tile_width)))
+
+
 def sfd_profile_enable(plan, enable: bool) -> None:
     _lib.check(_lib.load().sfd_profile_enable(plan, 1 if enable else 0))
 
@@ -157,6 +175,26 @@ class Plan:
 
     def lengths(self, v: int):
         return sfd_view_lengths(self.handle, v)
+
+    def autotune(self, holo: torch.Tensor, reps: int = 5, outs=None):
+        """Time every tile width of every pass on this data and keep the
+        fastest (see ``sfd_autotune``); returns the schedule."""
+        holo = self._check_holo(holo)
+        outs = self.new_outputs() if outs is None else outs
+        sfd_autotune(self.handle, holo, outs, self.workspace, reps)
+        return self.schedule()
+
+    def set_schedule(self, L: int, col: bool, tile_width: int) -> None:
+        sfd_set_schedule(self.handle, L, col, tile_width)
+
+    def schedule(self):
+        """{(pass, L): tile width} with pass "col" (y transforms) or "row" (x transforms)."""
+        out = {}
+        for v in range(len(self.views)):
+            lx, ly = self.lengths(v)
+            out[("col", ly)] = sfd_schedule(self.handle, ly, True)
+            out[("row", lx)] = sfd_schedule(self.handle, lx, False)
+        return out
 
     def new_outputs(self):
         """Output tensors for one call: intensities, fields, or both (intensities first)."""

@@ -8,6 +8,8 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -96,16 +98,45 @@ struct ViewLayout {
   size_t prex = 0, prey = 0, postx = 0, posty = 0, hx = 0, hy = 0, inter = 0;
 };
 
-// One column-tile copy of a hologram (see sfd::TileJob).
+// One column-tile copy of a hologram for the column passes of length L
+// (see sfd::TileJob); G and stride follow the plan's schedule.
 struct TileLayout {
-  int holo, G, stride;
+  int holo, L, G, stride;
   size_t off;
 };
+
+// Column-tile row stride (elements) for tile width G: padded off a power of two.
+int tile_stride(int ny, int G) { return (ny * G + 63) / 64 * 64 + 64; }
+
+// Elements of a tile copy of an nx x ny grid, the most any tile width of the
+// column pass at length L needs (so that a schedule change keeps the layout).
+size_t tile_alloc_elems(int nx, int ny, int L) {
+  int w[16];
+  const int n = std::min(sfd::pass_tile_widths(L, true, w, 16), 16);
+  size_t m = 0;
+  for (int i = 0; i < n; ++i) m = std::max(m, (size_t)((nx + w[i] - 1) / w[i]) * (size_t)tile_stride(ny, w[i]));
+  return m;
+}
+
+// Narrowest tile width of a pass at length L (the most tiles).
+int min_tile_width(int L, bool col) {
+  int w[16];
+  const int n = std::min(sfd::pass_tile_widths(L, col, w, 16), 16);
+  int m = 1 << 30;
+  for (int i = 0; i < n; ++i) m = std::min(m, w[i]);
+  return m;
+}
 
 // Row stride of the N1y x N0x intermediate: padded off a power of two so the
 // column pass's strided writes spread over the cache channels.
 int inter_ld(int n0x) { return (n0x + 15) / 16 * 16 + 16; }
 
+}  // namespace
+
+namespace {
+// Tuned tile widths, keyed by the plan's shapes: (col, L, shape signature).
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, std::string>, int> g_tuned;
 }  // namespace
 
 struct sfd_plan_s {
@@ -153,6 +184,16 @@ struct sfd_plan_s {
   };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> event_pool;
+
+  // Schedule: tile width per transform length of the column (y) and row (x)
+  // passes; lengths not listed use the default.
+  std::map<int, int> gcol, grow;
+  std::string shape_sig;  // hologram grid, view sizes and flags, for the tuning table
+  int tile_g(int L, bool col) const {
+    const auto& m = col ? gcol : grow;
+    const auto it = m.find(L);
+    return it != m.end() ? it->second : sfd::rows_per_tile(L, col);
+  }
 
   // Recorded forward launch sequence (batched plans): valid for graph_ws.
   hipStream_t cap_stream = nullptr;
@@ -506,7 +547,7 @@ sfd_status launch_rows(const CallDescs& D, const sfd::RowJob* d_rows, int first,
     sfd::PassArgs a{};
     a.jobs = d_rows + i;
     a.njobs = j - i;
-    const int G = sfd::rows_per_tile(L, col);
+    const int G = P->tile_g(L, col);
     int acc = 0;
     for (int k = i; k < j; ++k) {
       a.tile_prefix[k - i] = acc;
@@ -515,10 +556,29 @@ sfd_status launch_rows(const CallDescs& D, const sfd::RowJob* d_rows, int first,
     a.tile_prefix[j - i] = acc;
     a.total_tiles = acc;
     const float2* tw = reinterpret_cast<const float2*>(ws + P->tw_off.at(L));
-    SFD_TIMED(P, kind, stream, sfd::launch_pass(L, col, a, tw, stream));
+    SFD_TIMED(P, kind, stream, sfd::launch_pass(L, col, G, a, tw, stream));
     i = j;
   }
   return SFD_OK;
+}
+
+// Tile widths and strides that follow the schedule (the allocations were
+// sized for every tile width, so offsets never move).
+void apply_schedule(sfd_plan_s* P) {
+  for (TileLayout& T : P->tiles) {
+    T.G = P->tile_g(T.L, true);
+    T.stride = tile_stride(P->holo.ny, T.G);
+  }
+  for (size_t v = 0; v < P->blay.size(); ++v) {
+    sfd_plan_s::BwdLayout& B = P->blay[v];
+    const sfd_grid& o = P->views[v].out;
+    B.ga = P->tile_g(P->lay[v].ly, true);
+    B.gtile_stride = tile_stride(o.ny, B.ga);
+    const int gr = P->tile_g(P->lay[v].lx, false);
+    B.nt_r = (o.ny + gr - 1) / gr;
+    B.nt_a = (P->holo.ny + gr - 1) / gr;
+  }
+  P->drop_graph();
 }
 
 // The batched forward sequence: every view's tables, spectra and hologram
@@ -932,20 +992,18 @@ sfd_status sfd_plan(sfd_plan_t* plan, double wavelength, const sfd_grid* holo_gr
   ls.erase(std::unique(ls.begin(), ls.end()), ls.end());
   P->lengths = ls;
 
-  // Column-tile copies: one per (hologram, tile width) the views need.
+  // Column-tile copies: one per (hologram, column-pass length) the views need.
   const size_t in_elem = (flags & SFD_IN_REAL_F32) ? sizeof(float) : sizeof(float2);
   P->lay.resize(n_views);
   for (int v = 0; v < n_views; ++v) {
-    const int G = sfd::rows_per_tile(choose_length(h.ny, views[v].out.ny), true);
+    const int ly = choose_length(h.ny, views[v].out.ny);
     int found = -1;
     for (size_t k = 0; k < P->tiles.size(); ++k)
-      if (P->tiles[k].holo == views[v].holo && P->tiles[k].G == G) found = (int)k;
+      if (P->tiles[k].holo == views[v].holo && P->tiles[k].L == ly) found = (int)k;
     if (found < 0) {
-      TileLayout T;
+      TileLayout T{};
       T.holo = views[v].holo;
-      T.G = G;
-      T.stride = (h.ny * G + 63) / 64 * 64 + 64;  // elements, off a power of two
-      T.off = 0;
+      T.L = ly;
       P->tiles.push_back(T);
       found = (int)P->tiles.size() - 1;
     }
@@ -957,9 +1015,8 @@ sfd_status sfd_plan(sfd_plan_t* plan, double wavelength, const sfd_grid* holo_gr
   P->desc_bytes = desc_capacity(n_views, (int)ls.size(), (int)P->tiles.size());
   off += P->desc_bytes;
   for (TileLayout& T : P->tiles) {
-    const size_t ntiles = (size_t)(h.nx + T.G - 1) / T.G;
     T.off = off;
-    off += align_up(ntiles * (size_t)T.stride * in_elem);
+    off += align_up(tile_alloc_elems(h.nx, h.ny, T.L) * in_elem);
   }
   for (int L : ls) {
     P->tw_off[L] = off;
@@ -1021,16 +1078,15 @@ sfd_status sfd_plan(sfd_plan_t* plan, double wavelength, const sfd_grid* holo_gr
       B.hyf = take(c8 * ly);
       B.hxa = take(c8 * lx);
       B.hya = take(c8 * ly);
-      B.ga = sfd::rows_per_tile(ly, true);
-      B.gtile_stride = (o.ny * B.ga + 63) / 64 * 64 + 64;
-      B.gtile = take(c8 * (size_t)((o.nx + B.ga - 1) / B.ga) * B.gtile_stride);
+      B.gtile = take(c8 * tile_alloc_elems(o.nx, o.ny, ly));
       B.wf = take(c8 * (size_t)o.ny * inter_ld(h.nx));
       B.wm = take(c8 * (size_t)o.ny * inter_ld(h.nx));
       B.wa = take(c8 * (size_t)h.ny * inter_ld(o.nx));
       B.vbuf = P->holo_views[views[v].holo] > 1 ? take(c8 * (size_t)h.nx * h.ny) : 0;
-      const int gr = sfd::rows_per_tile(lx, false);
-      B.nt_r = (o.ny + gr - 1) / gr;
-      B.nt_a = (h.ny + gr - 1) / gr;
+      // Partials: room for the most row-pass tiles any schedule launches.
+      const int gmin = min_tile_width(lx, false);
+      B.nt_r = (o.ny + gmin - 1) / gmin;
+      B.nt_a = (h.ny + gmin - 1) / gmin;
       B.p12 = take(4 * sizeof(double) * B.nt_r);
       B.p3 = take(4 * sizeof(double) * B.nt_r);
       B.p4 = take(4 * sizeof(double) * B.nt_r);
@@ -1038,6 +1094,22 @@ sfd_status sfd_plan(sfd_plan_t* plan, double wavelength, const sfd_grid* holo_gr
     }
   }
   P->ws_bytes = off;
+  // Start from the tuning table for these shapes, if an earlier autotune filled it.
+  {
+    std::string sig = std::to_string(h.nx) + "x" + std::to_string(h.ny) + "/" + std::to_string(n_holo) + "/" +
+                      std::to_string(flags & ~(uint32_t)(SFD_EAGER | SFD_PER_VIEW_LAUNCH));
+    for (int v = 0; v < n_views; ++v)
+      sig += ";" + std::to_string(views[v].out.nx) + "x" + std::to_string(views[v].out.ny) + "@" +
+             std::to_string(views[v].holo);
+    P->shape_sig = sig;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (int L : ls)
+      for (int col = 0; col < 2; ++col) {
+        const auto it = g_tuned.find(std::make_tuple(col, L, sig));
+        if (it != g_tuned.end()) (col ? P->gcol : P->grow)[L] = it->second;
+      }
+  }
+  apply_schedule(P);
   *plan = P;
   return SFD_OK;
 }
@@ -1160,6 +1232,103 @@ sfd_status sfd_backward(sfd_plan_t plan, void* const* grad_out, void* const* fie
   if ((st = check_z(plan, z_or_null)) != SFD_OK) return st;
   return run_backward(plan, grad_out, field_out, holo, z_or_null, grad_in, grad_z, static_cast<char*>(workspace),
                       stream);
+}
+
+sfd_status sfd_autotune(sfd_plan_t plan, const void* holo, void* const* out, void* workspace, size_t ws_bytes,
+                        int32_t reps, hipStream_t stream) {
+  g_err.clear();
+  sfd_status st = check_common(plan, workspace, ws_bytes);
+  if (st != SFD_OK) return st;
+  if (reps < 1 || reps > 1000) return fail(SFD_ERR_INVALID_ARG, "reps must be in [1, 1000]");
+  if (plan->profiling) return fail(SFD_ERR_INVALID_ARG, "turn kernel timing off before autotuning");
+  // Time direct launches (a graph replay runs the same kernels); restore the
+  // flags on every exit.
+  struct FlagGuard {
+    sfd_plan_s* p;
+    uint32_t f;
+    ~FlagGuard() { p->flags = f; }
+  } guard{plan, plan->flags};
+  plan->flags |= SFD_EAGER;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  struct EventGuard {
+    hipEvent_t* a;
+    hipEvent_t* b;
+    ~EventGuard() {
+      if (*a) (void)hipEventDestroy(*a);
+      if (*b) (void)hipEventDestroy(*b);
+    }
+  } eguard{&e0, &e1};
+  SFD_HIP_TRY(hipEventCreate(&e0));
+  SFD_HIP_TRY(hipEventCreate(&e1));
+  auto timed = [&](float* ms) -> sfd_status {
+    sfd_status s2 = sfd_reconstruct(plan, holo, nullptr, out, workspace, ws_bytes, stream);  // warm-up
+    if (s2 != SFD_OK) return s2;
+    SFD_HIP_TRY(hipEventRecord(e0, stream));
+    for (int r = 0; r < reps; ++r)
+      if ((s2 = sfd_reconstruct(plan, holo, nullptr, out, workspace, ws_bytes, stream)) != SFD_OK) return s2;
+    SFD_HIP_TRY(hipEventRecord(e1, stream));
+    SFD_HIP_TRY(hipEventSynchronize(e1));
+    SFD_HIP_TRY(hipEventElapsedTime(ms, e0, e1));
+    return SFD_OK;
+  };
+  std::vector<std::pair<int, int>> passes;  // (col, L)
+  for (const ViewLayout& v : plan->lay) {
+    passes.push_back({1, v.ly});
+    passes.push_back({0, v.lx});
+  }
+  std::sort(passes.begin(), passes.end());
+  passes.erase(std::unique(passes.begin(), passes.end()), passes.end());
+  for (const auto& pl : passes) {
+    const int col = pl.first, L = pl.second;
+    int widths[16];
+    const int n = std::min(sfd::pass_tile_widths(L, col != 0, widths, 16), 16);
+    auto& m = col ? plan->gcol : plan->grow;
+    int best = plan->tile_g(L, col != 0);
+    float best_ms = 0.f;
+    for (int i = 0; i < n; ++i) {
+      m[L] = widths[i];
+      apply_schedule(plan);
+      float ms = 0.f;
+      if ((st = timed(&ms)) != SFD_OK) {
+        m[L] = best;
+        apply_schedule(plan);
+        return st;
+      }
+      if (i == 0 || ms < best_ms) {
+        best_ms = ms;
+        best = widths[i];
+      }
+    }
+    m[L] = best;
+    apply_schedule(plan);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[std::make_tuple(col, L, plan->shape_sig)] = best;
+  }
+  return SFD_OK;
+}
+
+sfd_status sfd_schedule(sfd_plan_t plan, int32_t L, int32_t col, int32_t* tile_width) {
+  g_err.clear();
+  if (!plan || !tile_width) return fail(SFD_ERR_INVALID_ARG, "NULL argument");
+  if (std::find(plan->lengths.begin(), plan->lengths.end(), (int)L) == plan->lengths.end())
+    return fail(SFD_ERR_INVALID_ARG, "the plan has no transforms of length " + std::to_string(L));
+  *tile_width = plan->tile_g(L, col != 0);
+  return SFD_OK;
+}
+
+sfd_status sfd_set_schedule(sfd_plan_t plan, int32_t L, int32_t col, int32_t tile_width) {
+  g_err.clear();
+  if (!plan) return fail(SFD_ERR_INVALID_ARG, "plan is NULL");
+  if (std::find(plan->lengths.begin(), plan->lengths.end(), (int)L) == plan->lengths.end())
+    return fail(SFD_ERR_INVALID_ARG, "the plan has no transforms of length " + std::to_string(L));
+  int widths[16];
+  const int n = std::min(sfd::pass_tile_widths(L, col != 0, widths, 16), 16);
+  if (std::find(widths, widths + n, (int)tile_width) == widths + n)
+    return fail(SFD_ERR_INVALID_ARG, "no " + std::string(col ? "column" : "row") + " pass kernel of tile width " +
+                                         std::to_string(tile_width) + " at length " + std::to_string(L));
+  (col ? plan->gcol : plan->grow)[L] = tile_width;
+  apply_schedule(plan);
+  return SFD_OK;
 }
 
 sfd_status sfd_profile_enable(sfd_plan_t plan, int32_t enable) {

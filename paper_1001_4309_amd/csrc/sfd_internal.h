@@ -170,12 +170,16 @@ hipError_t launch_setup(const SetupArgs& args, hipStream_t s);
 int spectra_per_block(int L);
 
 // col = true: the y transforms (column kernel); false: the x transforms.
-hipError_t launch_pass(int L, bool col, const PassArgs& args, const float2* tw, hipStream_t s);
+// G is the tile width: one of pass_tile_widths(L, col).
+hipError_t launch_pass(int L, bool col, int G, const PassArgs& args, const float2* tw, hipStream_t s);
 
 hipError_t launch_gradz(const GradZJob* d_jobs, int njobs, hipStream_t s);
 hipError_t launch_gather(const GatherJob* d_jobs, int njobs, int max_n, hipStream_t s);
 
-// Transforms per workgroup (the tile) of a pass at a transform length.
+// Tile widths (transforms per workgroup) a pass supports at length L, the
+// default first; returns how many there are (writes at most cap of them).
+int pass_tile_widths(int L, bool col, int* widths, int cap);
+// The default tile width of a pass at length L (0 if L is unsupported).
 int rows_per_tile(int L, bool col);
 bool supported_length(int L);
 // Entries of the twiddle table of the passes' (spec = false) or the kernel

@@ -295,19 +295,14 @@ __global__ void __launch_bounds__(kSetupThreads) setup_kernel(const SetupArgs A)
 #define SFD_COL_WPE 1
 #endif
 
-// Workgroup shape of the passes: NW wavefronts; G = NW * 64 / TPR rows (or
-// columns) per workgroup.
-template <int L>
-struct RowCfg {
+// Workgroup shape of a pass: G rows (or columns) of TPR threads each.
+template <int L, int G_>
+struct PassShape {
   static constexpr int TPR = PassPlan<L>::TPR;
-  static constexpr int NW = TPR >= 256 ? 4 : TPR >= 128 ? 2 : 2;
-  static constexpr int G = NW * 64 / TPR;
-};
-template <int L>
-struct ColCfg {
-  static constexpr int TPR = PassPlan<L>::TPR;
-  static constexpr int NW = TPR >= 128 ? 8 : TPR >= 32 ? 8 * TPR / 64 : 2;
-  static constexpr int G = NW * 64 / TPR;
+  static constexpr int G = G_;
+  static constexpr int THREADS = G * TPR;
+  static constexpr int NW = THREADS / 64;
+  static_assert(THREADS % 64 == 0 && THREADS <= 1024, "a pass workgroup is 1 to 16 whole wavefronts");
 };
 
 // Map a workgroup to a tile so that consecutive tiles (which touch adjacent
@@ -442,14 +437,15 @@ __device__ __forceinline__ void row_reduce(const RowJob& J, const float2 (&v)[R]
 
 // x transforms: row r of the job reads in + r * in_ld and writes
 // out + r * out_ld (contiguous), both straight from registers.
-template <int L>
-__global__ void __launch_bounds__(RowCfg<L>::NW * 64) __attribute__((amdgpu_waves_per_eu(SFD_ROW_WPE))) row_kernel(const PassArgs args, const float2* __restrict__ tw) {
-  constexpr int TPR = RowCfg<L>::TPR;
+template <int L, int GR>
+__global__ void __launch_bounds__((PassShape<L, GR>::THREADS)) __attribute__((amdgpu_waves_per_eu(SFD_ROW_WPE))) row_kernel(const PassArgs args, const float2* __restrict__ tw) {
+  using S = PassShape<L, GR>;
+  constexpr int TPR = S::TPR;
   constexpr int R = L / TPR;
-  constexpr int G = RowCfg<L>::G;
+  constexpr int G = S::G;
   constexpr int RB = row_lds_bytes<L, kSplit>();
   // Exchange buffers, then room for the epilogue reduction (4 doubles per wavefront).
-  __shared__ __align__(16) unsigned char lds[G * RB + RowCfg<L>::NW * 32];
+  __shared__ __align__(16) unsigned char lds[G * RB + S::NW * 32];
 
   const int tile = xcd_tile(blockIdx.x, args.total_tiles);
   const int jid = find_job(args, tile);
@@ -508,7 +504,7 @@ __global__ void __launch_bounds__(RowCfg<L>::NW * 64) __attribute__((amdgpu_wave
       if (TPR * (i + 1) <= n_out || m < n_out) gst(out, (unsigned)m, (v[i].x * v[i].x + v[i].y * v[i].y) * sc);
     }
   }
-  if (mode & kReduce) row_reduce<TPR, R, RowCfg<L>::NW>(J, v, row, valid, t, tile - args.tile_prefix[jid],
+  if (mode & kReduce) row_reduce<TPR, R, S::NW>(J, v, row, valid, t, tile - args.tile_prefix[jid],
                                                          reinterpret_cast<double*>(lds + G * RB));
 }
 
@@ -516,12 +512,13 @@ __global__ void __launch_bounds__(RowCfg<L>::NW * 64) __attribute__((amdgpu_wave
 // writes out[m * out_ld + c] for m < n_out (complex).  G columns per
 // workgroup go through LDS staging in chunks of L/2 elements, so that each
 // global access covers G consecutive columns.
-template <int L>
-__global__ void __launch_bounds__(ColCfg<L>::NW * 64) __attribute__((amdgpu_waves_per_eu(SFD_COL_WPE))) col_kernel(const PassArgs args, const float2* __restrict__ tw) {
-  constexpr int TPR = ColCfg<L>::TPR;
+template <int L, int GC>
+__global__ void __launch_bounds__((PassShape<L, GC>::THREADS)) __attribute__((amdgpu_waves_per_eu(SFD_COL_WPE))) col_kernel(const PassArgs args, const float2* __restrict__ tw) {
+  using S = PassShape<L, GC>;
+  constexpr int TPR = S::TPR;
   constexpr int R = L / TPR;
-  constexpr int G = ColCfg<L>::G;
-  constexpr int THREADS = ColCfg<L>::NW * 64;
+  constexpr int G = S::G;
+  constexpr int THREADS = S::THREADS;
   constexpr int RB = row_lds_bytes<L, kSplit>();
   constexpr int C = L / 2;    // staging chunk along the transform
   constexpr int SST = C + 9;  // staging stride per column (elements)
@@ -637,18 +634,37 @@ __global__ void __launch_bounds__(ColCfg<L>::NW * 64) __attribute__((amdgpu_wave
 
 bool supported_length(int L) { return twiddle_len(L, false) >= 0; }
 
-int rows_per_tile(int L, bool col) {
-  switch (L) {
-    case 64: return col ? ColCfg<64>::G : RowCfg<64>::G;
-    case 128: return col ? ColCfg<128>::G : RowCfg<128>::G;
-    case 256: return col ? ColCfg<256>::G : RowCfg<256>::G;
-    case 512: return col ? ColCfg<512>::G : RowCfg<512>::G;
-    case 1024: return col ? ColCfg<1024>::G : RowCfg<1024>::G;
-    case 2048: return col ? ColCfg<2048>::G : RowCfg<2048>::G;
-    case 4096: return col ? ColCfg<4096>::G : RowCfg<4096>::G;
-    case 8192: return col ? ColCfg<8192>::G : RowCfg<8192>::G;
-    default: return 0;
+// Tile widths a pass can be launched with at each length (the workgroup is
+// G * TPR threads and G exchange rows must fit in LDS); the first entry is
+// the default.
+#define SFD_ROW_SHAPES(X) \
+  X(64, 32) X(64, 16) X(64, 64) X(128, 16) X(128, 8) X(128, 32) X(256, 8) X(256, 4) X(256, 16) \
+  X(512, 4) X(512, 2) X(512, 8) X(1024, 2) X(1024, 1) X(1024, 4) X(2048, 2) X(2048, 1) X(2048, 4) \
+  X(4096, 1) X(8192, 1)
+#define SFD_COL_SHAPES(X) \
+  X(64, 32) X(64, 16) X(128, 16) X(128, 8) X(256, 8) X(256, 4) X(512, 8) X(512, 4) \
+  X(1024, 8) X(1024, 4) X(1024, 16) X(2048, 8) X(2048, 4) X(2048, 2) X(4096, 2) X(4096, 4) \
+  X(8192, 2) X(8192, 1)
+
+int pass_tile_widths(int L, bool col, int* widths, int cap) {
+  int n = 0;
+#define SFD_PUSH(l, g) \
+  if (l == L) {        \
+    if (n < cap) widths[n] = g; \
+    ++n;               \
   }
+  if (col) {
+    SFD_COL_SHAPES(SFD_PUSH)
+  } else {
+    SFD_ROW_SHAPES(SFD_PUSH)
+  }
+#undef SFD_PUSH
+  return n;
+}
+
+int rows_per_tile(int L, bool col) {
+  int g = 0;
+  return pass_tile_widths(L, col, &g, 1) > 0 ? g : 0;
 }
 
 // Sum of a tile-partial array (acc index k) in a fixed order.
@@ -739,28 +755,23 @@ int spectra_per_block(int L) {
   }
 }
 
-template <int L>
-static hipError_t pass_l(bool col, const PassArgs& a, const float2* tw, hipStream_t s) {
-  if (col)
-    hipLaunchKernelGGL(col_kernel<L>, dim3(a.total_tiles), dim3(ColCfg<L>::NW * 64), 0, s, a, tw);
-  else
-    hipLaunchKernelGGL(row_kernel<L>, dim3(a.total_tiles), dim3(RowCfg<L>::NW * 64), 0, s, a, tw);
-  return hipGetLastError();
-}
-
-hipError_t launch_pass(int L, bool col, const PassArgs& a, const float2* tw, hipStream_t s) {
+hipError_t launch_pass(int L, bool col, int G, const PassArgs& a, const float2* tw, hipStream_t s) {
   if (a.total_tiles <= 0) return hipSuccess;
-  switch (L) {
-    case 64: return pass_l<64>(col, a, tw, s);
-    case 128: return pass_l<128>(col, a, tw, s);
-    case 256: return pass_l<256>(col, a, tw, s);
-    case 512: return pass_l<512>(col, a, tw, s);
-    case 1024: return pass_l<1024>(col, a, tw, s);
-    case 2048: return pass_l<2048>(col, a, tw, s);
-    case 4096: return pass_l<4096>(col, a, tw, s);
-    case 8192: return pass_l<8192>(col, a, tw, s);
-    default: return hipErrorInvalidValue;
+#define SFD_LAUNCH_ROW(l, g)                                                                              \
+  if (!col && L == l && G == g) {                                                                        \
+    hipLaunchKernelGGL((row_kernel<l, g>), dim3(a.total_tiles), dim3(PassShape<l, g>::THREADS), 0, s, a, tw); \
+    return hipGetLastError();                                                                            \
   }
+#define SFD_LAUNCH_COL(l, g)                                                                              \
+  if (col && L == l && G == g) {                                                                         \
+    hipLaunchKernelGGL((col_kernel<l, g>), dim3(a.total_tiles), dim3(PassShape<l, g>::THREADS), 0, s, a, tw); \
+    return hipGetLastError();                                                                            \
+  }
+  SFD_ROW_SHAPES(SFD_LAUNCH_ROW)
+  SFD_COL_SHAPES(SFD_LAUNCH_COL)
+#undef SFD_LAUNCH_ROW
+#undef SFD_LAUNCH_COL
+  return hipErrorInvalidValue;
 }
 
 }  // namespace sfd

@@ -166,3 +166,42 @@ def test_last_error_is_cleared_on_success(lib):
     st, h = _plan(lib)
     assert st == lib_mod.SFD_OK and lib.sfd_last_error().decode() == ""
     lib.sfd_destroy(h)
+
+
+def test_schedule_queries_and_manual_setting(lib):
+    """Tile widths: defaults, the allowed set per length, rejection of others,
+    and a workspace size that does not depend on the schedule."""
+    views = [lib_mod.SfdView(_grid(1024, 1024, 8e-6, 8e-6), 0.03, 0)]
+    st, h = _plan(lib, holo=_grid(1024, 1024), views=views)
+    assert st == 0
+    g = ctypes.c_int32()
+    assert lib.sfd_schedule(h, 2048, 1, ctypes.byref(g)) == 0 and g.value == 8
+    assert lib.sfd_schedule(h, 2048, 0, ctypes.byref(g)) == 0 and g.value == 2
+    assert lib.sfd_schedule(h, 1024, 1, ctypes.byref(g)) == lib_mod.SFD_ERR_INVALID_ARG
+    n0 = ctypes.c_size_t()
+    assert lib.sfd_workspace_size(h, ctypes.byref(n0)) == 0
+    for col, width in ((1, 4), (1, 2), (0, 1), (0, 4)):
+        assert lib.sfd_set_schedule(h, 2048, col, width) == 0
+        assert lib.sfd_schedule(h, 2048, col, ctypes.byref(g)) == 0 and g.value == width
+        n = ctypes.c_size_t()
+        assert lib.sfd_workspace_size(h, ctypes.byref(n)) == 0 and n.value == n0.value
+    assert lib.sfd_set_schedule(h, 2048, 1, 3) == lib_mod.SFD_ERR_INVALID_ARG
+    assert b"tile width 3" in lib.sfd_last_error()
+    assert lib.sfd_set_schedule(h, 2048, 0, 16) == lib_mod.SFD_ERR_INVALID_ARG
+    assert lib.sfd_set_schedule(h, 4096, 1, 2) == lib_mod.SFD_ERR_INVALID_ARG
+    assert lib.sfd_destroy(h) == 0
+
+
+def test_autotune_validates_before_any_hip_call(lib):
+    st, h = _plan(lib)
+    assert st == 0
+    n = ctypes.c_size_t()
+    lib.sfd_workspace_size(h, ctypes.byref(n))
+    out = (ctypes.c_void_p * 1)(4096)
+    assert lib.sfd_autotune(h, ctypes.c_void_p(4096), out, ctypes.c_void_p(0), n.value, 3, None) == \
+        lib_mod.SFD_ERR_INVALID_ARG
+    assert lib.sfd_autotune(h, ctypes.c_void_p(4096), out, ctypes.c_void_p(256), n.value, 0, None) == \
+        lib_mod.SFD_ERR_INVALID_ARG
+    assert lib.sfd_autotune(h, ctypes.c_void_p(4096), out, ctypes.c_void_p(256), 0, 3, None) == \
+        lib_mod.SFD_ERR_WORKSPACE
+    assert lib.sfd_destroy(h) == 0

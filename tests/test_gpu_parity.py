@@ -179,3 +179,41 @@ def test_graph_replays_equal_eager_launches():
     torch.cuda.synchronize()
     for a, b in zip(fresh, ref):
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("cfg", ["config1", "config2"])
+def test_every_tile_width_gives_identical_results(cfg):
+    """Each transform is computed the same way whichever workgroup holds it,
+    so every schedule must reproduce the default bit for bit."""
+    w = getattr(workloads, cfg)()
+    holo = _holo(w)
+    p = _plan(w, outputs="both")
+    ref = [t.clone() for t in p.reconstruct(holo)]
+    lx, ly = p.lengths(0)
+    for col, L in ((True, ly), (False, lx)):
+        default = p.schedule()[("col" if col else "row", L)]
+        widths = {1, 2, 4, 8, 16, 32, 64}
+        for g in sorted(widths):
+            try:
+                p.set_schedule(L, col, g)
+            except sfd.SfdError:
+                continue
+            got = p.reconstruct(holo)
+            torch.cuda.synchronize()
+            for a, b in zip(got, ref):
+                assert torch.equal(a, b), (col, L, g)
+        p.set_schedule(L, col, default)
+
+
+def test_autotune_keeps_results_and_seeds_new_plans():
+    w = workloads.config2()
+    holo = _holo(w)
+    p = _plan(w)
+    ref = [t.clone() for t in p.reconstruct(holo)]
+    sched = p.autotune(holo, reps=3)
+    print("tuned schedule", sched, flush=True)
+    got = p.reconstruct(holo)
+    torch.cuda.synchronize()
+    for a, b in zip(got, ref):
+        assert torch.equal(a, b)
+    assert _plan(w).schedule() == sched
