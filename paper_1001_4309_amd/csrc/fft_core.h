@@ -120,10 +120,16 @@ __device__ __forceinline__ void dft(float2 (&a)[N]) {
 // ---------------------------------------------------------------------------
 // Plans and twiddle tables.
 
+template <int a, int... rest>
+struct FirstOf {
+  static constexpr int value = a;
+};
+
 template <int... Rs>
 struct Radices {
   static constexpr int count = sizeof...(Rs);
   static constexpr int product = (Rs * ...);
+  static constexpr int first = FirstOf<Rs...>::value;
 };
 
 // A transform shape: length L held by TPR threads (R = L / TPR values each)
@@ -270,21 +276,50 @@ __device__ __forceinline__ int lds_ridx(int t, int i) {
   else return lds_pad(t + TPR * i);
 }
 
-// One Stockham stage.  v[i] holds element t + TPR * i of the stage input.
-// If LAST, the output replaces v in natural order; otherwise it goes through
-// the row's LDS buffer (complex, or real and imaginary parts in turn when
-// SPLIT) and v is reloaded in the t + TPR * i layout.  ``tw`` points at this
-// stage's part of the twiddle table.
-template <int L, int TPR, int r, int Ns, bool INV, bool LAST, bool SPLIT, bool TWC = false>
-__device__ __forceinline__ void fft_stage(float2 (&v)[L / TPR], void* __restrict__ buf, int t,
-                                          const float2* __restrict__ tw) {
+// Twiddles of one stage held in registers: for butterfly q of the thread
+// (j = t + TPR q) and input k >= 1, exp(-2 pi i k (j mod Ns) / (Ns r)) from
+// the stage's part of the table.  Loaded one stage ahead (before the previous
+// stage's exchange) so that their latency overlaps the LDS round trip.
+// With TWC the twiddles are computed instead (FP32 sincospi of the exact
+// argument k jm / (Ns r)): for a single transform that runs alone, this is
+// faster than waiting for table reads.
+template <int TPR, int R, int r, int Ns, bool TWC = false>
+struct StageTw {
+  static constexpr int nb = R / r;
+  static constexpr bool any = Ns > 1;
+  float2 w[any ? nb : 1][any ? r - 1 : 1];
+  __device__ __forceinline__ void load(int t, const float2* __restrict__ tw) {
+    if constexpr (any) {
+#pragma unroll
+      for (int q = 0; q < nb; ++q) {
+        const unsigned jm = (unsigned)(t + TPR * q) & (unsigned)(Ns - 1);
+#pragma unroll
+        for (int k = 1; k < r; ++k) {
+          if constexpr (TWC) {
+            float sn, cs;
+            sincospif(-2.0f * (float)(k * (int)jm) / (float)(Ns * r), &sn, &cs);
+            w[q][k - 1] = make_float2(cs, sn);
+          } else {
+            w[q][k - 1] = gld(tw, (unsigned)((k - 1) * Ns) + jm);
+          }
+        }
+      }
+    }
+  }
+};
+
+// Butterflies of one Stockham stage.  v[i] holds element t + TPR * i of the
+// stage input.  The outputs stay in v (butterfly q's output k in slot
+// q + k nb, which for the last stage is natural order) unless the exchange
+// is complex (not SPLIT), in which case they go straight to the LDS buffer.
+template <int L, int TPR, int r, int Ns, bool INV, bool LAST, bool SPLIT, bool TWC>
+__device__ __forceinline__ void stage_compute(float2 (&v)[L / TPR], void* __restrict__ buf, int t,
+                                              const StageTw<TPR, L / TPR, r, Ns, TWC>& W) {
   constexpr int R = L / TPR;
   constexpr int nb = R / r;
-  constexpr bool WAVE = TPR <= 64;
   static_assert(R % r == 0, "radix must divide the values per thread");
   static_assert(r <= 32 && (32 % r) == 0, "radices are powers of two up to 32");
   float2* cbuf = static_cast<float2*>(buf);
-  float* fbuf = static_cast<float*>(buf);
 #pragma unroll
   for (int q = 0; q < nb; ++q) {
     const int j = t + TPR * q;
@@ -292,18 +327,8 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[L / TPR], void* __restrict
 #pragma unroll
     for (int k = 0; k < r; ++k) b[k] = v[q + k * nb];
     if constexpr (Ns > 1) {
-      const int jm = j & (Ns - 1);
 #pragma unroll
-      for (int k = 1; k < r; ++k) {
-        float2 w;
-        if constexpr (TWC) {
-          // Computed twiddle: the argument k jm / (Ns r) is exact in FP32.
-          sincospif(-2.0f * (float)(k * jm) / (float)(Ns * r), &w.y, &w.x);
-        } else {
-          w = gld(tw, (unsigned)((k - 1) * Ns + jm));
-        }
-        b[k] = INV ? cmulc(b[k], w) : cmul(b[k], w);
-      }
+      for (int k = 1; k < r; ++k) b[k] = INV ? cmulc(b[k], W.w[q][k - 1]) : cmul(b[k], W.w[q][k - 1]);
     }
     dft<r, INV>(b);
     if constexpr (nb > 1) sched_fence();
@@ -316,58 +341,75 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[L / TPR], void* __restrict
       for (int k = 0; k < r; ++k) cbuf[wb + lds_woff<r, Ns>(k)] = b[k];
     }
   }
-  if constexpr (!LAST) {
-    if constexpr (!SPLIT) {
-      lds_sync<WAVE>();
+}
+
+// Exchange after a stage: outputs (in LDS, or in v for SPLIT) are reloaded as
+// element t + TPR * i of the next stage's input.
+template <int L, int TPR, int r, int Ns, bool SPLIT>
+__device__ __forceinline__ void stage_exchange(float2 (&v)[L / TPR], void* __restrict__ buf, int t) {
+  constexpr int R = L / TPR;
+  constexpr int nb = R / r;
+  constexpr bool WAVE = TPR <= 64;
+  float2* cbuf = static_cast<float2*>(buf);
+  float* fbuf = static_cast<float*>(buf);
+  if constexpr (!SPLIT) {
+    lds_sync<WAVE>();
 #pragma unroll
-      for (int i = 0; i < R; ++i) v[i] = cbuf[lds_ridx<TPR>(t, i)];
-      lds_sync<WAVE>();
-    } else {
-      // Real parts, then imaginary parts, through a float buffer of L slots.
+    for (int i = 0; i < R; ++i) v[i] = cbuf[lds_ridx<TPR>(t, i)];
+    lds_sync<WAVE>();
+  } else {
+    // Real parts, then imaginary parts, through a float buffer of L slots.
 #pragma unroll
-      for (int q = 0; q < nb; ++q) {
-        const int wb = lds_wbase<r, Ns>(t + TPR * q);
+    for (int q = 0; q < nb; ++q) {
+      const int wb = lds_wbase<r, Ns>(t + TPR * q);
 #pragma unroll
-        for (int k = 0; k < r; ++k) fbuf[wb + lds_woff<r, Ns>(k)] = v[q + k * nb].x;
-      }
-      lds_sync<WAVE>();
-      // In place: every old real part is already in LDS.
-#pragma unroll
-      for (int i = 0; i < R; ++i) v[i].x = fbuf[lds_ridx<TPR>(t, i)];
-      lds_sync<WAVE>();
-#pragma unroll
-      for (int q = 0; q < nb; ++q) {
-        const int wb = lds_wbase<r, Ns>(t + TPR * q);
-#pragma unroll
-        for (int k = 0; k < r; ++k) fbuf[wb + lds_woff<r, Ns>(k)] = v[q + k * nb].y;
-      }
-      lds_sync<WAVE>();
-#pragma unroll
-      for (int i = 0; i < R; ++i) v[i].y = fbuf[lds_ridx<TPR>(t, i)];
-      lds_sync<WAVE>();
+      for (int k = 0; k < r; ++k) fbuf[wb + lds_woff<r, Ns>(k)] = v[q + k * nb].x;
     }
+    lds_sync<WAVE>();
+    // In place: every old real part is already in LDS.
+#pragma unroll
+    for (int i = 0; i < R; ++i) v[i].x = fbuf[lds_ridx<TPR>(t, i)];
+    lds_sync<WAVE>();
+#pragma unroll
+    for (int q = 0; q < nb; ++q) {
+      const int wb = lds_wbase<r, Ns>(t + TPR * q);
+#pragma unroll
+      for (int k = 0; k < r; ++k) fbuf[wb + lds_woff<r, Ns>(k)] = v[q + k * nb].y;
+    }
+    lds_sync<WAVE>();
+#pragma unroll
+    for (int i = 0; i < R; ++i) v[i].y = fbuf[lds_ridx<TPR>(t, i)];
+    lds_sync<WAVE>();
   }
 }
 
+// Stage (Ns, r) with its twiddles W already loaded; loads the next stage's
+// twiddles before this stage's exchange.
 template <int L, int TPR, bool INV, bool SPLIT, bool TWC, int Ns, int OFF, int r, int... rest>
-__device__ __forceinline__ void fft_stages(float2 (&v)[L / TPR], void* buf, int t, const float2* tw) {
+__device__ __forceinline__ void fft_stages(float2 (&v)[L / TPR], void* buf, int t, const float2* tw,
+                                           const StageTw<TPR, L / TPR, r, Ns, TWC>& W) {
   constexpr bool last = sizeof...(rest) == 0;
-  fft_stage<L, TPR, r, Ns, INV, last, SPLIT, TWC>(v, buf, t, tw + OFF);
+  stage_compute<L, TPR, r, Ns, INV, last, SPLIT, TWC>(v, buf, t, W);
   if constexpr (!last) {
     constexpr int next_off = OFF + (Ns > 1 ? (r - 1) * Ns : 0);
-    fft_stages<L, TPR, INV, SPLIT, TWC, Ns * r, next_off, rest...>(v, buf, t, tw);
+    constexpr int rn = Radices<rest...>::first;
+    StageTw<TPR, L / TPR, rn, Ns * r, TWC> Wn;
+    Wn.load(t, tw + next_off);
+    stage_exchange<L, TPR, r, Ns, SPLIT>(v, buf, t);
+    fft_stages<L, TPR, INV, SPLIT, TWC, Ns * r, next_off, rest...>(v, buf, t, tw, Wn);
   }
 }
 
-template <class P, bool INV, bool SPLIT, bool TWC, int... Rs>
-__device__ __forceinline__ void fft_run(Radices<Rs...>, float2 (&v)[P::R], void* buf, int t, const float2* tw) {
-  fft_stages<P::L, P::TPR, INV, SPLIT, TWC, 1, 0, Rs...>(v, buf, t, tw);
+template <class P, bool INV, bool SPLIT, bool TWC, int r0, int... Rs>
+__device__ __forceinline__ void fft_run(Radices<r0, Rs...>, float2 (&v)[P::R], void* buf, int t, const float2* tw) {
+  const StageTw<P::TPR, P::R, r0, 1, TWC> W0{};  // the first stage has no twiddles
+  fft_stages<P::L, P::TPR, INV, SPLIT, TWC, 1, 0, r0, Rs...>(v, buf, t, tw, W0);
 }
 
 // Forward (INV = false) or unnormalised inverse (INV = true) FFT of one row
 // of shape P.  ``buf`` is the row's LDS exchange buffer
-// (row_lds_bytes<P::L, SPLIT>() bytes).  TWC: twiddles computed in the stage
-// instead of read from ``tw`` (the table of shape P).
+// (row_lds_bytes<P::L, SPLIT>() bytes); ``tw`` is the twiddle table of P
+// (unused with TWC, which computes the twiddles).
 template <class P, bool INV, bool SPLIT, bool TWC = false>
 __device__ __forceinline__ void fft_row(float2 (&v)[P::R], void* buf, int t, const float2* tw) {
   fft_run<P, INV, SPLIT, TWC>(typename P::Rad{}, v, buf, t, tw);

@@ -94,29 +94,20 @@ void prefactor(double lam, double z, double px0, double py0, double* re, double*
 
 struct ViewLayout {
   int lx = 0, ly = 0;
-  int tile = -1;  // index of the hologram tile copy the column pass reads
+  int tile = -1;  // index of the hologram's column-major copy the column pass reads
   size_t prex = 0, prey = 0, postx = 0, posty = 0, hx = 0, hy = 0, inter = 0;
 };
 
-// One column-tile copy of a hologram for the column passes of length L
-// (see sfd::TileJob); G and stride follow the plan's schedule.
+// Column-major copy of a hologram for the column passes (see sfd::TileJob).
 struct TileLayout {
-  int holo, L, G, stride;
+  int holo;
   size_t off;
 };
 
-// Column-tile row stride (elements) for tile width G: padded off a power of two.
-int tile_stride(int ny, int G) { return (ny * G + 63) / 64 * 64 + 64; }
-
-// Elements of a tile copy of an nx x ny grid, the most any tile width of the
-// column pass at length L needs (so that a schedule change keeps the layout).
-size_t tile_alloc_elems(int nx, int ny, int L) {
-  int w[16];
-  const int n = std::min(sfd::pass_tile_widths(L, true, w, 16), 16);
-  size_t m = 0;
-  for (int i = 0; i < n; ++i) m = std::max(m, (size_t)((nx + w[i] - 1) / w[i]) * (size_t)tile_stride(ny, w[i]));
-  return m;
-}
+// Column stride (elements) of a column-major copy of a grid with ny rows:
+// padded off a power of two so that the transposing writes spread over the
+// memory channels.
+int col_ld(int ny) { return (ny + 63) / 64 * 64 + 64; }
 
 // Narrowest tile width of a pass at length L (the most tiles).
 int min_tile_width(int L, bool col) {
@@ -150,7 +141,6 @@ struct sfd_plan_s {
   std::vector<TileLayout> tiles;
   std::vector<int> lengths;           // distinct L values used
   std::map<int, size_t> tw_off;       // twiddle table of the passes' shape per L
-  std::map<int, size_t> spec_tw_off;  // twiddle table of the kernel-spectrum shape per L
   void* tw_ready_ws = nullptr;        // workspace whose twiddle tables are current
   size_t desc_off = 0, desc_bytes = 0;
   size_t ws_bytes = 0;
@@ -166,8 +156,7 @@ struct sfd_plan_s {
   struct BwdLayout {
     size_t prexf, preyf, postxf, postyf, prexm, preym, prexa, preya, postxa, postya;
     size_t hxf, hyf, hxa, hya;
-    size_t gtile;
-    int gtile_stride, ga;
+    size_t gtile;  // column-major copy of the view's gradient (ld col_ld(view ny))
     size_t wf, wm, wa, vbuf;  // vbuf = 0: adjoint written straight into grad_in
     size_t p12, p3, p4, p5;
     int nt_r, nt_a;           // tiles of the row passes on the view grid / hologram grid
@@ -343,14 +332,12 @@ sfd_status build_descs(sfd_plan_s* P, const void* holo, const double* z, void* c
   }
   D->tw.clear();
   for (int L : P->lengths) {
-    for (int spec = 0; spec < 2; ++spec) {
-      sfd::TwiddleJob t{};
-      t.tw = reinterpret_cast<float2*>(ws + (spec ? P->spec_tw_off.at(L) : P->tw_off.at(L)));
-      t.L = L;
-      t.count = sfd::twiddle_len(L, spec != 0);
-      t.spec = spec;
-      D->tw.push_back(t);
-    }
+    sfd::TwiddleJob t{};
+    t.tw = reinterpret_cast<float2*>(ws + P->tw_off.at(L));
+    t.L = L;
+    t.count = sfd::twiddle_len(L, false);
+    t.spec = 0;
+    D->tw.push_back(t);
   }
   D->tiles.clear();
   for (const TileLayout& T : P->tiles) {
@@ -359,8 +346,7 @@ sfd_status build_descs(sfd_plan_s* P, const void* holo, const double* z, void* c
     j.out = ws + T.off;
     j.nx = h.nx;
     j.ny = h.ny;
-    j.G = T.G;
-    j.tile_stride = T.stride;
+    j.ld = col_ld(h.ny);
     j.complex_in = in_real ? 0 : 1;
     D->tiles.push_back(j);
   }
@@ -379,10 +365,8 @@ sfd_status build_descs(sfd_plan_s* P, const void* holo, const double* z, void* c
     double c_re, c_im;
     prefactor(P->lam, zz, h.px, h.py, &c_re, &c_im);
 
-    const TileLayout& T = P->tiles[L.tile];
     const int ldw = inter_ld(h.nx);
     sfd::RowJob jc{};
-    jc.in = ws + T.off;
     jc.out = ws + L.inter;
     jc.pre = reinterpret_cast<const float2*>(ws + L.prey);
     jc.H = reinterpret_cast<const float2*>(ws + L.hy);
@@ -391,9 +375,10 @@ sfd_status build_descs(sfd_plan_s* P, const void* holo, const double* z, void* c
     jc.n_rows = h.nx;
     jc.n_in = h.ny;
     jc.n_out = w.out.ny;
-    jc.in_ld = T.stride;  // column-tile stride (elements)
     jc.out_ld = ldw;
     jc.mode = (in_real ? sfd::kInReal : 0) | (field ? sfd::kUsePost : 0) | sfd::kOutField;
+    jc.in = ws + P->tiles[L.tile].off;
+    jc.in_ld = col_ld(h.ny);
     py.push_back({L.ly, jc});
 
     sfd::RowJob jr{};
@@ -512,8 +497,7 @@ sfd_status launch_setup_for(sfd_plan_s* P, const CallDescs& D, char* ws, const s
     while (j < a0 + ns && D.axis_L[j] == D.axis_L[i]) ++j;
     const int L = D.axis_L[i];
     const int per = sfd::spectra_per_block(L);
-    const float2* stw = reinterpret_cast<const float2*>(ws + P->spec_tw_off.at(L));
-    if ((st = add({sfd::kRoleSpectrum, 0, (j - i + per - 1) / per, L, i, j - i, stw})) != SFD_OK) return st;
+    if ((st = add({sfd::kRoleSpectrum, 0, (j - i + per - 1) / per, L, i, j - i, nullptr})) != SFD_OK) return st;
     i = j;
   }
   // Pre/post chirp tables.
@@ -527,8 +511,8 @@ sfd_status launch_setup_for(sfd_plan_s* P, const CallDescs& D, char* ws, const s
                      0, nullptr})) != SFD_OK)
         return st;
   for (int k = t0; k < t0 + nt; ++k) {
-    const int cb = (D.tiles[k].nx + sfd::kTileCols - 1) / sfd::kTileCols;
-    const int rb = (D.tiles[k].ny + sfd::kTileRows - 1) / sfd::kTileRows;
+    const int cb = (D.tiles[k].nx + sfd::kTrBlock - 1) / sfd::kTrBlock;
+    const int rb = (D.tiles[k].ny + sfd::kTrBlock - 1) / sfd::kTrBlock;
     if ((st = add({sfd::kRoleTiles, 0, cb * rb, k, cb, 0, nullptr})) != SFD_OK) return st;
   }
   return flush();
@@ -562,18 +546,12 @@ sfd_status launch_rows(const CallDescs& D, const sfd::RowJob* d_rows, int first,
   return SFD_OK;
 }
 
-// Tile widths and strides that follow the schedule (the allocations were
-// sized for every tile width, so offsets never move).
+// Tile counts that follow the schedule (the allocations were sized for every
+// tile width, so offsets never move).
 void apply_schedule(sfd_plan_s* P) {
-  for (TileLayout& T : P->tiles) {
-    T.G = P->tile_g(T.L, true);
-    T.stride = tile_stride(P->holo.ny, T.G);
-  }
   for (size_t v = 0; v < P->blay.size(); ++v) {
     sfd_plan_s::BwdLayout& B = P->blay[v];
     const sfd_grid& o = P->views[v].out;
-    B.ga = P->tile_g(P->lay[v].ly, true);
-    B.gtile_stride = tile_stride(o.ny, B.ga);
     const int gr = P->tile_g(P->lay[v].lx, false);
     B.nt_r = (o.ny + gr - 1) / gr;
     B.nt_a = (P->holo.ny + gr - 1) / gr;
@@ -700,15 +678,14 @@ sfd_status run_backward(sfd_plan_s* P, void* const* grad_out, void* const* field
     D.axis.push_back(a.j);
     D.axis_L.push_back(a.L);
   }
-  for (int L : P->lengths)
-    for (int sp = 0; sp < 2; ++sp) {
-      sfd::TwiddleJob t{};
-      t.tw = reinterpret_cast<float2*>(ws + (sp ? P->spec_tw_off.at(L) : P->tw_off.at(L)));
-      t.L = L;
-      t.count = sfd::twiddle_len(L, sp != 0);
-      t.spec = sp;
-      D.tw.push_back(t);
-    }
+  for (int L : P->lengths) {
+    sfd::TwiddleJob t{};
+    t.tw = reinterpret_cast<float2*>(ws + P->tw_off.at(L));
+    t.L = L;
+    t.count = sfd::twiddle_len(L, false);
+    t.spec = 0;
+    D.tw.push_back(t);
+  }
 
   // Tiles: the hologram's (for the z-moment passes) and each view's gradient.
   if (want_z)
@@ -718,8 +695,7 @@ sfd_status run_backward(sfd_plan_s* P, void* const* grad_out, void* const* field
       j.out = ws + T.off;
       j.nx = h.nx;
       j.ny = h.ny;
-      j.G = T.G;
-      j.tile_stride = T.stride;
+      j.ld = col_ld(h.ny);
       j.complex_in = 1;
       D.tiles.push_back(j);
     }
@@ -732,8 +708,7 @@ sfd_status run_backward(sfd_plan_s* P, void* const* grad_out, void* const* field
     j.out = ws + B.gtile;
     j.nx = P->views[v].out.nx;
     j.ny = P->views[v].out.ny;
-    j.G = B.ga;
-    j.tile_stride = B.gtile_stride;
+    j.ld = col_ld(P->views[v].out.ny);
     j.complex_in = 1;
     D.tiles.push_back(j);
   }
@@ -769,12 +744,14 @@ sfd_status run_backward(sfd_plan_s* P, void* const* grad_out, void* const* field
       j.mode = sfd::kUsePost | sfd::kOutField;
       return j;
     };
-    cols.push_back({L.ly, col(ws + B.gtile, B.gtile_stride, B.wa, ldo, B.preya, B.hya, B.postya, w.out.nx, w.out.ny,
+    cols.push_back({L.ly, col(ws + B.gtile, col_ld(w.out.ny), B.wa, ldo, B.preya, B.hya, B.postya, w.out.nx, w.out.ny,
                              h.ny)});
     if (want_z) {
       const TileLayout& T = P->tiles[L.tile];
-      cols.push_back({L.ly, col(ws + T.off, T.stride, B.wf, ldh, B.preyf, B.hyf, B.postyf, h.nx, h.ny, w.out.ny)});
-      cols.push_back({L.ly, col(ws + T.off, T.stride, B.wm, ldh, B.preym, B.hyf, B.postyf, h.nx, h.ny, w.out.ny)});
+      cols.push_back({L.ly, col(ws + T.off, col_ld(h.ny), B.wf, ldh, B.preyf, B.hyf, B.postyf, h.nx, h.ny,
+                                w.out.ny)});
+      cols.push_back({L.ly, col(ws + T.off, col_ld(h.ny), B.wm, ldh, B.preym, B.hyf, B.postyf, h.nx, h.ny,
+                                w.out.ny)});
     }
     auto row = [&](size_t in, int in_ld, size_t pre, size_t H, size_t post, int n_rows, int n_in, int n_out,
                    int32_t mode, size_t partial) {
@@ -992,22 +969,17 @@ sfd_status sfd_plan(sfd_plan_t* plan, double wavelength, const sfd_grid* holo_gr
   ls.erase(std::unique(ls.begin(), ls.end()), ls.end());
   P->lengths = ls;
 
-  // Column-tile copies: one per (hologram, column-pass length) the views need.
+  // Column-major copies: one per hologram a view reads.
   const size_t in_elem = (flags & SFD_IN_REAL_F32) ? sizeof(float) : sizeof(float2);
   P->lay.resize(n_views);
+  std::vector<int> copy_of(n_holo, -1);
   for (int v = 0; v < n_views; ++v) {
-    const int ly = choose_length(h.ny, views[v].out.ny);
-    int found = -1;
-    for (size_t k = 0; k < P->tiles.size(); ++k)
-      if (P->tiles[k].holo == views[v].holo && P->tiles[k].L == ly) found = (int)k;
-    if (found < 0) {
-      TileLayout T{};
-      T.holo = views[v].holo;
-      T.L = ly;
-      P->tiles.push_back(T);
-      found = (int)P->tiles.size() - 1;
+    const int hv = views[v].holo;
+    if (copy_of[hv] < 0) {
+      copy_of[hv] = (int)P->tiles.size();
+      P->tiles.push_back(TileLayout{hv, 0});
     }
-    P->lay[v].tile = found;
+    P->lay[v].tile = copy_of[hv];
   }
 
   size_t off = 0;
@@ -1016,13 +988,11 @@ sfd_status sfd_plan(sfd_plan_t* plan, double wavelength, const sfd_grid* holo_gr
   off += P->desc_bytes;
   for (TileLayout& T : P->tiles) {
     T.off = off;
-    off += align_up(tile_alloc_elems(h.nx, h.ny, T.L) * in_elem);
+    off += align_up((size_t)h.nx * col_ld(h.ny) * in_elem);
   }
   for (int L : ls) {
     P->tw_off[L] = off;
     off += align_up(sizeof(float2) * std::max(1, sfd::twiddle_len(L, false)));
-    P->spec_tw_off[L] = off;
-    off += align_up(sizeof(float2) * std::max(1, sfd::twiddle_len(L, true)));
   }
   for (int v = 0; v < n_views; ++v) {
     ViewLayout& L = P->lay[v];
@@ -1078,7 +1048,7 @@ sfd_status sfd_plan(sfd_plan_t* plan, double wavelength, const sfd_grid* holo_gr
       B.hyf = take(c8 * ly);
       B.hxa = take(c8 * lx);
       B.hya = take(c8 * ly);
-      B.gtile = take(c8 * tile_alloc_elems(o.nx, o.ny, ly));
+      B.gtile = take(c8 * (size_t)o.nx * col_ld(o.ny));
       B.wf = take(c8 * (size_t)o.ny * inter_ld(h.nx));
       B.wm = take(c8 * (size_t)o.ny * inter_ld(h.nx));
       B.wa = take(c8 * (size_t)h.ny * inter_ld(o.nx));
@@ -1170,7 +1140,8 @@ sfd_status sfd_reconstruct(sfd_plan_t plan, const void* holo, const double* z_or
     // Baseline: every stage launched for one view at a time (axis jobs stay
     // in view order: 2v = x, 2v + 1 = y).
     for (int v = 0; v < V; ++v) {
-      if ((st = launch_setup_for(plan, D, ws, d_axis, d_tw, d_tiles, 2 * v, 2, false, plan->lay[v].tile, 1, stream)) !=
+      if ((st = launch_setup_for(plan, D, ws, d_axis, d_tw, d_tiles, 2 * v, 2, false, plan->lay[v].tile, 1,
+                                 stream)) !=
           SFD_OK)
         return st;
       if ((st = launch_rows(D, d_rows, v, 1, plan, ws, stream, SFD_KERNEL_PASS_Y)) != SFD_OK) return st;

@@ -101,20 +101,19 @@ struct TwiddleJob {
   int32_t pad_;
 };
 
-// A hologram rewritten as column tiles for the column pass: tile c holds
-// columns [c G, c G + G) as [n][g] (n < ny, g < G, zero past nx), tiles
-// tile_stride elements apart.  The column pass then reads each workgroup's
-// G columns as one contiguous block.
+// A grid rewritten column-major for the column pass: out[c * ld + n] =
+// in[n * nx + c] (n < ny, c < nx), so that each column is contiguous and the
+// column pass loads it like a row.
 struct TileJob {
   const void* in;   // [ny][nx] float32 or complex64
-  const float* in2; // complex input only: if set, the tile holds 2 in2 * in (a gradient
+  const float* in2; // complex input only: if set, the copy holds 2 in2 * in (a gradient
                     // with respect to the field formed from dL/dI and the field)
   void* out;
-  int32_t nx, ny, G;
-  int32_t tile_stride;  // elements
+  int32_t nx, ny;
+  int32_t ld;       // elements between consecutive columns of the copy (>= ny)
   int32_t complex_in;
-  int32_t pad_;
 };
+constexpr int kTrBlock = 32;  // square block one setup workgroup transposes
 
 // z-derivative of one view from the reduction partials (see sfd_backward):
 //   dL/dz = Re[(i k - 1/z) S1 - (i pi / (lambda z^2)) (S2 - 2 S3 - 2 S4 + S5)]
@@ -161,8 +160,6 @@ struct SetupArgs {
   SetupRole roles[kMaxSetupRoles];
 };
 constexpr int kSetupThreads = 256;
-constexpr int kTileRows = 8;     // hologram rows per tile workgroup
-constexpr int kTileCols = 256;   // hologram columns per tile workgroup
 
 // Host-side launchers (defined in sfd_kernels.hip).
 hipError_t launch_setup(const SetupArgs& args, hipStream_t s);

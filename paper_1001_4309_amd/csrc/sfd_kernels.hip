@@ -166,7 +166,7 @@ __device__ __forceinline__ void setup_spectrum(const SetupArgs& A, const SetupRo
 #pragma unroll
   for (int i = 0; i < R; ++i) v[i] = hs[g * L + t + TPR * i];
   __syncthreads();
-  fft_row<P, false, kSplit>(v, static_cast<char*>(lds) + g * row_lds_bytes<L, kSplit>(), t, Ro.tw);
+  fft_row<P, false, kSplit, true>(v, static_cast<char*>(lds) + g * row_lds_bytes<L, kSplit>(), t, nullptr);
   const int k = rb * GS + g;
   if (k >= Ro.c) return;
   const AxisJob& J = A.axis[Ro.b + k];
@@ -175,17 +175,19 @@ __device__ __forceinline__ void setup_spectrum(const SetupArgs& A, const SetupRo
   for (int i = 0; i < R; ++i) gst(J.H, (unsigned)(t + TPR * i), make_float2(v[i].x * inv, v[i].y * inv));
 }
 
-// Hologram -> column tiles (see TileJob): full-row reads of a kTileRows x
-// kTileCols block, then per tile kTileRows * G contiguous elements.
+// Column-major copy (see TileJob) of one kTrBlock x kTrBlock block: rows of
+// the block are read with consecutive threads on consecutive columns, and
+// written back as columns with consecutive threads on consecutive rows.
 template <typename T>
-__device__ __forceinline__ void tile_block(const TileJob& J, int r0, int c0, T* buf) {
-  constexpr int RB = kTileRows, CB = kTileCols, SP = CB + 1;
+__device__ __forceinline__ void transpose_block(const TileJob& J, int r0, int c0, T* buf) {
+  constexpr int B = kTrBlock, SP = B + 1, STEP = kSetupThreads / B;
   const T* in = static_cast<const T*>(J.in);
   T* out = static_cast<T*>(J.out);
-  const int tid = threadIdx.x;
+  const int lo = threadIdx.x % B, hi = threadIdx.x / B;
 #pragma unroll
-  for (int rr = 0; rr < RB; ++rr) {
-    const int n = r0 + rr, c = c0 + tid;
+  for (int k = 0; k < B / STEP; ++k) {
+    const int rr = hi + STEP * k;
+    const int n = r0 + rr, c = c0 + lo;
     T v{};
     if (n < J.ny && c < J.nx) {
       v = gld(in, (unsigned)(n * J.nx + c));
@@ -196,20 +198,14 @@ __device__ __forceinline__ void tile_block(const TileJob& J, int r0, int c0, T* 
         }
       }
     }
-    buf[rr * SP + tid] = v;
+    buf[rr * SP + lo] = v;
   }
   __syncthreads();
-  const int G = J.G;
 #pragma unroll
-  for (int it = 0; it < RB; ++it) {
-    const int e = tid + it * CB;
-    const int g = e % G;
-    const int rr = (e / G) % RB;
-    const int ct = e / (G * RB);
-    const int n = r0 + rr;
-    const int tile = c0 / G + ct;
-    if (n < J.ny && tile * G < J.nx)
-      gst(out, (unsigned)(tile * J.tile_stride + n * G + g), buf[rr * SP + ct * G + g]);
+  for (int k = 0; k < B / STEP; ++k) {
+    const int cc = hi + STEP * k;
+    const int n = r0 + lo, c = c0 + cc;
+    if (n < J.ny && c < J.nx) gst(out, (unsigned)(c * J.ld + n), buf[lo * SP + cc]);
   }
 }
 
@@ -221,7 +217,7 @@ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 // LDS of a setup launch whose spectra have lengths <= MAXL.
 template <int MAXL>
 constexpr int setup_lds_bytes() {
-  int b = kTileRows * (kTileCols + 1) * 8;
+  int b = kTrBlock * (kTrBlock + 1) * 8;
   if (MAXL >= 64) b = cmax(b, spectrum_lds_bytes<64>());
   if (MAXL >= 128) b = cmax(b, spectrum_lds_bytes<128>());
   if (MAXL >= 256) b = cmax(b, spectrum_lds_bytes<256>());
@@ -277,10 +273,10 @@ __global__ void __launch_bounds__(kSetupThreads) setup_kernel(const SetupArgs A)
     }
     case kRoleTiles: {
       const TileJob& T = A.tiles[Ro.a];
-      const int c0 = (rb % Ro.b) * kTileCols;
-      const int r0 = (rb / Ro.b) * kTileRows;
-      if (T.complex_in) tile_block<float2>(T, r0, c0, reinterpret_cast<float2*>(lds));
-      else tile_block<float>(T, r0, c0, reinterpret_cast<float*>(lds));
+      const int c0 = (rb % Ro.b) * kTrBlock;
+      const int r0 = (rb / Ro.b) * kTrBlock;
+      if (T.complex_in) transpose_block<float2>(T, r0, c0, reinterpret_cast<float2*>(lds));
+      else transpose_block<float>(T, r0, c0, reinterpret_cast<float*>(lds));
       break;
     }
     default: break;
@@ -346,10 +342,7 @@ template <int TPR, int R, bool REAL>
 __device__ __forceinline__ void load_row(float2 (&v)[R], const void* in, const float2* pre, int n, int t) {
   if (n == TPR * R / 2) {
 #pragma unroll
-    for (int i = 0; i < R / 2; ++i) {
-      v[i] = pre_times_in<TPR, R, REAL>(in, pre, (unsigned)(t + TPR * i));
-      if ((i & 7) == 7) sched_fence();
-    }
+    for (int i = 0; i < R / 2; ++i) v[i] = pre_times_in<TPR, R, REAL>(in, pre, (unsigned)(t + TPR * i));
 #pragma unroll
     for (int i = R / 2; i < R; ++i) v[i] = make_float2(0.f, 0.f);
     return;
@@ -470,10 +463,7 @@ __global__ void __launch_bounds__((PassShape<L, GR>::THREADS)) __attribute__((am
   const float2* __restrict__ H = J.H;
   sched_fence();
 #pragma unroll
-  for (int i = 0; i < R; ++i) {
-    v[i] = cmul(v[i], gld(H, (unsigned)(t + TPR * i)));
-    if ((i & 7) == 7) sched_fence();
-  }
+  for (int i = 0; i < R; ++i) v[i] = cmul(v[i], gld(H, (unsigned)(t + TPR * i)));
   sched_fence();
   fft_row<PassPlan<L>, true, kSplit>(v, buf, t, tw);
 
@@ -508,10 +498,11 @@ __global__ void __launch_bounds__((PassShape<L, GR>::THREADS)) __attribute__((am
                                                          reinterpret_cast<double*>(lds + G * RB));
 }
 
-// y transforms: column c of the job reads in[n * in_ld + c] for n < n_in and
-// writes out[m * out_ld + c] for m < n_out (complex).  G columns per
-// workgroup go through LDS staging in chunks of L/2 elements, so that each
-// global access covers G consecutive columns.
+// y transforms: column c of the job reads in[c * in_ld + n] for n < n_in
+// (the column-major copy of its grid, see TileJob) and writes
+// out[m * out_ld + c] for m < n_out (complex).  The G columns of a workgroup
+// leave through LDS staging in chunks of L/2 rows, so that each global store
+// covers G consecutive columns.
 template <int L, int GC>
 __global__ void __launch_bounds__((PassShape<L, GC>::THREADS)) __attribute__((amdgpu_waves_per_eu(SFD_COL_WPE))) col_kernel(const PassArgs args, const float2* __restrict__ tw) {
   using S = PassShape<L, GC>;
@@ -527,7 +518,6 @@ __global__ void __launch_bounds__((PassShape<L, GC>::THREADS)) __attribute__((am
   static_assert((G & (G - 1)) == 0, "columns per workgroup must be a power of two");
   __shared__ __align__(16) unsigned char lds[LDS_BYTES];
   float2* st = reinterpret_cast<float2*>(lds);
-  float* stf = reinterpret_cast<float*>(lds);
 
   const int tile = xcd_tile(blockIdx.x, args.total_tiles);
   const int jid = find_job(args, tile);
@@ -540,65 +530,25 @@ __global__ void __launch_bounds__((PassShape<L, GC>::THREADS)) __attribute__((am
   const int in_ld = (int)J.in_ld;
   const float2* __restrict__ pre = J.pre;
   const bool real_in = (J.mode & kInReal) != 0;
-  // Column of the staging loop for this thread (fixed: THREADS is a multiple of G).
+  // Column of the store staging loop for this thread (fixed: THREADS is a multiple of G).
   const int gs = threadIdx.x & (G - 1);
   const bool col_ok = c0 + gs < ncols;
 
+  // Column c0 + g of the column-major input copy, loaded like a row (a
+  // column past the grid's edge computes on the last one and stores nothing).
+  const int cl = c0 + g < ncols ? c0 + g : ncols - 1;
   float2 v[R];
-#pragma unroll
-  for (int c = 0; c < 2; ++c) {
-    const int n_lo = c * C;
-    if (n_lo >= n_in) {
-#pragma unroll
-      for (int i = c * (R / 2); i < (c + 1) * (R / 2); ++i) v[i] = make_float2(0.f, 0.f);
-      continue;
-    }
-    if (c > 0) __syncthreads();
-    // Element e of the chunk is column e % G, row n_lo + e / G; the input is
-    // this workgroup's column tile, so the reads are contiguous.
-    const unsigned tile_base = (unsigned)(c0 / G) * (unsigned)in_ld;
-    if (real_in) {
-      const float* in = static_cast<const float*>(J.in) + tile_base;
-      for (int e = threadIdx.x; e < G * C; e += THREADS) {
-        const int n = n_lo + e / G;
-        const float a = gld(in, (unsigned)((n < n_in ? n : n_in - 1) * G + gs));
-        stf[gs * SST + (n - n_lo)] = n < n_in ? a : 0.f;
-      }
-    } else {
-      const float2* in = static_cast<const float2*>(J.in) + tile_base;
-      for (int e = threadIdx.x; e < G * C; e += THREADS) {
-        const int n = n_lo + e / G;
-        const float2 a = gld(in, (unsigned)((n < n_in ? n : n_in - 1) * G + gs));
-        st[gs * SST + (n - n_lo)] = n < n_in ? a : make_float2(0.f, 0.f);
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = c * (R / 2); i < (c + 1) * (R / 2); ++i) {
-      const int m = t + TPR * i;
-      const float2 p = gld(pre, (unsigned)(m < n_in ? m : n_in - 1));
-      float2 x;
-      if (real_in) {
-        const float a = stf[g * SST + (m - n_lo)];
-        x = make_float2(a * p.x, a * p.y);
-      } else {
-        x = cmul(st[g * SST + (m - n_lo)], p);
-      }
-      v[i] = m < n_in ? x : make_float2(0.f, 0.f);
-      if ((i & 7) == 7) sched_fence();
-    }
-  }
-  __syncthreads();
+  if (real_in)
+    load_row<TPR, R, true>(v, static_cast<const float*>(J.in) + (int64_t)cl * in_ld, pre, n_in, t);
+  else
+    load_row<TPR, R, false>(v, static_cast<const float2*>(J.in) + (int64_t)cl * in_ld, pre, n_in, t);
 
   void* buf = lds + g * RB;
   fft_row<PassPlan<L>, false, kSplit>(v, buf, t, tw);
   const float2* __restrict__ H = J.H;
   sched_fence();
 #pragma unroll
-  for (int i = 0; i < R; ++i) {
-    v[i] = cmul(v[i], gld(H, (unsigned)(t + TPR * i)));
-    if ((i & 7) == 7) sched_fence();
-  }
+  for (int i = 0; i < R; ++i) v[i] = cmul(v[i], gld(H, (unsigned)(t + TPR * i)));
   sched_fence();
   fft_row<PassPlan<L>, true, kSplit>(v, buf, t, tw);
 
