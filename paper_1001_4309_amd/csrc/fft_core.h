@@ -280,10 +280,13 @@ __device__ __forceinline__ int lds_ridx(int t, int i) {
 // (j = t + TPR q) and input k >= 1, exp(-2 pi i k (j mod Ns) / (Ns r)) from
 // the stage's part of the table.  Loaded one stage ahead (before the previous
 // stage's exchange) so that their latency overlaps the LDS round trip.
-// With TWC the twiddles are computed instead (FP32 sincospi of the exact
-// argument k jm / (Ns r)): for a single transform that runs alone, this is
-// faster than waiting for table reads.
-template <int TPR, int R, int r, int Ns, bool TWC = false>
+// Where a transform's twiddles come from: the table in global memory, a copy
+// of it in LDS (same layout), or computed on the fly (FP32 sincospi of the
+// exact argument k jm / (Ns r): for a single transform that runs alone this
+// is faster than waiting for table reads).
+enum TwSrc { kTwGlobal = 0, kTwShared = 1, kTwCompute = 2 };
+
+template <int TPR, int R, int r, int Ns, int TWS = kTwGlobal>
 struct StageTw {
   static constexpr int nb = R / r;
   static constexpr bool any = Ns > 1;
@@ -295,10 +298,12 @@ struct StageTw {
         const unsigned jm = (unsigned)(t + TPR * q) & (unsigned)(Ns - 1);
 #pragma unroll
         for (int k = 1; k < r; ++k) {
-          if constexpr (TWC) {
+          if constexpr (TWS == kTwCompute) {
             float sn, cs;
             sincospif(-2.0f * (float)(k * (int)jm) / (float)(Ns * r), &sn, &cs);
             w[q][k - 1] = make_float2(cs, sn);
+          } else if constexpr (TWS == kTwShared) {
+            w[q][k - 1] = tw[(k - 1) * Ns + (int)jm];
           } else {
             w[q][k - 1] = gld(tw, (unsigned)((k - 1) * Ns) + jm);
           }
@@ -312,9 +317,9 @@ struct StageTw {
 // stage input.  The outputs stay in v (butterfly q's output k in slot
 // q + k nb, which for the last stage is natural order) unless the exchange
 // is complex (not SPLIT), in which case they go straight to the LDS buffer.
-template <int L, int TPR, int r, int Ns, bool INV, bool LAST, bool SPLIT, bool TWC>
+template <int L, int TPR, int r, int Ns, bool INV, bool LAST, bool SPLIT, int TWS>
 __device__ __forceinline__ void stage_compute(float2 (&v)[L / TPR], void* __restrict__ buf, int t,
-                                              const StageTw<TPR, L / TPR, r, Ns, TWC>& W) {
+                                              const StageTw<TPR, L / TPR, r, Ns, TWS>& W) {
   constexpr int R = L / TPR;
   constexpr int nb = R / r;
   static_assert(R % r == 0, "radix must divide the values per thread");
@@ -385,34 +390,34 @@ __device__ __forceinline__ void stage_exchange(float2 (&v)[L / TPR], void* __res
 
 // Stage (Ns, r) with its twiddles W already loaded; loads the next stage's
 // twiddles before this stage's exchange.
-template <int L, int TPR, bool INV, bool SPLIT, bool TWC, int Ns, int OFF, int r, int... rest>
+template <int L, int TPR, bool INV, bool SPLIT, int TWS, int Ns, int OFF, int r, int... rest>
 __device__ __forceinline__ void fft_stages(float2 (&v)[L / TPR], void* buf, int t, const float2* tw,
-                                           const StageTw<TPR, L / TPR, r, Ns, TWC>& W) {
+                                           const StageTw<TPR, L / TPR, r, Ns, TWS>& W) {
   constexpr bool last = sizeof...(rest) == 0;
-  stage_compute<L, TPR, r, Ns, INV, last, SPLIT, TWC>(v, buf, t, W);
+  stage_compute<L, TPR, r, Ns, INV, last, SPLIT, TWS>(v, buf, t, W);
   if constexpr (!last) {
     constexpr int next_off = OFF + (Ns > 1 ? (r - 1) * Ns : 0);
     constexpr int rn = Radices<rest...>::first;
-    StageTw<TPR, L / TPR, rn, Ns * r, TWC> Wn;
+    StageTw<TPR, L / TPR, rn, Ns * r, TWS> Wn;
     Wn.load(t, tw + next_off);
     stage_exchange<L, TPR, r, Ns, SPLIT>(v, buf, t);
-    fft_stages<L, TPR, INV, SPLIT, TWC, Ns * r, next_off, rest...>(v, buf, t, tw, Wn);
+    fft_stages<L, TPR, INV, SPLIT, TWS, Ns * r, next_off, rest...>(v, buf, t, tw, Wn);
   }
 }
 
-template <class P, bool INV, bool SPLIT, bool TWC, int r0, int... Rs>
+template <class P, bool INV, bool SPLIT, int TWS, int r0, int... Rs>
 __device__ __forceinline__ void fft_run(Radices<r0, Rs...>, float2 (&v)[P::R], void* buf, int t, const float2* tw) {
-  const StageTw<P::TPR, P::R, r0, 1, TWC> W0{};  // the first stage has no twiddles
-  fft_stages<P::L, P::TPR, INV, SPLIT, TWC, 1, 0, r0, Rs...>(v, buf, t, tw, W0);
+  const StageTw<P::TPR, P::R, r0, 1, TWS> W0{};  // the first stage has no twiddles
+  fft_stages<P::L, P::TPR, INV, SPLIT, TWS, 1, 0, r0, Rs...>(v, buf, t, tw, W0);
 }
 
 // Forward (INV = false) or unnormalised inverse (INV = true) FFT of one row
 // of shape P.  ``buf`` is the row's LDS exchange buffer
-// (row_lds_bytes<P::L, SPLIT>() bytes); ``tw`` is the twiddle table of P
-// (unused with TWC, which computes the twiddles).
-template <class P, bool INV, bool SPLIT, bool TWC = false>
+// (row_lds_bytes<P::L, SPLIT>() bytes); ``tw`` is the twiddle table of P in
+// global memory (kTwGlobal) or LDS (kTwShared), unused with kTwCompute.
+template <class P, bool INV, bool SPLIT, int TWS = kTwGlobal>
 __device__ __forceinline__ void fft_row(float2 (&v)[P::R], void* buf, int t, const float2* tw) {
-  fft_run<P, INV, SPLIT, TWC>(typename P::Rad{}, v, buf, t, tw);
+  fft_run<P, INV, SPLIT, TWS>(typename P::Rad{}, v, buf, t, tw);
 }
 
 // Twiddle table entry e of a shape's table (layout of TwInfo), evaluated in FP64

@@ -166,7 +166,7 @@ __device__ __forceinline__ void setup_spectrum(const SetupArgs& A, const SetupRo
 #pragma unroll
   for (int i = 0; i < R; ++i) v[i] = hs[g * L + t + TPR * i];
   __syncthreads();
-  fft_row<P, false, kSplit, true>(v, static_cast<char*>(lds) + g * row_lds_bytes<L, kSplit>(), t, nullptr);
+  fft_row<P, false, kSplit, kTwCompute>(v, static_cast<char*>(lds) + g * row_lds_bytes<L, kSplit>(), t, nullptr);
   const int k = rb * GS + g;
   if (k >= Ro.c) return;
   const AxisJob& J = A.axis[Ro.b + k];
@@ -428,6 +428,33 @@ __device__ __forceinline__ void row_reduce(const RowJob& J, const float2 (&v)[R]
   }
 }
 
+// Per-workgroup LDS copies of the transform's twiddle table and of the job's
+// kernel spectrum H (for lengths up to 2048, where both fit beside the
+// exchange buffers): one cooperative load at the start of the workgroup,
+// overlapped with the rows' own loads, replaces the per-stage table reads and
+// the H reads of every row.
+template <int L>
+struct SharedTables {
+  static constexpr bool on = L <= 2048;
+  static constexpr int tw_n = twiddle_entries<PassPlan<L>>();
+  static constexpr int bytes = on ? (tw_n + L) * 8 : 0;
+  static constexpr int src = on ? kTwShared : kTwGlobal;
+};
+
+template <int L, int THREADS>
+__device__ __forceinline__ void stage_tables(float2* tws, float2* hs, const float2* __restrict__ tw,
+                                             const float2* __restrict__ H) {
+  static_assert(SharedTables<L>::tw_n % 2 == 0, "tables are copied two entries at a time");
+  float4* t4 = reinterpret_cast<float4*>(tws);
+  float4* h4 = reinterpret_cast<float4*>(hs);
+  const float4* tg = reinterpret_cast<const float4*>(tw);
+  const float4* hg = reinterpret_cast<const float4*>(H);
+#pragma unroll 4
+  for (int e = threadIdx.x; e < SharedTables<L>::tw_n / 2; e += THREADS) t4[e] = gld(tg, (unsigned)e);
+#pragma unroll 4
+  for (int e = threadIdx.x; e < L / 2; e += THREADS) h4[e] = gld(hg, (unsigned)e);
+}
+
 // x transforms: row r of the job reads in + r * in_ld and writes
 // out + r * out_ld (contiguous), both straight from registers.
 template <int L, int GR>
@@ -437,8 +464,13 @@ __global__ void __launch_bounds__((PassShape<L, GR>::THREADS)) __attribute__((am
   constexpr int R = L / TPR;
   constexpr int G = S::G;
   constexpr int RB = row_lds_bytes<L, kSplit>();
-  // Exchange buffers, then room for the epilogue reduction (4 doubles per wavefront).
-  __shared__ __align__(16) unsigned char lds[G * RB + S::NW * 32];
+  using T = SharedTables<L>;
+  // Shared tables, exchange buffers, then room for the epilogue reduction (4
+  // doubles per wavefront).
+  __shared__ __align__(16) unsigned char lds[T::bytes + G * RB + S::NW * 32];
+  float2* tws = reinterpret_cast<float2*>(lds);
+  float2* hs = tws + T::tw_n;
+  unsigned char* xbuf = lds + T::bytes;
 
   const int tile = xcd_tile(blockIdx.x, args.total_tiles);
   const int jid = find_job(args, tile);
@@ -458,14 +490,19 @@ __global__ void __launch_bounds__((PassShape<L, GR>::THREADS)) __attribute__((am
   else
     load_row<TPR, R, false>(v, static_cast<const float2*>(J.in) + (int64_t)vrow * J.in_ld, J.pre, n_in, t);
 
-  void* buf = lds + g * RB;
-  fft_row<PassPlan<L>, false, kSplit>(v, buf, t, tw);
   const float2* __restrict__ H = J.H;
+  if constexpr (T::on) {
+    stage_tables<L, S::THREADS>(tws, hs, tw, H);
+    __syncthreads();
+  }
+  const float2* twx = T::on ? tws : tw;
+  void* buf = xbuf + g * RB;
+  fft_row<PassPlan<L>, false, kSplit, T::src>(v, buf, t, twx);
   sched_fence();
 #pragma unroll
-  for (int i = 0; i < R; ++i) v[i] = cmul(v[i], gld(H, (unsigned)(t + TPR * i)));
+  for (int i = 0; i < R; ++i) v[i] = cmul(v[i], T::on ? hs[t + TPR * i] : gld(H, (unsigned)(t + TPR * i)));
   sched_fence();
-  fft_row<PassPlan<L>, true, kSplit>(v, buf, t, tw);
+  fft_row<PassPlan<L>, true, kSplit, T::src>(v, buf, t, twx);
 
   const int n_out = J.n_out;
   const int mode = J.mode;
@@ -495,7 +532,7 @@ __global__ void __launch_bounds__((PassShape<L, GR>::THREADS)) __attribute__((am
     }
   }
   if (mode & kReduce) row_reduce<TPR, R, S::NW>(J, v, row, valid, t, tile - args.tile_prefix[jid],
-                                                         reinterpret_cast<double*>(lds + G * RB));
+                                                         reinterpret_cast<double*>(xbuf + G * RB));
 }
 
 // y transforms: column c of the job reads in[c * in_ld + n] for n < n_in
@@ -514,10 +551,15 @@ __global__ void __launch_bounds__((PassShape<L, GC>::THREADS)) __attribute__((am
   constexpr int C = L / 2;    // staging chunk along the transform
   constexpr int SST = C + 9;  // staging stride per column (elements)
   constexpr int STAGE_BYTES = G * SST * 8;
-  constexpr int LDS_BYTES = G * RB > STAGE_BYTES ? G * RB : STAGE_BYTES;
+  constexpr int XCH_BYTES = G * RB > STAGE_BYTES ? G * RB : STAGE_BYTES;
+  using T = SharedTables<L>;
   static_assert((G & (G - 1)) == 0, "columns per workgroup must be a power of two");
-  __shared__ __align__(16) unsigned char lds[LDS_BYTES];
-  float2* st = reinterpret_cast<float2*>(lds);
+  // Shared tables, then the exchange buffers (reused as the store staging).
+  __shared__ __align__(16) unsigned char lds[T::bytes + XCH_BYTES];
+  float2* tws = reinterpret_cast<float2*>(lds);
+  float2* hs = tws + T::tw_n;
+  unsigned char* xbuf = lds + T::bytes;
+  float2* st = reinterpret_cast<float2*>(xbuf);
 
   const int tile = xcd_tile(blockIdx.x, args.total_tiles);
   const int jid = find_job(args, tile);
@@ -543,14 +585,19 @@ __global__ void __launch_bounds__((PassShape<L, GC>::THREADS)) __attribute__((am
   else
     load_row<TPR, R, false>(v, static_cast<const float2*>(J.in) + (int64_t)cl * in_ld, pre, n_in, t);
 
-  void* buf = lds + g * RB;
-  fft_row<PassPlan<L>, false, kSplit>(v, buf, t, tw);
   const float2* __restrict__ H = J.H;
+  if constexpr (T::on) {
+    stage_tables<L, THREADS>(tws, hs, tw, H);
+    __syncthreads();
+  }
+  const float2* twx = T::on ? tws : tw;
+  void* buf = xbuf + g * RB;
+  fft_row<PassPlan<L>, false, kSplit, T::src>(v, buf, t, twx);
   sched_fence();
 #pragma unroll
-  for (int i = 0; i < R; ++i) v[i] = cmul(v[i], gld(H, (unsigned)(t + TPR * i)));
+  for (int i = 0; i < R; ++i) v[i] = cmul(v[i], T::on ? hs[t + TPR * i] : gld(H, (unsigned)(t + TPR * i)));
   sched_fence();
-  fft_row<PassPlan<L>, true, kSplit>(v, buf, t, tw);
+  fft_row<PassPlan<L>, true, kSplit, T::src>(v, buf, t, twx);
 
   const int n_out = J.n_out;
   if (J.mode & kUsePost) {
