@@ -61,6 +61,96 @@ def pass_costs(w, plan):
     return cost
 
 
+KERNEL_SOURCES = ("paper_1001_4309_amd/csrc/sfd_kernels.hip", "paper_1001_4309_amd/csrc/fft_core.h",
+                  "paper_1001_4309_amd/csrc/sfd_internal.h")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def kernel_name(kind: str, L: int, g: int) -> str:
+    return f"{'row' if kind == 'pass_x' else 'col'}_kernel<{L}, {g}>"
+
+
+def traffic_file(config: int) -> str:
+    return os.path.join(ROOT, "profiles", f"pass_kernels_traffic_config{config}.txt")
+
+
+def read_traffic(config: int, name: str):
+    """HBM bytes per launch of kernel ``name`` from the committed counter
+    summary, or None when there is none or the kernel sources have changed
+    since the counters were taken."""
+    path = traffic_file(config)
+    if not os.path.exists(path):
+        return None
+    fields, kernels = {}, {}
+    for line in open(path):
+        line = line.strip()
+        if line.startswith("kernel:"):
+            k, _, rest = line[len("kernel:"):].partition("|")
+            kernels[k.strip()] = dict(kv.split("=") for kv in rest.split())
+        elif ":" in line and not line.startswith("#"):
+            a, _, b = line.partition(":")
+            fields[a.strip()] = b.strip()
+    if fields.get("source-sha256") != kernel_source_hash() or name not in kernels:
+        return None
+    k = kernels[name]
+    return (float(k["fetch_kib"]) * float(fields["fetch-factor"]) +
+            float(k["write_kib"]) * float(fields["write-factor"])) * 1024.0
+
+
+def summarize_pmc(fetch_dir: str, write_dir: str, config: int, copy_mib: int, command: str) -> None:
+    """Write the per-kernel traffic summary from two rocprofv3 --pmc runs
+    (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch).  The factors scale the
+    counters to bytes: a plain device copy of ``copy_mib`` MiB per run reads
+    and writes that much."""
+    import csv
+    import glob
+
+    def per_kernel(d, counter):
+        acc = {}
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for row in csv.DictReader(open(f)):
+                if row["Counter_Name"] != counter:
+                    continue
+                name = row["Kernel_Name"].replace("void ", "").replace("sfd::", "")
+                name = name.split("(")[0]
+                key = row.get("Dispatch_Id") or row.get("Correlation_Id")
+                acc.setdefault(name, {}).setdefault(key, 0.0)
+                acc[name][key] += float(row["Counter_Value"])
+        return {k: (sum(v.values()) / len(v), len(v)) for k, v in acc.items()}
+
+    fetch, write = per_kernel(fetch_dir, "FETCH_SIZE"), per_kernel(write_dir, "WRITE_SIZE")
+    copy = [k for k in fetch if "copyBuffer" in k]
+    # The calibration copy is split into equal dispatches: total KiB / copied KiB.
+    f_copy = sum(v * n for v, n in [fetch[k] for k in copy])
+    w_copy = sum(v * n for v, n in [write[k] for k in copy if k in write])
+    ff = copy_mib * 1024.0 / f_copy
+    wf = copy_mib * 1024.0 / w_copy
+    lines = [f"# rocprofv3 FETCH_SIZE / WRITE_SIZE per dispatch (KiB), workload config {config}",
+             f"# command: {command}",
+             f"source-sha256: {kernel_source_hash()}",
+             f"fetch-factor: {ff:.4f}",
+             f"write-factor: {wf:.4f}",
+             f"# calibration: a {copy_mib} MiB device copy read {f_copy:.0f} KiB on FETCH_SIZE and wrote "
+             f"{w_copy:.0f} KiB on WRITE_SIZE"]
+    for k in sorted(fetch):
+        if "copyBuffer" in k or k not in write or "elementwise" in k:
+            continue
+        (fk, n), (wk, _) = fetch[k], write[k]
+        lines.append(f"kernel: {k} | fetch_kib={fk:.1f} write_kib={wk:.1f} dispatches={n} "
+                     f"hbm_mib={(fk * ff + wk * wf) / 1024:.2f}")
+    with open(traffic_file(config), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def cpu_baseline(w, seconds: float):
     import numpy as np
     import threadpoolctl
@@ -106,9 +196,18 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tile widths")
+    ap.add_argument("--schedule", default="",
+                    help="tile widths to use instead of autotuning, e.g. col2048=4,row2048=4")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the traffic summary of two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--pmc-command", default="", help="command recorded in the traffic summary")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (calibrates traffic counters)")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.config, args.calib_copy_mib,
+                      args.pmc_command)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -139,7 +238,12 @@ def main():
     plan = sfd.Plan(w.wavelength, w.holo_grid, len(w.holograms), w.views, device=dev)
     outs = plan.new_outputs()
     nv = len(w.views)
-    if not args.no_autotune:
+    if args.schedule:
+        for item in args.schedule.split(","):
+            key, g = item.split("=")
+            col = key.startswith("col")
+            plan.set_schedule(int(key[3:]), col, int(g))
+    elif not args.no_autotune:
         plan.autotune(holo, reps=10, outs=outs)
     schedule = {f"{k[0]}{k[1]}": g for k, g in sorted(plan.schedule().items())}
     log("schedule (tile widths):", schedule)
@@ -168,9 +272,13 @@ def main():
     avg_s = tot_ms / n_launch / 1e3
     launches_per_step = n_launch / prof_steps
     flops = costs[dom][1] / launches_per_step
+    lx0, ly0 = plan.lengths(0)
+    dom_L = lx0 if dom == "pass_x" else ly0
+    dom_name = kernel_name(dom, dom_L, plan.schedule()[("row" if dom == "pass_x" else "col", dom_L)])
+    traffic = read_traffic(args.config, dom_name)  # HBM bytes per launch, from the committed counters
     roofline = {"bound": "alu", "achieved": flops / avg_s / 1e12, "peak": FP32_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": flops / avg_s / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
-                "traffic": None, "kernel": dom, "avg_launch_us": avg_s * 1e6,
+                "traffic": traffic, "kernel": dom_name, "avg_launch_us": avg_s * 1e6,
                 "algorithmic_flops_per_launch": flops,
                 "algorithmic_bytes_per_launch": costs[dom][0] / launches_per_step}
     step_bytes = costs["pass_x"][0] + costs["pass_y"][0]
