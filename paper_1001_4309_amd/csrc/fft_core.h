@@ -281,10 +281,12 @@ __device__ __forceinline__ int lds_ridx(int t, int i) {
 // the stage's part of the table.  Loaded one stage ahead (before the previous
 // stage's exchange) so that their latency overlaps the LDS round trip.
 // Where a transform's twiddles come from: the table in global memory, a copy
-// of it in LDS (same layout), or computed on the fly (FP32 sincospi of the
-// exact argument k jm / (Ns r): for a single transform that runs alone this
-// is faster than waiting for table reads).
-enum TwSrc { kTwGlobal = 0, kTwShared = 1, kTwCompute = 2 };
+// of it in LDS (same layout), computed on the fly (FP32 sincospi of the exact
+// argument k jm / (Ns r)), or computed from one sincospi per butterfly with
+// the powers w^k formed by squarings and products (at most 2 log2 r complex
+// multiplications deep, so a few FP32 ulps).  The computed forms serve single
+// transforms that run alone, where waiting for table reads would dominate.
+enum TwSrc { kTwGlobal = 0, kTwShared = 1, kTwCompute = 2, kTwPower = 3 };
 
 template <int TPR, int R, int r, int Ns, int TWS = kTwGlobal>
 struct StageTw {
@@ -292,7 +294,30 @@ struct StageTw {
   static constexpr bool any = Ns > 1;
   float2 w[any ? nb : 1][any ? r - 1 : 1];
   __device__ __forceinline__ void load(int t, const float2* __restrict__ tw) {
-    if constexpr (any) {
+    if constexpr (any && TWS == kTwPower) {
+#pragma unroll
+      for (int q = 0; q < nb; ++q) {
+        const unsigned jm = (unsigned)(t + TPR * q) & (unsigned)(Ns - 1);
+        float sn, cs;
+        sincospif(-2.0f * (float)jm / (float)(Ns * r), &sn, &cs);
+        float2 p2[5];  // w^(2^b)
+        p2[0] = make_float2(cs, sn);
+#pragma unroll
+        for (int b = 1; b < 5; ++b) p2[b] = cmul(p2[b - 1], p2[b - 1]);
+#pragma unroll
+        for (int k = 1; k < r; ++k) {
+          float2 acc = make_float2(1.f, 0.f);
+          bool first = true;
+#pragma unroll
+          for (int b = 0; b < 5; ++b)
+            if ((k >> b) & 1) {
+              acc = first ? p2[b] : cmul(acc, p2[b]);
+              first = false;
+            }
+          w[q][k - 1] = acc;
+        }
+      }
+    } else if constexpr (any) {
 #pragma unroll
       for (int q = 0; q < nb; ++q) {
         const unsigned jm = (unsigned)(t + TPR * q) & (unsigned)(Ns - 1);

@@ -379,13 +379,14 @@ sfd_status build_descs(sfd_plan_s* P, const void* holo, const double* z, void* c
     jc.mode = (in_real ? sfd::kInReal : 0) | (field ? sfd::kUsePost : 0) | sfd::kOutField;
     jc.in = ws + P->tiles[L.tile].off;
     jc.in_ld = col_ld(h.ny);
+    jc.colscale = reinterpret_cast<const float2*>(ws + L.prex);
     py.push_back({L.ly, jc});
 
     sfd::RowJob jr{};
     jr.in = ws + L.inter;
     jr.out = field ? out[inten ? V + v : v] : out[v];
     jr.out2 = (field && inten) ? static_cast<float*>(out[v]) : nullptr;
-    jr.pre = reinterpret_cast<const float2*>(ws + L.prex);
+    jr.pre = nullptr;  // the column pass applied pre_x (constant along each column)
     jr.H = reinterpret_cast<const float2*>(ws + L.hx);
     jr.post = field ? reinterpret_cast<const float2*>(ws + L.postx) : nullptr;
     // With the field written, |c|^2 is already inside it (c rides on post).

@@ -49,9 +49,12 @@ struct RowJob {
   const void* in;      // float32 (kInReal) or complex64
   void* out;           // complex64, or float32 when only the intensity is written
   float* out2;         // float32 intensity when both outputs are written, else nullptr
-  const float2* pre;   // [n_in]
+  const float2* pre;   // [n_in], or nullptr when the input already carries it
   const float2* H;     // [L]
   const float2* post;  // [n_out] or nullptr
+  // Column pass only, or nullptr: output column c is multiplied by colscale[c]
+  // (the next pass's pre-chirp, which is constant along a column).
+  const float2* colscale;
   float iscale;        // intensity scale
   int32_t n_rows, n_in, n_out;
   int64_t in_ld, out_ld;

@@ -26,11 +26,19 @@ namespace sfd {
 
 // exp(i pi v) with v reduced to [-1, 1] in FP64 first, then evaluated in FP64
 // and rounded once to complex64.
+// exp(i pi v) for a large phase v (in half-turns).  The reduction to
+// [-1, 1] is done in FP64, exact enough for phases of 10^5 half-turns and
+// more.  The reduced argument r is split as r_hi + r_lo with r_hi its FP32
+// rounding; FP32 sin/cos of pi r_hi and the first-order correction for
+// pi r_lo (|pi r_lo| < 1e-7, so the dropped second-order term is ~1e-14)
+// give the FP32 result at FP32 sin/cos accuracy without FP64 trigonometry.
 __device__ __forceinline__ float2 cispi_f64(double v) {
   const double r = v - 2.0 * rint(0.5 * v);
-  double s, c;
-  sincospi(r, &s, &c);
-  return make_float2(static_cast<float>(c), static_cast<float>(s));
+  const float rh = static_cast<float>(r);
+  const float rl = static_cast<float>((r - static_cast<double>(rh)) * M_PI);
+  float s, c;
+  sincospif(rh, &s, &c);
+  return make_float2(fmaf(-s, rl, c), fmaf(c, rl, s));
 }
 
 // The same phase carried entirely in FP32 (comparison variant).
@@ -134,7 +142,8 @@ constexpr bool kSplit = true;
 // Spectrum: H = FFT_L(h) / L for GS axis jobs of length L per workgroup (one,
 // or as many as fill the workgroup when a transform needs 128+ threads).  All
 // threads first evaluate h of Eq. (4) (FP64 phase) into LDS, then the
-// transform threads run the FFT with computed twiddles; this role depends on
+// transform threads run the FFT with computed twiddles (a lone transform
+// would otherwise wait on table reads at every stage); this role depends on
 // no other.
 template <int L>
 struct SpecShape {
@@ -152,12 +161,17 @@ __device__ __forceinline__ void setup_spectrum(const SetupArgs& A, const SetupRo
   constexpr int R = P::R;
   constexpr int GS = SpecShape<L>::GS;
   float2* hs = static_cast<float2*>(lds);
-  for (int e = threadIdx.x; e < GS * L; e += kSetupThreads) {
-    const int g = e / L;
-    const int k = rb * GS + g;
-    float2 h = make_float2(0.f, 0.f);
-    if (k < Ro.c) h = kernel_value(A.axis[Ro.b + k], e - g * L);
-    hs[e] = h;
+  // The job is the same for every thread of a transform: its fields are read
+  // once (scalar loads) before the loop rather than per element.
+#pragma unroll
+  for (int gj = 0; gj < GS; ++gj) {
+    const int k = rb * GS + gj;
+    if (k < Ro.c) {
+      const AxisJob J = A.axis[Ro.b + k];
+      for (int i = threadIdx.x; i < L; i += kSetupThreads) hs[gj * L + i] = kernel_value(J, i);
+    } else {
+      for (int i = threadIdx.x; i < L; i += kSetupThreads) hs[gj * L + i] = make_float2(0.f, 0.f);
+    }
   }
   __syncthreads();
   const int g = threadIdx.x / TPR;
@@ -301,6 +315,7 @@ struct PassShape {
   static_assert(THREADS % 64 == 0 && THREADS <= 1024, "a pass workgroup is 1 to 16 whole wavefronts");
 };
 
+
 // Map a workgroup to a tile so that consecutive tiles (which touch adjacent
 // pieces of the same cache lines) run on the same XCD: workgroups are
 // dispatched round-robin over the 8 XCDs.
@@ -324,25 +339,25 @@ __device__ __forceinline__ int find_job(const PassArgs& args, int tile) {
 // it, in scalar registers).
 __device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
-// v[i] = in[t + TPR i] * pre[t + TPR i] for t + TPR i < n, zero beyond: the
-// padded, pre-chirped row (n >= 1).  The common case n = L/2 (the paper's
-// doubled grid) is straight-line code; otherwise loads go to a clamped index
-// (so they still issue back to back) and the padding is selected to zero.
-template <int TPR, int R, bool REAL>
+// The padded, pre-chirped row (n >= 1).  The common case n = L/2 (the
+// paper's doubled grid) is straight-line code; otherwise loads go to a
+// clamped index (so they still issue back to back) and the padding is
+// selected to zero.
+template <bool REAL, bool PRE>
 __device__ __forceinline__ float2 pre_times_in(const void* in, const float2* pre, unsigned m) {
+  float2 x;
+  if constexpr (REAL) x = make_float2(gld(static_cast<const float*>(in), m), 0.f);
+  else x = gld(static_cast<const float2*>(in), m);
+  if constexpr (!PRE) return x;
   const float2 p = gld(pre, m);
-  if constexpr (REAL) {
-    const float a = gld(static_cast<const float*>(in), m);
-    return make_float2(a * p.x, a * p.y);
-  } else {
-    return cmul(gld(static_cast<const float2*>(in), m), p);
-  }
+  if constexpr (REAL) return make_float2(x.x * p.x, x.x * p.y);
+  else return cmul(x, p);
 }
-template <int TPR, int R, bool REAL>
-__device__ __forceinline__ void load_row(float2 (&v)[R], const void* in, const float2* pre, int n, int t) {
+template <int TPR, int R, bool REAL, bool PRE>
+__device__ __forceinline__ void load_row_t(float2 (&v)[R], const void* in, const float2* pre, int n, int t) {
   if (n == TPR * R / 2) {
 #pragma unroll
-    for (int i = 0; i < R / 2; ++i) v[i] = pre_times_in<TPR, R, REAL>(in, pre, (unsigned)(t + TPR * i));
+    for (int i = 0; i < R / 2; ++i) v[i] = pre_times_in<REAL, PRE>(in, pre, (unsigned)(t + TPR * i));
 #pragma unroll
     for (int i = R / 2; i < R; ++i) v[i] = make_float2(0.f, 0.f);
     return;
@@ -350,10 +365,17 @@ __device__ __forceinline__ void load_row(float2 (&v)[R], const void* in, const f
 #pragma unroll
   for (int i = 0; i < R; ++i) {
     const int m = t + TPR * i;
-    const float2 x = pre_times_in<TPR, R, REAL>(in, pre, (unsigned)(m < n ? m : n - 1));
+    const float2 x = pre_times_in<REAL, PRE>(in, pre, (unsigned)(m < n ? m : n - 1));
     v[i] = m < n ? x : make_float2(0.f, 0.f);
     if ((i & 7) == 7) sched_fence();
   }
+}
+// v[i] = in[t + TPR i] (times pre[t + TPR i] unless pre is null) for
+// t + TPR i < n, zero beyond.
+template <int TPR, int R, bool REAL>
+__device__ __forceinline__ void load_row(float2 (&v)[R], const void* in, const float2* pre, int n, int t) {
+  if (pre) load_row_t<TPR, R, REAL, true>(v, in, pre, n, t);
+  else load_row_t<TPR, R, REAL, false>(v, in, pre, n, t);
 }
 
 // Epilogue reduction of the row kernel (see RowJob): FP64 per thread, then
@@ -607,6 +629,11 @@ __global__ void __launch_bounds__((PassShape<L, GC>::THREADS)) __attribute__((am
       const int m = t + TPR * i;
       if (TPR * (i + 1) <= n_out || m < n_out) v[i] = cmul(v[i], gld(post, (unsigned)m));
     }
+  }
+  if (J.colscale) {
+    const float2 cs = gld(J.colscale, (unsigned)cl);
+#pragma unroll
+    for (int i = 0; i < R; ++i) v[i] = cmul(v[i], cs);
   }
   float2* out = static_cast<float2*>(J.out) + c0 + gs;
   const int out_ld = (int)J.out_ld;
