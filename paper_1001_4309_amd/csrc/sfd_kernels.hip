@@ -162,12 +162,16 @@ __device__ __forceinline__ void setup_spectrum(const SetupArgs& A, const SetupRo
   constexpr int GS = SpecShape<L>::GS;
   float2* hs = static_cast<float2*>(lds);
   // The job is the same for every thread of a transform: its fields are read
-  // once (scalar loads) before the loop rather than per element.
+  // once (scalar loads) before the loop rather than per element, and its
+  // output pointer is kept for the end.
+  float2* Hout[GS];
 #pragma unroll
   for (int gj = 0; gj < GS; ++gj) {
     const int k = rb * GS + gj;
+    Hout[gj] = nullptr;
     if (k < Ro.c) {
       const AxisJob J = A.axis[Ro.b + k];
+      Hout[gj] = J.H;
       for (int i = threadIdx.x; i < L; i += kSetupThreads) hs[gj * L + i] = kernel_value(J, i);
     } else {
       for (int i = threadIdx.x; i < L; i += kSetupThreads) hs[gj * L + i] = make_float2(0.f, 0.f);
@@ -181,12 +185,14 @@ __device__ __forceinline__ void setup_spectrum(const SetupArgs& A, const SetupRo
   for (int i = 0; i < R; ++i) v[i] = hs[g * L + t + TPR * i];
   __syncthreads();
   fft_row<P, false, kSplit, kTwCompute>(v, static_cast<char*>(lds) + g * row_lds_bytes<L, kSplit>(), t, nullptr);
-  const int k = rb * GS + g;
-  if (k >= Ro.c) return;
-  const AxisJob& J = A.axis[Ro.b + k];
+  float2* Hg = Hout[0];
+#pragma unroll
+  for (int gj = 1; gj < GS; ++gj)
+    if (g == gj) Hg = Hout[gj];
+  if (!Hg) return;
   const float inv = 1.0f / (float)L;
 #pragma unroll
-  for (int i = 0; i < R; ++i) gst(J.H, (unsigned)(t + TPR * i), make_float2(v[i].x * inv, v[i].y * inv));
+  for (int i = 0; i < R; ++i) gst(Hg, (unsigned)(t + TPR * i), make_float2(v[i].x * inv, v[i].y * inv));
 }
 
 // Column-major copy (see TileJob) of one kTrBlock x kTrBlock block: rows of
