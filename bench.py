@@ -171,9 +171,59 @@ def cpu_baseline(w, seconds: float):
         if time.perf_counter() - t0 >= seconds:
             break
     dt = time.perf_counter() - t0
+    # The paper-literal FFT path (steps 2-10 on the padded 2D grid), one view.
+    view = w.views[0]
+    t1 = time.perf_counter()
+    oracle.fft_path(w.holograms[view.holo], src, ogrid(view.grid), w.wavelength, view.z)
+    dt_fft = time.perf_counter() - t1
     return {"value": n / dt, "unit": "views/s", "cores": int(cores), "kind": "oracle",
             "sample": f"{n} views ({n // len(w.views)} passes over the {len(w.views)} views of the workload), "
-                      f"FP64 separable direct sum (zgemm) plus |u|^2, {dt:.1f} s"}
+                      f"FP64 separable direct sum (zgemm) plus |u|^2, {dt:.1f} s",
+            "fft_path_views_per_s": 1.0 / dt_fft,
+            "fft_path_sample": f"1 view through the FP64 steps 2-10 on the padded 2D grid, {dt_fft:.2f} s"}
+
+
+def bench_backward(dev, steps: int, warmup: int):
+    """Forward (intensity and field) plus backward (field gradient and dL/dz)
+    of the differentiation workload: 16 complex 1024^2 fields, one view each,
+    L = 2048.  The loss gradient dL/dI = 2 (I - T) is formed once, outside the
+    timed region; the timed step is the two library calls."""
+    import numpy as np
+    import torch
+
+    import paper_1001_4309_amd as sfd
+    import workloads
+
+    w = workloads.config4()
+    plan = sfd.Plan(w.wavelength, w.holo_grid, len(w.holograms), w.views, outputs="both", complex_input=True,
+                    device=dev)
+    fields = torch.from_numpy(w.holograms).to(dev)
+    outs = plan.new_outputs()
+    nv = len(w.views)
+    res = plan.reconstruct(fields, outs=outs)
+    gi = [2.0 * (res[v] - 0.5 * res[v].mean()) for v in range(nv)]
+    torch.cuda.synchronize()
+
+    def step():
+        r = plan.reconstruct(fields, outs=outs)
+        plan.backward(gi, fields, field_out=r[nv:])
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.reconstruct(fields, outs=outs)
+    torch.cuda.synchronize()
+    fwd = (time.perf_counter() - t0) / steps
+    return {"workload": w.name, "fields_per_step": nv, "ms_per_step": sec * 1e3,
+            "fields_per_s": nv / sec, "forward_ms": fwd * 1e3, "backward_ms": (sec - fwd) * 1e3,
+            "what": "forward (intensity + field) and backward (field gradient + dL/dz), per 16-field batch"}
 
 
 def time_steps(plan, holo, outs, steps: int) -> float:
@@ -196,6 +246,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tile widths")
+    ap.add_argument("--no-backward", action="store_true", help="skip the forward + backward measurement")
     ap.add_argument("--schedule", default="",
                     help="tile widths to use instead of autotuning, e.g. col2048=4,row2048=4")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -282,8 +333,21 @@ def main():
                 "algorithmic_flops_per_launch": flops,
                 "algorithmic_bytes_per_launch": costs[dom][0] / launches_per_step}
     step_bytes = costs["pass_x"][0] + costs["pass_y"][0]
+    # Reference: a plain 1 GiB device-to-device copy on the same GPU.
+    ca = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    cb = torch.empty_like(ca)
+    cb.copy_(ca)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        cb.copy_(ca)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbps = 5 * 2 * ca.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del ca, cb
     hbm = {"algorithmic_bytes_per_step": step_bytes, "achieved_GBps": step_bytes / sec / 1e9,
-           "frac_of_8TBps": step_bytes / sec / 1e9 / HBM_PEAK_GBPS}
+           "frac_of_8TBps": step_bytes / sec / 1e9 / HBM_PEAK_GBPS,
+           "device_copy_GBps": copy_gbps, "frac_of_device_copy": step_bytes / sec / 1e9 / copy_gbps}
 
     per_view = None
     if not args.no_per_view:
@@ -294,6 +358,12 @@ def main():
         psec = time_steps(pv, holo, pouts, args.steps)
         per_view = {"views_per_s": nv / psec, "ms_per_step": psec * 1e3, "batched_speedup": psec / sec}
         log(f"per-view launch: {psec * 1e6:.1f} us/step, {nv / psec:.0f} views/s")
+
+    backward = None
+    if not args.no_backward:
+        backward = bench_backward(dev, max(1, min(args.steps, 50)), max(1, min(args.warmup, 5)))
+        log(f"forward + backward: {backward['ms_per_step']:.3f} ms per 16 fields "
+            f"({backward['fields_per_s']:.0f} fields/s; forward {backward['forward_ms']:.3f} ms)")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -322,6 +392,7 @@ def main():
         "roofline": roofline,
         "hbm": hbm,
         "per_view_launch": per_view,
+        "backward": backward,
         "kernels": kern,
         "cpu_baseline": cpu,
     }
