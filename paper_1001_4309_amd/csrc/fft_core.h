@@ -117,6 +117,61 @@ __device__ __forceinline__ void dft(float2 (&a)[N]) {
   }
 }
 
+// Length-N DFT whose inputs N/2..N-1 are zero (they are not read): split by
+// output parity, X[2m] = DFT_{N/2}(a)[m] and X[2m+1] = DFT_{N/2}(a w^j)[m],
+// which drops the first level of additions.
+template <int N, bool INV, int J = 0>
+__device__ __forceinline__ void twist_half(float2 (&hi)[N / 2], const float2 (&a)[N]) {
+  if constexpr (J < N / 2) {
+    hi[J] = mul_w<N, J, INV>(a[J]);
+    twist_half<N, INV, J + 1>(hi, a);
+  }
+}
+template <int N, bool INV>
+__device__ __forceinline__ void dft_half_in(float2 (&a)[N]) {
+  if constexpr (N == 1) {
+    return;
+  } else {
+    float2 lo[N / 2], hi[N / 2];
+#pragma unroll
+    for (int j = 0; j < N / 2; ++j) lo[j] = a[j];
+    twist_half<N, INV>(hi, a);
+    dft<N / 2, INV>(lo);
+    dft<N / 2, INV>(hi);
+#pragma unroll
+    for (int m = 0; m < N / 2; ++m) {
+      a[2 * m] = lo[m];
+      a[2 * m + 1] = hi[m];
+    }
+  }
+}
+
+// Outputs 0..N/2-1 of a length-N DFT (the others are left unspecified): the
+// last decimation-in-time level without its subtractions.
+template <int N, bool INV, int K = 0>
+__device__ __forceinline__ void combine_low(float2 (&out)[N], const float2 (&e)[N / 2], const float2 (&o)[N / 2]) {
+  if constexpr (K < N / 2) {
+    out[K] = cadd(e[K], mul_w<N, K, INV>(o[K]));
+    combine_low<N, INV, K + 1>(out, e, o);
+  }
+}
+template <int N, bool INV>
+__device__ __forceinline__ void dft_low_out(float2 (&a)[N]) {
+  if constexpr (N == 1) {
+    return;
+  } else {
+    float2 e[N / 2], o[N / 2];
+#pragma unroll
+    for (int i = 0; i < N / 2; ++i) {
+      e[i] = a[2 * i];
+      o[i] = a[2 * i + 1];
+    }
+    dft<N / 2, INV>(e);
+    dft<N / 2, INV>(o);
+    combine_low<N, INV>(a, e, o);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Plans and twiddle tables.
 
@@ -342,7 +397,11 @@ struct StageTw {
 // stage input.  The outputs stay in v (butterfly q's output k in slot
 // q + k nb, which for the last stage is natural order) unless the exchange
 // is complex (not SPLIT), in which case they go straight to the LDS buffer.
-template <int L, int TPR, int r, int Ns, bool INV, bool LAST, bool SPLIT, int TWS>
+// PRUNE: 1 = the upper half of every butterfly's inputs is zero (the padded
+// half of a forward transform's first stage); 2 = only the lower half of
+// every butterfly's outputs is needed (the cropped half of an inverse
+// transform's last stage; the slots of the upper half are left as they are).
+template <int L, int TPR, int r, int Ns, bool INV, bool LAST, bool SPLIT, int TWS, int PRUNE = 0>
 __device__ __forceinline__ void stage_compute(float2 (&v)[L / TPR], void* __restrict__ buf, int t,
                                               const StageTw<TPR, L / TPR, r, Ns, TWS>& W) {
   constexpr int R = L / TPR;
@@ -354,17 +413,23 @@ __device__ __forceinline__ void stage_compute(float2 (&v)[L / TPR], void* __rest
   for (int q = 0; q < nb; ++q) {
     const int j = t + TPR * q;
     float2 b[r];
+    constexpr int kin = PRUNE == 1 ? r / 2 : r;
 #pragma unroll
-    for (int k = 0; k < r; ++k) b[k] = v[q + k * nb];
+    for (int k = 0; k < kin; ++k) b[k] = v[q + k * nb];
+#pragma unroll
+    for (int k = kin; k < r; ++k) b[k] = make_float2(0.f, 0.f);  // not read by dft_half_in
     if constexpr (Ns > 1) {
 #pragma unroll
-      for (int k = 1; k < r; ++k) b[k] = INV ? cmulc(b[k], W.w[q][k - 1]) : cmul(b[k], W.w[q][k - 1]);
+      for (int k = 1; k < kin; ++k) b[k] = INV ? cmulc(b[k], W.w[q][k - 1]) : cmul(b[k], W.w[q][k - 1]);
     }
-    dft<r, INV>(b);
+    if constexpr (PRUNE == 1) dft_half_in<r, INV>(b);
+    else if constexpr (PRUNE == 2) dft_low_out<r, INV>(b);
+    else dft<r, INV>(b);
     if constexpr (nb > 1) sched_fence();
     if constexpr (LAST || SPLIT) {
+      constexpr int kout = PRUNE == 2 ? r / 2 : r;
 #pragma unroll
-      for (int k = 0; k < r; ++k) v[q + k * nb] = b[k];
+      for (int k = 0; k < kout; ++k) v[q + k * nb] = b[k];
     } else {
       const int wb = lds_wbase<r, Ns>(j);
 #pragma unroll
@@ -415,34 +480,38 @@ __device__ __forceinline__ void stage_exchange(float2 (&v)[L / TPR], void* __res
 
 // Stage (Ns, r) with its twiddles W already loaded; loads the next stage's
 // twiddles before this stage's exchange.
-template <int L, int TPR, bool INV, bool SPLIT, int TWS, int Ns, int OFF, int r, int... rest>
+template <int L, int TPR, bool INV, bool SPLIT, int TWS, bool HALF, int Ns, int OFF, int r, int... rest>
 __device__ __forceinline__ void fft_stages(float2 (&v)[L / TPR], void* buf, int t, const float2* tw,
                                            const StageTw<TPR, L / TPR, r, Ns, TWS>& W) {
   constexpr bool last = sizeof...(rest) == 0;
-  stage_compute<L, TPR, r, Ns, INV, last, SPLIT, TWS>(v, buf, t, W);
+  constexpr int prune = !HALF ? 0 : (!INV && Ns == 1) ? 1 : (INV && last) ? 2 : 0;
+  stage_compute<L, TPR, r, Ns, INV, last, SPLIT, TWS, prune>(v, buf, t, W);
   if constexpr (!last) {
     constexpr int next_off = OFF + (Ns > 1 ? (r - 1) * Ns : 0);
     constexpr int rn = Radices<rest...>::first;
     StageTw<TPR, L / TPR, rn, Ns * r, TWS> Wn;
     Wn.load(t, tw + next_off);
     stage_exchange<L, TPR, r, Ns, SPLIT>(v, buf, t);
-    fft_stages<L, TPR, INV, SPLIT, TWS, Ns * r, next_off, rest...>(v, buf, t, tw, Wn);
+    fft_stages<L, TPR, INV, SPLIT, TWS, HALF, Ns * r, next_off, rest...>(v, buf, t, tw, Wn);
   }
 }
 
-template <class P, bool INV, bool SPLIT, int TWS, int r0, int... Rs>
+template <class P, bool INV, bool SPLIT, int TWS, bool HALF, int r0, int... Rs>
 __device__ __forceinline__ void fft_run(Radices<r0, Rs...>, float2 (&v)[P::R], void* buf, int t, const float2* tw) {
   const StageTw<P::TPR, P::R, r0, 1, TWS> W0{};  // the first stage has no twiddles
-  fft_stages<P::L, P::TPR, INV, SPLIT, TWS, 1, 0, r0, Rs...>(v, buf, t, tw, W0);
+  fft_stages<P::L, P::TPR, INV, SPLIT, TWS, HALF, 1, 0, r0, Rs...>(v, buf, t, tw, W0);
 }
 
 // Forward (INV = false) or unnormalised inverse (INV = true) FFT of one row
 // of shape P.  ``buf`` is the row's LDS exchange buffer
 // (row_lds_bytes<P::L, SPLIT>() bytes); ``tw`` is the twiddle table of P in
 // global memory (kTwGlobal) or LDS (kTwShared), unused with kTwCompute.
-template <class P, bool INV, bool SPLIT, int TWS = kTwGlobal>
+// HALF: a forward transform whose input's upper half (elements L/2..L-1) is
+// zero, or an inverse transform of which only the lower half of the output
+// is used; the first (forward) or last (inverse) stage skips that half.
+template <class P, bool INV, bool SPLIT, int TWS = kTwGlobal, bool HALF = false>
 __device__ __forceinline__ void fft_row(float2 (&v)[P::R], void* buf, int t, const float2* tw) {
-  fft_run<P, INV, SPLIT, TWS>(typename P::Rad{}, v, buf, t, tw);
+  fft_run<P, INV, SPLIT, TWS, HALF>(typename P::Rad{}, v, buf, t, tw);
 }
 
 // Twiddle table entry e of a shape's table (layout of TwInfo), evaluated in FP64

@@ -170,8 +170,11 @@ hipError_t launch_setup(const SetupArgs& args, hipStream_t s);
 int spectra_per_block(int L);
 
 // col = true: the y transforms (column kernel); false: the x transforms.
-// G is the tile width: one of pass_tile_widths(L, col).
-hipError_t launch_pass(int L, bool col, int G, const PassArgs& args, const float2* tw, hipStream_t s);
+// G is the tile width: one of pass_tile_widths(L, col).  var selects a
+// specialised kernel: 1 when every job has n_in == L/2, n_out <= L/2 and no
+// kReduce; 2 when, in addition, every job writes intensities only (row pass,
+// no kUsePost or kOutField); 0 otherwise.
+hipError_t launch_pass(int L, bool col, int G, int var, const PassArgs& args, const float2* tw, hipStream_t s);
 
 hipError_t launch_gradz(const GradZJob* d_jobs, int njobs, hipStream_t s);
 hipError_t launch_gather(const GatherJob* d_jobs, int njobs, int max_n, hipStream_t s);

@@ -19,6 +19,8 @@
 //                  loads and stores straight from registers.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "fft_core.h"
 #include "sfd_internal.h"
 
@@ -376,6 +378,20 @@ __device__ __forceinline__ void load_row_t(float2 (&v)[R], const void* in, const
     if ((i & 7) == 7) sched_fence();
   }
 }
+// The common case only (n = L/2): the first half loaded, the padding zero.
+template <int TPR, int R, bool REAL>
+__device__ __forceinline__ void load_half(float2 (&v)[R], const void* in, const float2* pre, int t) {
+  if (pre) {
+#pragma unroll
+    for (int i = 0; i < R / 2; ++i) v[i] = pre_times_in<REAL, true>(in, pre, (unsigned)(t + TPR * i));
+  } else {
+#pragma unroll
+    for (int i = 0; i < R / 2; ++i) v[i] = pre_times_in<REAL, false>(in, pre, (unsigned)(t + TPR * i));
+  }
+#pragma unroll
+  for (int i = R / 2; i < R; ++i) v[i] = make_float2(0.f, 0.f);
+}
+
 // v[i] = in[t + TPR i] (times pre[t + TPR i] unless pre is null) for
 // t + TPR i < n, zero beyond.
 template <int TPR, int R, bool REAL>
@@ -485,13 +501,20 @@ __device__ __forceinline__ void stage_tables(float2* tws, float2* hs, const floa
 
 // x transforms: row r of the job reads in + r * in_ld and writes
 // out + r * out_ld (contiguous), both straight from registers.
-template <int L, int GR>
+// VAR selects a specialisation, which keeps the code of the common cases
+// small: 0 = any job; 1 = every job of the launch has an input of L/2
+// samples, an output of at most L/2 and no reduction (half loads, pruned
+// transforms, no reduction epilogue); 2 = as 1, and the jobs write only
+// intensities.
+template <int L, int GR, int VAR>
 __global__ void __launch_bounds__((PassShape<L, GR>::THREADS)) __attribute__((amdgpu_waves_per_eu(SFD_ROW_WPE))) row_kernel(const PassArgs args, const float2* __restrict__ tw) {
   using S = PassShape<L, GR>;
   constexpr int TPR = S::TPR;
   constexpr int R = L / TPR;
   constexpr int G = S::G;
   constexpr int RB = row_lds_bytes<L, kSplit>();
+  constexpr bool FAST = VAR >= 1;
+  constexpr bool INT_ONLY = VAR == 2;
   using T = SharedTables<L>;
   // Shared tables, exchange buffers, then room for the epilogue reduction (4
   // doubles per wavefront).
@@ -513,10 +536,17 @@ __global__ void __launch_bounds__((PassShape<L, GR>::THREADS)) __attribute__((am
 
   // A row past the end of the job computes on row 0 and stores nothing.
   float2 v[R];
-  if (J.mode & kInReal)
-    load_row<TPR, R, true>(v, static_cast<const float*>(J.in) + (int64_t)vrow * J.in_ld, J.pre, n_in, t);
-  else
-    load_row<TPR, R, false>(v, static_cast<const float2*>(J.in) + (int64_t)vrow * J.in_ld, J.pre, n_in, t);
+  if constexpr (FAST) {
+    if (J.mode & kInReal)
+      load_half<TPR, R, true>(v, static_cast<const float*>(J.in) + (int64_t)vrow * J.in_ld, J.pre, t);
+    else
+      load_half<TPR, R, false>(v, static_cast<const float2*>(J.in) + (int64_t)vrow * J.in_ld, J.pre, t);
+  } else {
+    if (J.mode & kInReal)
+      load_row<TPR, R, true>(v, static_cast<const float*>(J.in) + (int64_t)vrow * J.in_ld, J.pre, n_in, t);
+    else
+      load_row<TPR, R, false>(v, static_cast<const float2*>(J.in) + (int64_t)vrow * J.in_ld, J.pre, n_in, t);
+  }
 
   const float2* __restrict__ H = J.H;
   if constexpr (T::on) {
@@ -525,42 +555,53 @@ __global__ void __launch_bounds__((PassShape<L, GR>::THREADS)) __attribute__((am
   }
   const float2* twx = T::on ? tws : tw;
   void* buf = xbuf + g * RB;
-  fft_row<PassPlan<L>, false, kSplit, T::src>(v, buf, t, twx);
-  sched_fence();
-#pragma unroll
-  for (int i = 0; i < R; ++i) v[i] = cmul(v[i], T::on ? hs[t + TPR * i] : gld(H, (unsigned)(t + TPR * i)));
-  sched_fence();
-  fft_row<PassPlan<L>, true, kSplit, T::src>(v, buf, t, twx);
-
   const int n_out = J.n_out;
   const int mode = J.mode;
-  if (mode & kUsePost) {
-    const float2* post = J.post;
+  // HALF: the common case (input of L/2 samples, output of at most L/2),
+  // where the first forward and the last inverse stage skip the padded and
+  // the cropped half.
+  auto body = [&](auto half_c) {
+    constexpr bool HALF = decltype(half_c)::value;
+    constexpr int RL = HALF ? R / 2 : R;
+    fft_row<PassPlan<L>, false, kSplit, T::src, HALF>(v, buf, t, twx);
+    sched_fence();
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
-      const int m = t + TPR * i;
-      if (TPR * (i + 1) <= n_out || m < n_out) v[i] = cmul(v[i], gld(post, (unsigned)m));
-    }
-  }
-  if (valid && (mode & kOutField)) {
-    float2* out = static_cast<float2*>(J.out) + (int64_t)row * J.out_ld;
+    for (int i = 0; i < R; ++i) v[i] = cmul(v[i], T::on ? hs[t + TPR * i] : gld(H, (unsigned)(t + TPR * i)));
+    sched_fence();
+    fft_row<PassPlan<L>, true, kSplit, T::src, HALF>(v, buf, t, twx);
+
+    if (!INT_ONLY && (mode & kUsePost)) {
+      const float2* post = J.post;
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
-      const int m = t + TPR * i;
-      if (TPR * (i + 1) <= n_out || m < n_out) gst(out, (unsigned)m, v[i]);
+      for (int i = 0; i < RL; ++i) {
+        const int m = t + TPR * i;
+        if (TPR * (i + 1) <= n_out || m < n_out) v[i] = cmul(v[i], gld(post, (unsigned)m));
+      }
     }
-  }
-  if (valid && (mode & kOutIntensity)) {
-    float* out = ((mode & kOutField) ? J.out2 : static_cast<float*>(J.out)) + (int64_t)row * J.out_ld;
-    const float sc = J.iscale;
+    if (!INT_ONLY && valid && (mode & kOutField)) {
+      float2* out = static_cast<float2*>(J.out) + (int64_t)row * J.out_ld;
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
-      const int m = t + TPR * i;
-      if (TPR * (i + 1) <= n_out || m < n_out) gst(out, (unsigned)m, (v[i].x * v[i].x + v[i].y * v[i].y) * sc);
+      for (int i = 0; i < RL; ++i) {
+        const int m = t + TPR * i;
+        if (TPR * (i + 1) <= n_out || m < n_out) gst(out, (unsigned)m, v[i]);
+      }
     }
-  }
-  if (mode & kReduce) row_reduce<TPR, R, S::NW>(J, v, row, valid, t, tile - args.tile_prefix[jid],
-                                                         reinterpret_cast<double*>(xbuf + G * RB));
+    if (valid && (mode & kOutIntensity)) {
+      float* out = ((!INT_ONLY && (mode & kOutField)) ? J.out2 : static_cast<float*>(J.out)) + (int64_t)row * J.out_ld;
+      const float sc = J.iscale;
+#pragma unroll
+      for (int i = 0; i < RL; ++i) {
+        const int m = t + TPR * i;
+        if (TPR * (i + 1) <= n_out || m < n_out) gst(out, (unsigned)m, (v[i].x * v[i].x + v[i].y * v[i].y) * sc);
+      }
+    }
+    if constexpr (!HALF) {
+      if (mode & kReduce) row_reduce<TPR, R, S::NW>(J, v, row, valid, t, tile - args.tile_prefix[jid],
+                                                             reinterpret_cast<double*>(xbuf + G * RB));
+    }
+  };
+  if constexpr (FAST) body(std::true_type{});
+  else body(std::false_type{});
 }
 
 // y transforms: column c of the job reads in[c * in_ld + n] for n < n_in
@@ -568,13 +609,14 @@ __global__ void __launch_bounds__((PassShape<L, GR>::THREADS)) __attribute__((am
 // out[m * out_ld + c] for m < n_out (complex).  The G columns of a workgroup
 // leave through LDS staging in chunks of L/2 rows, so that each global store
 // covers G consecutive columns.
-template <int L, int GC>
+template <int L, int GC, int VAR>
 __global__ void __launch_bounds__((PassShape<L, GC>::THREADS)) __attribute__((amdgpu_waves_per_eu(SFD_COL_WPE))) col_kernel(const PassArgs args, const float2* __restrict__ tw) {
   using S = PassShape<L, GC>;
   constexpr int TPR = S::TPR;
   constexpr int R = L / TPR;
   constexpr int G = S::G;
   constexpr int THREADS = S::THREADS;
+  constexpr bool FAST = VAR >= 1;  // as in row_kernel (column passes write fields only)
   constexpr int RB = row_lds_bytes<L, kSplit>();
   constexpr int C = L / 2;    // staging chunk along the transform
   constexpr int SST = C + 9;  // staging stride per column (elements)
@@ -608,10 +650,15 @@ __global__ void __launch_bounds__((PassShape<L, GC>::THREADS)) __attribute__((am
   // column past the grid's edge computes on the last one and stores nothing).
   const int cl = c0 + g < ncols ? c0 + g : ncols - 1;
   float2 v[R];
-  if (real_in)
-    load_row<TPR, R, true>(v, static_cast<const float*>(J.in) + (int64_t)cl * in_ld, pre, n_in, t);
-  else
-    load_row<TPR, R, false>(v, static_cast<const float2*>(J.in) + (int64_t)cl * in_ld, pre, n_in, t);
+  if constexpr (FAST) {
+    if (real_in) load_half<TPR, R, true>(v, static_cast<const float*>(J.in) + (int64_t)cl * in_ld, pre, t);
+    else load_half<TPR, R, false>(v, static_cast<const float2*>(J.in) + (int64_t)cl * in_ld, pre, t);
+  } else {
+    if (real_in)
+      load_row<TPR, R, true>(v, static_cast<const float*>(J.in) + (int64_t)cl * in_ld, pre, n_in, t);
+    else
+      load_row<TPR, R, false>(v, static_cast<const float2*>(J.in) + (int64_t)cl * in_ld, pre, n_in, t);
+  }
 
   const float2* __restrict__ H = J.H;
   if constexpr (T::on) {
@@ -620,46 +667,54 @@ __global__ void __launch_bounds__((PassShape<L, GC>::THREADS)) __attribute__((am
   }
   const float2* twx = T::on ? tws : tw;
   void* buf = xbuf + g * RB;
-  fft_row<PassPlan<L>, false, kSplit, T::src>(v, buf, t, twx);
-  sched_fence();
-#pragma unroll
-  for (int i = 0; i < R; ++i) v[i] = cmul(v[i], T::on ? hs[t + TPR * i] : gld(H, (unsigned)(t + TPR * i)));
-  sched_fence();
-  fft_row<PassPlan<L>, true, kSplit, T::src>(v, buf, t, twx);
-
   const int n_out = J.n_out;
-  if (J.mode & kUsePost) {
-    const float2* post = J.post;
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-      const int m = t + TPR * i;
-      if (TPR * (i + 1) <= n_out || m < n_out) v[i] = cmul(v[i], gld(post, (unsigned)m));
-    }
-  }
-  if (J.colscale) {
-    const float2 cs = gld(J.colscale, (unsigned)cl);
-#pragma unroll
-    for (int i = 0; i < R; ++i) v[i] = cmul(v[i], cs);
-  }
   float2* out = static_cast<float2*>(J.out) + c0 + gs;
   const int out_ld = (int)J.out_ld;
+  // HALF as in the row kernel; then only the first staging chunk exists.
+  auto body = [&](auto half_c) {
+    constexpr bool HALF = decltype(half_c)::value;
+    constexpr int RL = HALF ? R / 2 : R;
+    constexpr int NC = HALF ? 1 : 2;
+    fft_row<PassPlan<L>, false, kSplit, T::src, HALF>(v, buf, t, twx);
+    sched_fence();
 #pragma unroll
-  for (int c = 0; c < 2; ++c) {
-    const int m_lo = c * C;
-    if (m_lo >= n_out) break;
-    __syncthreads();
+    for (int i = 0; i < R; ++i) v[i] = cmul(v[i], T::on ? hs[t + TPR * i] : gld(H, (unsigned)(t + TPR * i)));
+    sched_fence();
+    fft_row<PassPlan<L>, true, kSplit, T::src, HALF>(v, buf, t, twx);
+
+    if (J.mode & kUsePost) {
+      const float2* post = J.post;
 #pragma unroll
-    for (int i = c * (R / 2); i < (c + 1) * (R / 2); ++i) {
-      const int m = t + TPR * i;
-      if (TPR * (i + 1) <= n_out || m < n_out) st[g * SST + (m - m_lo)] = v[i];
+      for (int i = 0; i < RL; ++i) {
+        const int m = t + TPR * i;
+        if (TPR * (i + 1) <= n_out || m < n_out) v[i] = cmul(v[i], gld(post, (unsigned)m));
+      }
     }
-    __syncthreads();
-    const int cnt = (n_out - m_lo < C ? n_out - m_lo : C) * G;
-    for (int e = threadIdx.x; e < cnt; e += THREADS) {
-      const int m = m_lo + e / G;
-      if (col_ok) gst(out, (unsigned)(m * out_ld), st[gs * SST + (m - m_lo)]);
+    if (J.colscale) {
+      const float2 cs = gld(J.colscale, (unsigned)cl);
+#pragma unroll
+      for (int i = 0; i < RL; ++i) v[i] = cmul(v[i], cs);
     }
-  }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int m_lo = c * C;
+      if (m_lo >= n_out) break;
+      __syncthreads();
+#pragma unroll
+      for (int i = c * (R / 2); i < (c + 1) * (R / 2); ++i) {
+        const int m = t + TPR * i;
+        if (TPR * (i + 1) <= n_out || m < n_out) st[g * SST + (m - m_lo)] = v[i];
+      }
+      __syncthreads();
+      const int cnt = (n_out - m_lo < C ? n_out - m_lo : C) * G;
+      for (int e = threadIdx.x; e < cnt; e += THREADS) {
+        const int m = m_lo + e / G;
+        if (col_ok) gst(out, (unsigned)(m * out_ld), st[gs * SST + (m - m_lo)]);
+      }
+    }
+  };
+  if constexpr (FAST) body(std::true_type{});
+  else body(std::false_type{});
 }
 
 bool supported_length(int L) { return twiddle_len(L, false) >= 0; }
@@ -674,7 +729,7 @@ bool supported_length(int L) { return twiddle_len(L, false) >= 0; }
 #define SFD_COL_SHAPES(X) \
   X(64, 32) X(64, 16) X(128, 16) X(128, 8) X(256, 8) X(256, 4) X(512, 8) X(512, 4) \
   X(1024, 8) X(1024, 4) X(1024, 16) X(2048, 8) X(2048, 4) X(2048, 2) X(4096, 2) X(4096, 4) \
-  X(8192, 2) X(8192, 1)
+  X(8192, 1) X(8192, 2)
 
 int pass_tile_widths(int L, bool col, int* widths, int cap) {
   int n = 0;
@@ -785,22 +840,28 @@ int spectra_per_block(int L) {
   }
 }
 
-hipError_t launch_pass(int L, bool col, int G, const PassArgs& a, const float2* tw, hipStream_t s) {
+hipError_t launch_pass(int L, bool col, int G, int var, const PassArgs& a, const float2* tw, hipStream_t s) {
   if (a.total_tiles <= 0) return hipSuccess;
-#define SFD_LAUNCH_ROW(l, g)                                                                              \
-  if (!col && L == l && G == g) {                                                                        \
-    hipLaunchKernelGGL((row_kernel<l, g>), dim3(a.total_tiles), dim3(PassShape<l, g>::THREADS), 0, s, a, tw); \
-    return hipGetLastError();                                                                            \
+#define SFD_LAUNCH_V(kern, l, g, v) \
+  hipLaunchKernelGGL((kern<l, g, v>), dim3(a.total_tiles), dim3(PassShape<l, g>::THREADS), 0, s, a, tw)
+#define SFD_LAUNCH_ROW(l, g)                          \
+  if (!col && L == l && G == g) {                     \
+    if (var == 2) SFD_LAUNCH_V(row_kernel, l, g, 2);  \
+    else if (var == 1) SFD_LAUNCH_V(row_kernel, l, g, 1); \
+    else SFD_LAUNCH_V(row_kernel, l, g, 0);           \
+    return hipGetLastError();                         \
   }
-#define SFD_LAUNCH_COL(l, g)                                                                              \
-  if (col && L == l && G == g) {                                                                         \
-    hipLaunchKernelGGL((col_kernel<l, g>), dim3(a.total_tiles), dim3(PassShape<l, g>::THREADS), 0, s, a, tw); \
-    return hipGetLastError();                                                                            \
+#define SFD_LAUNCH_COL(l, g)                          \
+  if (col && L == l && G == g) {                      \
+    if (var >= 1) SFD_LAUNCH_V(col_kernel, l, g, 1);  \
+    else SFD_LAUNCH_V(col_kernel, l, g, 0);           \
+    return hipGetLastError();                         \
   }
   SFD_ROW_SHAPES(SFD_LAUNCH_ROW)
   SFD_COL_SHAPES(SFD_LAUNCH_COL)
 #undef SFD_LAUNCH_ROW
 #undef SFD_LAUNCH_COL
+#undef SFD_LAUNCH_V
   return hipErrorInvalidValue;
 }
 
