@@ -540,11 +540,12 @@ sfd_status launch_rows(const CallDescs& D, const sfd::RowJob* d_rows, int first,
     }
     a.tile_prefix[j - i] = acc;
     a.total_tiles = acc;
-    bool fast = true, int_only = !col;
+    bool fast = true, int_only = true;
     for (int k = i; k < j; ++k) {
       const sfd::RowJob& r = D.rows[k];
       fast = fast && 2 * r.n_in == L && 2 * r.n_out <= L && !(r.mode & sfd::kReduce);
-      int_only = int_only && (r.mode & sfd::kOutIntensity) && !(r.mode & (sfd::kOutField | sfd::kUsePost));
+      int_only = int_only && !(r.mode & sfd::kUsePost) &&
+                 (col || ((r.mode & sfd::kOutIntensity) && !(r.mode & sfd::kOutField)));
     }
     const int var = !fast ? 0 : int_only ? 2 : 1;
     const float2* tw = reinterpret_cast<const float2*>(ws + P->tw_off.at(L));

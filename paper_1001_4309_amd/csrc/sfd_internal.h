@@ -172,8 +172,8 @@ int spectra_per_block(int L);
 // col = true: the y transforms (column kernel); false: the x transforms.
 // G is the tile width: one of pass_tile_widths(L, col).  var selects a
 // specialised kernel: 1 when every job has n_in == L/2, n_out <= L/2 and no
-// kReduce; 2 when, in addition, every job writes intensities only (row pass,
-// no kUsePost or kOutField); 0 otherwise.
+// kReduce; 2 when, in addition, no job applies a post-chirp (and, in the row
+// pass, every job writes intensities only); 0 otherwise.
 hipError_t launch_pass(int L, bool col, int G, int var, const PassArgs& args, const float2* tw, hipStream_t s);
 
 hipError_t launch_gradz(const GradZJob* d_jobs, int njobs, hipStream_t s);

@@ -616,7 +616,10 @@ __global__ void __launch_bounds__((PassShape<L, GC>::THREADS)) __attribute__((am
   constexpr int R = L / TPR;
   constexpr int G = S::G;
   constexpr int THREADS = S::THREADS;
-  constexpr bool FAST = VAR >= 1;  // as in row_kernel (column passes write fields only)
+  // As in row_kernel; column passes write fields, so VAR 2 here means no
+  // post-chirp (intensity-only plans).
+  constexpr bool FAST = VAR >= 1;
+  constexpr bool NO_POST = VAR == 2;
   constexpr int RB = row_lds_bytes<L, kSplit>();
   constexpr int C = L / 2;    // staging chunk along the transform
   constexpr int SST = C + 9;  // staging stride per column (elements)
@@ -682,7 +685,7 @@ __global__ void __launch_bounds__((PassShape<L, GC>::THREADS)) __attribute__((am
     sched_fence();
     fft_row<PassPlan<L>, true, kSplit, T::src, HALF>(v, buf, t, twx);
 
-    if (J.mode & kUsePost) {
+    if (!NO_POST && (J.mode & kUsePost)) {
       const float2* post = J.post;
 #pragma unroll
       for (int i = 0; i < RL; ++i) {
@@ -853,7 +856,8 @@ hipError_t launch_pass(int L, bool col, int G, int var, const PassArgs& a, const
   }
 #define SFD_LAUNCH_COL(l, g)                          \
   if (col && L == l && G == g) {                      \
-    if (var >= 1) SFD_LAUNCH_V(col_kernel, l, g, 1);  \
+    if (var == 2) SFD_LAUNCH_V(col_kernel, l, g, 2);  \
+    else if (var == 1) SFD_LAUNCH_V(col_kernel, l, g, 1); \
     else SFD_LAUNCH_V(col_kernel, l, g, 0);           \
     return hipGetLastError();                         \
   }
