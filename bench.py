@@ -75,13 +75,22 @@ def kernel_source_hash() -> str:
 
 
 def kernel_name(kind: str, L: int, g: int, var: int) -> str:
-    return f"{'row' if kind == 'pass_x' else 'col'}_kernel<{L}, {g}, {var}>"
+    """The kernel's name as rocprofv3 reports it: template arguments length,
+    tile width, specialisation and transforms per slot."""
+    import paper_1001_4309_amd as sfd
+
+    col = kind == "pass_y"
+    per_slot = dict(sfd.sfd_tile_widths(L, col)).get(g, 1)
+    return f"{'col' if col else 'row'}_kernel<{L}, {g}, {var}, {per_slot}>"
 
 
 def pass_variant(w, plan, kind: str) -> int:
     """The kernel specialisation the library picks for a pass of this
-    workload: 2 (half-padded input, cropped output, intensity only), 1
-    (half-padded and cropped) or 0 (general)."""
+    workload (the rule of the library's pass launcher).  Row pass: 2
+    (half-padded input, cropped output, intensity only), 1 (half-padded and
+    cropped) or 0 (general).  Column pass: 1 (half-padded and cropped,
+    complex input), 2 (the same with a real input and no post-chirp), 3 (real
+    input with post-chirp) or 0."""
     g = w.holo_grid
     fast = True
     for v, view in enumerate(w.views):
@@ -92,7 +101,11 @@ def pass_variant(w, plan, kind: str) -> int:
             fast = fast and 2 * g.ny == ly and 2 * view.grid.ny <= ly
     if not fast:
         return 0
-    return 2 if plan.outputs == "intensity" else 1
+    if kind == "pass_x":
+        return 2 if plan.outputs == "intensity" else 1
+    if plan.complex_input:
+        return 1
+    return 2 if plan.outputs == "intensity" else 3
 
 
 def traffic_file(config: int) -> str:

@@ -190,6 +190,16 @@ sfd_status sfd_schedule(sfd_plan_t plan, int32_t L, int32_t col, int32_t* tile_w
  * is computed the same way whatever workgroup holds it. */
 sfd_status sfd_set_schedule(sfd_plan_t plan, int32_t L, int32_t col, int32_t tile_width);
 
+/* Tile widths (transforms per workgroup) the column (col != 0) or row
+ * (col == 0) pass has kernels for at transform length L, the default first
+ * (host query, no plan needed).  Writes up to cap widths to ``widths`` and,
+ * when ``per_slot`` is not NULL, for each the number of transforms that one
+ * slot of TPR threads of that workgroup runs in turn (1, or more when the
+ * kernel fetches the next transform's input while it computes the current
+ * one).  Returns how many widths there are (0 when L is not a supported
+ * length), or -1 if cap < 0 or cap > 0 with widths NULL. */
+int32_t sfd_tile_widths(int32_t L, int32_t col, int32_t* widths, int32_t* per_slot, int32_t cap);
+
 /* Kernel kinds reported by sfd_profile_report. */
 enum {
   SFD_KERNEL_TABLES = 0,   /* chirp and twiddle tables (Eqs. 2-4) */

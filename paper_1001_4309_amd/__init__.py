@@ -25,8 +25,8 @@ from ._lib import (SFD_EAGER, SFD_IN_C64, SFD_IN_REAL_F32, SFD_OUT_FIELD, SFD_OU
                    SFD_PER_VIEW_LAUNCH, SFD_PHASE_FP32, SfdError, SfdGrid, SfdView)
 
 __all__ = ["Plan", "SFDFunction", "sfd_plan", "sfd_workspace_size", "sfd_view_lengths", "sfd_reconstruct",
-           "sfd_backward", "sfd_autotune", "sfd_schedule", "sfd_set_schedule", "sfd_profile_enable",
-           "sfd_profile_report", "sfd_destroy", "SfdError"]
+           "sfd_backward", "sfd_autotune", "sfd_schedule", "sfd_set_schedule", "sfd_tile_widths",
+           "sfd_profile_enable", "sfd_profile_report", "sfd_destroy", "SfdError"]
 
 
 def _grid(g) -> SfdGrid:
@@ -116,6 +116,13 @@ def sfd_schedule(plan, L: int, col: bool) -> int:
     g = ctypes.c_int32()
     _lib.check(_lib.load().sfd_schedule(plan, int(L), 1 if col else 0, ctypes.byref(g)))
     return int(g.value)
+
+
+def sfd_tile_widths(L: int, col: bool) -> list:
+    """[(tile width, transforms per slot), ...] of the column (col) or row
+    pass at transform length L, the default first (empty if L is not
+    supported)."""
+    return _lib.tile_widths(L, col)
 
 
 def sfd_set_schedule(plan, L: int, col: bool, tile_width: int) -> None:

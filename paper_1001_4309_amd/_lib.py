@@ -26,8 +26,8 @@ SFD_PER_VIEW_LAUNCH = 1 << 5
 SFD_EAGER = 1 << 6
 
 EXPORTED = ["sfd_plan", "sfd_workspace_size", "sfd_view_lengths", "sfd_reconstruct",
-            "sfd_backward", "sfd_autotune", "sfd_schedule", "sfd_set_schedule", "sfd_profile_enable",
-            "sfd_profile_report", "sfd_destroy", "sfd_last_error"]
+            "sfd_backward", "sfd_autotune", "sfd_schedule", "sfd_set_schedule", "sfd_tile_widths",
+            "sfd_profile_enable", "sfd_profile_report", "sfd_destroy", "sfd_last_error"]
 
 SFD_KERNEL_TABLES = 0
 SFD_KERNEL_SPECTRA = 1
@@ -81,6 +81,9 @@ def load() -> ctypes.CDLL:
     lib.sfd_autotune.argtypes = [vp, vp, ctypes.POINTER(vp), vp, ctypes.c_size_t, ctypes.c_int32, vp]
     lib.sfd_schedule.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     lib.sfd_set_schedule.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    lib.sfd_tile_widths.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
+    lib.sfd_tile_widths.restype = ctypes.c_int32
     lib.sfd_profile_enable.argtypes = [vp, ctypes.c_int32]
     lib.sfd_profile_report.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
                                        ctypes.POINTER(ctypes.c_double)]
@@ -93,6 +96,18 @@ def load() -> ctypes.CDLL:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
+
+
+def tile_widths(L: int, col: bool) -> list:
+    """[(tile width, transforms per slot), ...] the column (col) or row pass
+    has kernels for at transform length L, the default first."""
+    lib = load()
+    w = (ctypes.c_int32 * 64)()
+    p = (ctypes.c_int32 * 64)()
+    n = lib.sfd_tile_widths(int(L), 1 if col else 0, w, p, 64)
+    if n < 0:
+        raise SfdError(SFD_ERR_INVALID_ARG, lib.sfd_last_error().decode())
+    return [(w[k], p[k]) for k in range(min(n, 64))]
 
 
 def check(status: int) -> None:

@@ -28,12 +28,16 @@ namespace sfd {
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+// Complex products with the fused multiply-adds written out, so that every
+// call site rounds the same way whatever the compiler's contraction choices
+// around it (kernels that hold a transform differently then still agree
+// bit for bit).
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  return make_float2(fmaf(a.x, b.x, -(a.y * b.y)), fmaf(a.x, b.y, a.y * b.x));
 }
 // a * conj(b)
 __device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
-  return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+  return make_float2(fmaf(a.x, b.x, a.y * b.y), fmaf(a.y, b.x, -(a.x * b.y)));
 }
 
 // cos(2 pi k / 32) for k = 0..8; other angles follow by symmetry.
@@ -72,7 +76,7 @@ __device__ __forceinline__ float2 mul_w(float2 a) {
     constexpr float ss = s > 0 ? 1.f : -1.f;
     return make_float2((sc * a.x - ss * a.y) * h, (ss * a.x + sc * a.y) * h);
   } else {
-    return make_float2(a.x * c - a.y * s, a.x * s + a.y * c);
+    return make_float2(fmaf(a.x, c, -(a.y * s)), fmaf(a.x, s, a.y * c));
   }
 }
 

@@ -540,14 +540,19 @@ sfd_status launch_rows(const CallDescs& D, const sfd::RowJob* d_rows, int first,
     }
     a.tile_prefix[j - i] = acc;
     a.total_tiles = acc;
-    bool fast = true, int_only = true;
+    // Kernel specialisation (see launch_pass).
+    bool fast = true, no_post = true, int_only = true, all_real = true, all_complex = true;
     for (int k = i; k < j; ++k) {
       const sfd::RowJob& r = D.rows[k];
       fast = fast && 2 * r.n_in == L && 2 * r.n_out <= L && !(r.mode & sfd::kReduce);
-      int_only = int_only && !(r.mode & sfd::kUsePost) &&
-                 (col || ((r.mode & sfd::kOutIntensity) && !(r.mode & sfd::kOutField)));
+      no_post = no_post && !(r.mode & sfd::kUsePost);
+      int_only = int_only && (r.mode & sfd::kOutIntensity) && !(r.mode & sfd::kOutField);
+      all_real = all_real && (r.mode & sfd::kInReal);
+      all_complex = all_complex && !(r.mode & sfd::kInReal);
     }
-    const int var = !fast ? 0 : int_only ? 2 : 1;
+    int var = 0;
+    if (fast && col) var = all_complex ? 1 : !all_real ? 0 : no_post ? 2 : 3;
+    else if (fast && all_complex) var = no_post && int_only ? 2 : 1;
     const float2* tw = reinterpret_cast<const float2*>(ws + P->tw_off.at(L));
     SFD_TIMED(P, kind, stream, sfd::launch_pass(L, col, G, var, a, tw, stream));
     i = j;
@@ -1294,6 +1299,21 @@ sfd_status sfd_schedule(sfd_plan_t plan, int32_t L, int32_t col, int32_t* tile_w
     return fail(SFD_ERR_INVALID_ARG, "the plan has no transforms of length " + std::to_string(L));
   *tile_width = plan->tile_g(L, col != 0);
   return SFD_OK;
+}
+
+int32_t sfd_tile_widths(int32_t L, int32_t col, int32_t* widths, int32_t* per_slot, int32_t cap) {
+  g_err.clear();
+  if (cap < 0 || (cap > 0 && !widths)) {
+    fail(SFD_ERR_INVALID_ARG, "sfd_tile_widths: cap < 0, or widths is NULL");
+    return -1;
+  }
+  int w[64], p[64];
+  const int n = sfd::pass_tile_widths(L, col != 0, w, 64, p);
+  for (int k = 0; k < std::min(n, (int)cap); ++k) {
+    widths[k] = w[k];
+    if (per_slot) per_slot[k] = p[k];
+  }
+  return n;
 }
 
 sfd_status sfd_set_schedule(sfd_plan_t plan, int32_t L, int32_t col, int32_t tile_width) {

@@ -170,18 +170,23 @@ hipError_t launch_setup(const SetupArgs& args, hipStream_t s);
 int spectra_per_block(int L);
 
 // col = true: the y transforms (column kernel); false: the x transforms.
-// G is the tile width: one of pass_tile_widths(L, col).  var selects a
-// specialised kernel: 1 when every job has n_in == L/2, n_out <= L/2 and no
-// kReduce; 2 when, in addition, no job applies a post-chirp (and, in the row
-// pass, every job writes intensities only); 0 otherwise.
+// G is the tile width (transforms per workgroup): one of
+// pass_tile_widths(L, col).  var selects a
+// specialised kernel.  Row pass: 1 when every job has n_in == L/2,
+// n_out <= L/2, a complex input and no kReduce; 2 when, in addition, no job
+// applies a post-chirp and every job writes intensities only.  Column pass:
+// 1 when every job has n_in == L/2, n_out <= L/2 and a complex input; 2 when
+// every job has n_in == L/2, n_out <= L/2, a real input and no post-chirp;
+// 3 as 2 with post-chirps allowed.  0 otherwise.
 hipError_t launch_pass(int L, bool col, int G, int var, const PassArgs& args, const float2* tw, hipStream_t s);
 
 hipError_t launch_gradz(const GradZJob* d_jobs, int njobs, hipStream_t s);
 hipError_t launch_gather(const GatherJob* d_jobs, int njobs, int max_n, hipStream_t s);
 
 // Tile widths (transforms per workgroup) a pass supports at length L, the
-// default first; returns how many there are (writes at most cap of them).
-int pass_tile_widths(int L, bool col, int* widths, int cap);
+// default first; returns how many there are (writes at most cap of them,
+// and, when per_slot is set, the transforms each slot runs in turn).
+int pass_tile_widths(int L, bool col, int* widths, int cap, int* per_slot = nullptr);
 // The default tile width of a pass at length L (0 if L is unsupported).
 int rows_per_tile(int L, bool col);
 bool supported_length(int L);

@@ -313,13 +313,18 @@ __global__ void __launch_bounds__(kSetupThreads) setup_kernel(const SetupArgs A)
 #define SFD_COL_WPE 1
 #endif
 
-// Workgroup shape of a pass: G rows (or columns) of TPR threads each.
-template <int L, int G_>
+// Workgroup shape of a pass: G transforms (rows or columns) per workgroup,
+// held by NS = G / P slots of TPR threads each; a slot runs P transforms in
+// turn.
+template <int L, int G_, int P_ = 1>
 struct PassShape {
   static constexpr int TPR = PassPlan<L>::TPR;
   static constexpr int G = G_;
-  static constexpr int THREADS = G * TPR;
+  static constexpr int P = P_;
+  static constexpr int NS = G_ / P_;
+  static constexpr int THREADS = NS * TPR;
   static constexpr int NW = THREADS / 64;
+  static_assert(G_ % P_ == 0, "a slot runs a whole number of transforms");
   static_assert(THREADS % 64 == 0 && THREADS <= 1024, "a pass workgroup is 1 to 16 whole wavefronts");
 };
 
@@ -343,9 +348,39 @@ __device__ __forceinline__ int find_job(const PassArgs& args, int tile) {
   return lo;
 }
 
+// Stores through a buffer resource of a given extent in bytes: the hardware
+// drops a store whose offset lies at or past the extent (range checking of
+// raw buffer addressing).  A store that only some lanes make is then still
+// one unconditional instruction, so the number of memory operations in
+// flight does not depend on the predicate, and a later wait for an earlier
+// load does not have to wait for the stores too.  kDrop lies past every
+// extent used here: extents are at most L/2 rows of a grid no wider than
+// 8192 + padding complex entries, far below 2^31 bytes.
+constexpr uint32_t kDrop = 0x80000000u;
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t store_rsrc(void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t off, float x) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), r, (int)off, 0, 0);
+}
+__device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t off, float2 x) {
+  const u32x2_t w = {__builtin_bit_cast(uint32_t, x.x), __builtin_bit_cast(uint32_t, x.y)};
+  __builtin_amdgcn_raw_buffer_store_b64(w, r, (int)off, 0, 0);
+}
+
 // Wave-uniform value (the compiler then keeps it, and addresses built from
 // it, in scalar registers).
 __device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// The same value, opaque to the compiler: addresses derived from it inside
+// a loop are then formed in each iteration rather than hoisted out of the
+// loop and held in registers across it.
+__device__ __forceinline__ int opaque(int x) {
+  int y;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(y) : "v"(x));
+  return y;
+}
 
 // The padded, pre-chirped row (n >= 1).  The common case n = L/2 (the
 // paper's doubled grid) is straight-line code; otherwise loads go to a
@@ -400,13 +435,13 @@ __device__ __forceinline__ void load_row(float2 (&v)[R], const void* in, const f
   else load_row_t<TPR, R, REAL, false>(v, in, pre, n, t);
 }
 
-// Epilogue reduction of the row kernel (see RowJob): FP64 per thread, then
-// across the wavefront and the workgroup in a fixed order, one complex pair
-// per tile into J.partial.
-template <int TPR, int R, int NW>
-__device__ __forceinline__ void row_reduce(const RowJob& J, const float2 (&v)[R], int row, bool valid, int t, int tile,
-                                           double* sbuf) {
-  double a[4] = {0.0, 0.0, 0.0, 0.0};
+// Epilogue reduction of the row kernel (see RowJob): FP64 per thread over
+// the rows it holds (row_accumulate), then across the wavefront and the
+// workgroup in a fixed order, one complex pair per tile into J.partial
+// (reduce_tile).
+template <int TPR, int R>
+__device__ __forceinline__ void row_accumulate(const RowJob& J, const float2 (&v)[R], int row, bool valid, int t,
+                                               double (&a)[4]) {
   if (valid) {
     const int n_out = J.n_out;
     const int mode = J.mode;
@@ -453,6 +488,9 @@ __device__ __forceinline__ void row_reduce(const RowJob& J, const float2 (&v)[R]
       }
     }
   }
+}
+template <int NW>
+__device__ __forceinline__ void reduce_tile(const RowJob& J, double (&a)[4], int tile, double* sbuf) {
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
 #pragma unroll
@@ -485,18 +523,88 @@ struct SharedTables {
   static constexpr int src = on ? kTwShared : kTwGlobal;
 };
 
-template <int L, int THREADS>
-__device__ __forceinline__ void stage_tables(float2* tws, float2* hs, const float2* __restrict__ tw,
-                                             const float2* __restrict__ H) {
+// Cooperative copies into LDS at the start of a workgroup: the twiddle
+// table, the job's H and, for slots that run several transforms of the job
+// (PRE), the first L/2 entries of its pre-chirp when it has one.  Every
+// thread issues all of its loads before its first LDS write, so that their
+// latencies overlap; a thread past the end of a table reloads its last
+// entry instead of skipping the load, which keeps the loads branch-free.
+template <int N, int THREADS>
+struct CopyShare {
+  static constexpr int K = N > 0 ? (N + THREADS - 1) / THREADS : 0;
+  static constexpr int KA = K > 0 ? K : 1;  // register array size
+};
+template <int N, int THREADS, int KA>
+__device__ __forceinline__ void copy_load(float4 (&r)[KA], const float2* src) {
+  const float4* s4 = reinterpret_cast<const float4*>(src);
+#pragma unroll
+  for (int k = 0; k < CopyShare<N, THREADS>::K; ++k) {
+    const int e = threadIdx.x + k * THREADS;
+    r[k] = gld(s4, (unsigned)(e < N ? e : N - 1));
+  }
+}
+template <int N, int THREADS, int KA>
+__device__ __forceinline__ void copy_store(float2* dst, const float4 (&r)[KA]) {
+  float4* d4 = reinterpret_cast<float4*>(dst);
+#pragma unroll
+  for (int k = 0; k < CopyShare<N, THREADS>::K; ++k) {
+    const int e = threadIdx.x + k * THREADS;
+    if (N % THREADS == 0 || e < N) d4[e] = r[k];
+  }
+}
+template <int L, int THREADS, bool PRE>
+__device__ __forceinline__ void stage_tables(float2* tws, float2* hs, float2* ps, const float2* __restrict__ tw,
+                                             const float2* __restrict__ H, const float2* __restrict__ pre) {
   static_assert(SharedTables<L>::tw_n % 2 == 0, "tables are copied two entries at a time");
-  float4* t4 = reinterpret_cast<float4*>(tws);
-  float4* h4 = reinterpret_cast<float4*>(hs);
-  const float4* tg = reinterpret_cast<const float4*>(tw);
-  const float4* hg = reinterpret_cast<const float4*>(H);
-#pragma unroll 4
-  for (int e = threadIdx.x; e < SharedTables<L>::tw_n / 2; e += THREADS) t4[e] = gld(tg, (unsigned)e);
-#pragma unroll 4
-  for (int e = threadIdx.x; e < L / 2; e += THREADS) h4[e] = gld(hg, (unsigned)e);
+  constexpr int NT = SharedTables<L>::tw_n / 2;
+  constexpr int NH = L / 2;
+  constexpr int NP = PRE ? L / 4 : 0;
+  float4 a[CopyShare<NT, THREADS>::KA];
+  float4 b[CopyShare<NH, THREADS>::KA];
+  float4 c[CopyShare<NP, THREADS>::KA];
+  copy_load<NT, THREADS>(a, tw);
+  copy_load<NH, THREADS>(b, H);
+  if constexpr (PRE) {
+    if (pre) copy_load<NP, THREADS>(c, pre);
+  }
+  copy_store<NT, THREADS>(tws, a);
+  copy_store<NH, THREADS>(hs, b);
+  if constexpr (PRE) {
+    if (pre) copy_store<NP, THREADS>(ps, c);
+  }
+}
+
+// The common case (input of L/2 samples) in two steps, so that the loads of
+// the next transform can be issued before the current one is computed:
+// fetch_half loads the raw first half (a real input only into .x),
+// apply_half forms the padded, pre-chirped row from it (pre from LDS, or
+// none when ps is null).
+template <int TPR, bool REAL, int H>
+__device__ __forceinline__ void fetch_half(float2 (&x)[H], const void* in, int64_t off, int t) {
+  if constexpr (REAL) {
+    const float* p = static_cast<const float*>(in) + off;
+#pragma unroll
+    for (int i = 0; i < H; ++i) x[i].x = gld(p, (unsigned)(t + TPR * i));
+  } else {
+    const float2* p = static_cast<const float2*>(in) + off;
+#pragma unroll
+    for (int i = 0; i < H; ++i) x[i] = gld(p, (unsigned)(t + TPR * i));
+  }
+}
+template <int TPR, int R, bool REAL>
+__device__ __forceinline__ void apply_half(float2 (&v)[R], const float2 (&x)[R / 2], const float2* ps, int t) {
+  if (!ps) {
+#pragma unroll
+    for (int i = 0; i < R / 2; ++i) v[i] = REAL ? make_float2(x[i].x, 0.f) : x[i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < R / 2; ++i) {
+      const float2 p = ps[t + TPR * i];
+      v[i] = REAL ? make_float2(x[i].x * p.x, x[i].x * p.y) : cmul(x[i], p);
+    }
+  }
+#pragma unroll
+  for (int i = R / 2; i < R; ++i) v[i] = make_float2(0.f, 0.f);
 }
 
 // x transforms: row r of the job reads in + r * in_ld and writes
@@ -505,23 +613,29 @@ __device__ __forceinline__ void stage_tables(float2* tws, float2* hs, const floa
 // small: 0 = any job; 1 = every job of the launch has an input of L/2
 // samples, an output of at most L/2 and no reduction (half loads, pruned
 // transforms, no reduction epilogue); 2 = as 1, and the jobs write only
-// intensities.
-template <int L, int GR, int VAR>
-__global__ void __launch_bounds__((PassShape<L, GR>::THREADS)) __attribute__((amdgpu_waves_per_eu(SFD_ROW_WPE))) row_kernel(const PassArgs args, const float2* __restrict__ tw) {
-  using S = PassShape<L, GR>;
+// intensities.  P > 1: each slot runs P rows of its tile in turn; in the
+// specialisations the next row's input is fetched while the current row is
+// transformed, and the pre-chirp is read from an LDS copy.
+template <int L, int GR, int VAR, int P>
+__global__ void __launch_bounds__((PassShape<L, GR, P>::THREADS)) __attribute__((amdgpu_waves_per_eu(SFD_ROW_WPE))) row_kernel(const PassArgs args, const float2* __restrict__ tw) {
+  using S = PassShape<L, GR, P>;
   constexpr int TPR = S::TPR;
   constexpr int R = L / TPR;
-  constexpr int G = S::G;
+  constexpr int NS = S::NS;
   constexpr int RB = row_lds_bytes<L, kSplit>();
   constexpr bool FAST = VAR >= 1;
   constexpr bool INT_ONLY = VAR == 2;
+  constexpr bool PF = FAST && P > 1;
   using T = SharedTables<L>;
-  // Shared tables, exchange buffers, then room for the epilogue reduction (4
-  // doubles per wavefront).
-  __shared__ __align__(16) unsigned char lds[T::bytes + G * RB + S::NW * 32];
+  static_assert(P == 1 || (T::on && TPR <= 64), "slots of several transforms are single wavefronts with LDS tables");
+  constexpr int PRE_BYTES = PF ? (L / 2) * 8 : 0;
+  // Shared tables, the pre-chirp copy, exchange buffers, then room for the
+  // epilogue reduction (4 doubles per wavefront).
+  __shared__ __align__(16) unsigned char lds[T::bytes + PRE_BYTES + NS * RB + S::NW * 32];
   float2* tws = reinterpret_cast<float2*>(lds);
   float2* hs = tws + T::tw_n;
-  unsigned char* xbuf = lds + T::bytes;
+  float2* ps = reinterpret_cast<float2*>(lds + T::bytes);
+  unsigned char* xbuf = lds + T::bytes + PRE_BYTES;
 
   const int tile = xcd_tile(blockIdx.x, args.total_tiles);
   const int jid = find_job(args, tile);
@@ -529,75 +643,143 @@ __global__ void __launch_bounds__((PassShape<L, GR>::THREADS)) __attribute__((am
   // With TPR >= 64 a row is a whole number of wavefronts: g is wave-uniform.
   const int g = TPR >= 64 ? uniform(threadIdx.x / TPR) : threadIdx.x / TPR;
   const int t = threadIdx.x - g * TPR;
-  const int row = (tile - args.tile_prefix[jid]) * G + g;
-  const bool valid = row < J.n_rows;
-  const int vrow = valid ? row : 0;
+  // Slot g runs rows row0 + p NS, p < P.  A row past the end of the job
+  // computes on row 0 and stores nothing.
+  const int row0 = (tile - args.tile_prefix[jid]) * GR + g;
+  // The job's fields, read once here (before any store, so that they can be
+  // scalar loads) rather than at their uses inside the row loop.
+  const int n_rows = J.n_rows;
   const int n_in = J.n_in;
-
-  // A row past the end of the job computes on row 0 and stores nothing.
-  float2 v[R];
-  if constexpr (FAST) {
-    if (J.mode & kInReal)
-      load_half<TPR, R, true>(v, static_cast<const float*>(J.in) + (int64_t)vrow * J.in_ld, J.pre, t);
-    else
-      load_half<TPR, R, false>(v, static_cast<const float2*>(J.in) + (int64_t)vrow * J.in_ld, J.pre, t);
-  } else {
-    if (J.mode & kInReal)
-      load_row<TPR, R, true>(v, static_cast<const float*>(J.in) + (int64_t)vrow * J.in_ld, J.pre, n_in, t);
-    else
-      load_row<TPR, R, false>(v, static_cast<const float2*>(J.in) + (int64_t)vrow * J.in_ld, J.pre, n_in, t);
-  }
-
+  const int n_out = J.n_out;
+  const int mode = J.mode;
+  // Row jobs of the specialisations read complex inputs (the launcher
+  // checks); the general kernel takes either.
+  const bool real_in = !FAST && (mode & kInReal) != 0;
+  const void* in = J.in;
+  const int64_t in_ld = J.in_ld;
+  const int64_t out_ld = J.out_ld;
+  const float2* __restrict__ pre = J.pre;
   const float2* __restrict__ H = J.H;
+  const float2* __restrict__ post = J.post;
+  void* const out1 = J.out;
+  float* const out2 = J.out2;
+  const float sc = J.iscale;
+
+  float2 v[R];
+  float2 x[PF ? R / 2 : 1];
+  auto load = [&](int row, int t) {
+    const int64_t off = (int64_t)(row < n_rows ? row : 0) * in_ld;
+    if constexpr (PF) {
+      fetch_half<TPR, false>(x, in, off, t);
+    } else if constexpr (FAST) {
+      load_half<TPR, R, false>(v, static_cast<const float2*>(in) + off, pre, t);
+    } else {
+      if (real_in) load_row<TPR, R, true>(v, static_cast<const float*>(in) + off, pre, n_in, t);
+      else load_row<TPR, R, false>(v, static_cast<const float2*>(in) + off, pre, n_in, t);
+    }
+  };
+  load(row0, t);
+
   if constexpr (T::on) {
-    stage_tables<L, S::THREADS>(tws, hs, tw, H);
+    stage_tables<L, S::THREADS, PF>(tws, hs, ps, tw, H, pre);
     __syncthreads();
   }
   const float2* twx = T::on ? tws : tw;
   void* buf = xbuf + g * RB;
-  const int n_out = J.n_out;
-  const int mode = J.mode;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
   // HALF: the common case (input of L/2 samples, output of at most L/2),
   // where the first forward and the last inverse stage skip the padded and
   // the cropped half.
   auto body = [&](auto half_c) {
     constexpr bool HALF = decltype(half_c)::value;
     constexpr int RL = HALF ? R / 2 : R;
-    fft_row<PassPlan<L>, false, kSplit, T::src, HALF>(v, buf, t, twx);
-    sched_fence();
+    // HALF with a row per wavefront: a row's outputs (field of, intensity
+    // oi) leave through one store resource per row, of n_out entries (none
+    // for a row past the job's end).  With several rows per slot, a row's
+    // outputs are stored only once the next row's input has arrived: the
+    // wait for that input then finds no store of this row in flight.
+    constexpr bool BUF = HALF && TPR >= 64;
+    float2 of[BUF && !INT_ONLY ? RL : 1];
+    float oi[BUF ? RL : 1];
+    auto flush = [&](int r, int lane) {
+      if constexpr (BUF) {
+        const uint32_t lim = r < n_rows ? (uint32_t)n_out : 0u;
+        if (!INT_ONLY && (mode & kOutField)) {
+          const auto rs = store_rsrc(static_cast<float2*>(out1) + (int64_t)r * out_ld, lim * 8u);
 #pragma unroll
-    for (int i = 0; i < R; ++i) v[i] = cmul(v[i], T::on ? hs[t + TPR * i] : gld(H, (unsigned)(t + TPR * i)));
-    sched_fence();
-    fft_row<PassPlan<L>, true, kSplit, T::src, HALF>(v, buf, t, twx);
+          for (int i = 0; i < RL; ++i) bst(rs, (uint32_t)(lane + TPR * i) * 8u, of[i]);
+        }
+        if (mode & kOutIntensity) {
+          float* o = ((!INT_ONLY && (mode & kOutField)) ? out2 : static_cast<float*>(out1)) + (int64_t)r * out_ld;
+          const auto rs = store_rsrc(o, lim * 4u);
+#pragma unroll
+          for (int i = 0; i < RL; ++i) bst(rs, (uint32_t)(lane + TPR * i) * 4u, oi[i]);
+        }
+      }
+    };
+#pragma unroll 1
+    for (int p = 0; p < P; ++p) {
+      const int tl = P > 1 ? opaque(t) : t;
+      const int row = row0 + p * NS;
+      const bool valid = row < n_rows;
+      if constexpr (PF) {
+        apply_half<TPR, R, false>(v, x, pre ? ps : nullptr, tl);
+        sched_fence();
+        if (p > 0) flush(row - NS, tl);
+        sched_fence();
+        if (p + 1 < P) load(row + NS, tl);
+      } else if (p > 0) {
+        load(row, tl);
+      }
+      fft_row<PassPlan<L>, false, kSplit, T::src, HALF>(v, buf, tl, twx);
+      sched_fence();
+#pragma unroll
+      for (int i = 0; i < R; ++i) v[i] = cmul(v[i], T::on ? hs[tl + TPR * i] : gld(H, (unsigned)(tl + TPR * i)));
+      sched_fence();
+      fft_row<PassPlan<L>, true, kSplit, T::src, HALF>(v, buf, tl, twx);
 
-    if (!INT_ONLY && (mode & kUsePost)) {
-      const float2* post = J.post;
+      if (!INT_ONLY && (mode & kUsePost)) {
 #pragma unroll
-      for (int i = 0; i < RL; ++i) {
-        const int m = t + TPR * i;
-        if (TPR * (i + 1) <= n_out || m < n_out) v[i] = cmul(v[i], gld(post, (unsigned)m));
+        for (int i = 0; i < RL; ++i) {
+          const int m = tl + TPR * i;
+          // HALF: a clamped (branch-free) load; entries past n_out are never stored.
+          if (HALF) v[i] = cmul(v[i], gld(post, (unsigned)(m < n_out ? m : n_out - 1)));
+          else if (TPR * (i + 1) <= n_out || m < n_out) v[i] = cmul(v[i], gld(post, (unsigned)m));
+        }
+      }
+      if constexpr (BUF) {
+#pragma unroll
+        for (int i = 0; i < RL; ++i) {
+          if constexpr (!INT_ONLY) of[i] = v[i];
+          oi[i] = fmaf(v[i].x, v[i].x, v[i].y * v[i].y) * sc;
+        }
+        if constexpr (!PF) flush(row, tl);
+      } else {
+        if (!INT_ONLY && valid && (mode & kOutField)) {
+          float2* out = static_cast<float2*>(out1) + (int64_t)row * out_ld;
+#pragma unroll
+          for (int i = 0; i < RL; ++i) {
+            const int m = tl + TPR * i;
+            if (TPR * (i + 1) <= n_out || m < n_out) gst(out, (unsigned)m, v[i]);
+          }
+        }
+        if (valid && (mode & kOutIntensity)) {
+          float* out = ((!INT_ONLY && (mode & kOutField)) ? out2 : static_cast<float*>(out1)) + (int64_t)row * out_ld;
+#pragma unroll
+          for (int i = 0; i < RL; ++i) {
+            const int m = tl + TPR * i;
+            if (TPR * (i + 1) <= n_out || m < n_out) gst(out, (unsigned)m, fmaf(v[i].x, v[i].x, v[i].y * v[i].y) * sc);
+          }
+        }
+      }
+      if constexpr (!HALF) {
+        if (mode & kReduce) row_accumulate<TPR, R>(J, v, row, valid, tl, acc);
       }
     }
-    if (!INT_ONLY && valid && (mode & kOutField)) {
-      float2* out = static_cast<float2*>(J.out) + (int64_t)row * J.out_ld;
-#pragma unroll
-      for (int i = 0; i < RL; ++i) {
-        const int m = t + TPR * i;
-        if (TPR * (i + 1) <= n_out || m < n_out) gst(out, (unsigned)m, v[i]);
-      }
-    }
-    if (valid && (mode & kOutIntensity)) {
-      float* out = ((!INT_ONLY && (mode & kOutField)) ? J.out2 : static_cast<float*>(J.out)) + (int64_t)row * J.out_ld;
-      const float sc = J.iscale;
-#pragma unroll
-      for (int i = 0; i < RL; ++i) {
-        const int m = t + TPR * i;
-        if (TPR * (i + 1) <= n_out || m < n_out) gst(out, (unsigned)m, (v[i].x * v[i].x + v[i].y * v[i].y) * sc);
-      }
-    }
+    if constexpr (PF) flush(row0 + (P - 1) * NS, t);
     if constexpr (!HALF) {
-      if (mode & kReduce) row_reduce<TPR, R, S::NW>(J, v, row, valid, t, tile - args.tile_prefix[jid],
-                                                             reinterpret_cast<double*>(xbuf + G * RB));
+      if (mode & kReduce)
+        reduce_tile<S::NW>(J, acc, tile - args.tile_prefix[jid], reinterpret_cast<double*>(xbuf + NS * RB));
     }
   };
   if constexpr (FAST) body(std::true_type{});
@@ -606,115 +788,185 @@ __global__ void __launch_bounds__((PassShape<L, GR>::THREADS)) __attribute__((am
 
 // y transforms: column c of the job reads in[c * in_ld + n] for n < n_in
 // (the column-major copy of its grid, see TileJob) and writes
-// out[m * out_ld + c] for m < n_out (complex).  The G columns of a workgroup
-// leave through LDS staging in chunks of L/2 rows, so that each global store
-// covers G consecutive columns.
-template <int L, int GC, int VAR>
-__global__ void __launch_bounds__((PassShape<L, GC>::THREADS)) __attribute__((amdgpu_waves_per_eu(SFD_COL_WPE))) col_kernel(const PassArgs args, const float2* __restrict__ tw) {
-  using S = PassShape<L, GC>;
+// out[m * out_ld + c] for m < n_out (complex).  The NS columns that the
+// slots of a workgroup hold at once leave through LDS staging in chunks of
+// L/2 rows, so that each global store covers NS consecutive columns.  P > 1
+// as in the row kernel.
+template <int L, int GC, int VAR, int P>
+__global__ void __launch_bounds__((PassShape<L, GC, P>::THREADS)) __attribute__((amdgpu_waves_per_eu(SFD_COL_WPE))) col_kernel(const PassArgs args, const float2* __restrict__ tw) {
+  using S = PassShape<L, GC, P>;
   constexpr int TPR = S::TPR;
   constexpr int R = L / TPR;
-  constexpr int G = S::G;
+  constexpr int NS = S::NS;
   constexpr int THREADS = S::THREADS;
-  // As in row_kernel; column passes write fields, so VAR 2 here means no
-  // post-chirp (intensity-only plans).
+  // VAR: 0 = any job; 1 = the jobs' inputs are L/2 samples, complex, their
+  // outputs at most L/2; 2 = as 1 with real inputs and no post-chirp (the
+  // hologram of an intensity-only plan); 3 = as 1 with real inputs.
   constexpr bool FAST = VAR >= 1;
+  constexpr bool REAL = VAR >= 2;
   constexpr bool NO_POST = VAR == 2;
+  constexpr bool PF = FAST && P > 1;
   constexpr int RB = row_lds_bytes<L, kSplit>();
   constexpr int C = L / 2;    // staging chunk along the transform
   constexpr int SST = C + 9;  // staging stride per column (elements)
-  constexpr int STAGE_BYTES = G * SST * 8;
-  constexpr int XCH_BYTES = G * RB > STAGE_BYTES ? G * RB : STAGE_BYTES;
+  constexpr int STAGE_BYTES = NS * SST * 8;
+  constexpr int XCH_BYTES = NS * RB > STAGE_BYTES ? NS * RB : STAGE_BYTES;
   using T = SharedTables<L>;
-  static_assert((G & (G - 1)) == 0, "columns per workgroup must be a power of two");
-  // Shared tables, then the exchange buffers (reused as the store staging).
-  __shared__ __align__(16) unsigned char lds[T::bytes + XCH_BYTES];
+  static_assert((NS & (NS - 1)) == 0, "slots per workgroup must be a power of two");
+  static_assert(P == 1 || (T::on && TPR <= 64), "slots of several transforms are single wavefronts with LDS tables");
+  constexpr int PRE_BYTES = PF ? (L / 2) * 8 : 0;
+  // Shared tables, the pre-chirp copy, then the exchange buffers (reused as
+  // the store staging).
+  __shared__ __align__(16) unsigned char lds[T::bytes + PRE_BYTES + XCH_BYTES];
   float2* tws = reinterpret_cast<float2*>(lds);
   float2* hs = tws + T::tw_n;
-  unsigned char* xbuf = lds + T::bytes;
+  float2* ps = reinterpret_cast<float2*>(lds + T::bytes);
+  unsigned char* xbuf = lds + T::bytes + PRE_BYTES;
   float2* st = reinterpret_cast<float2*>(xbuf);
 
   const int tile = xcd_tile(blockIdx.x, args.total_tiles);
   const int jid = find_job(args, tile);
   const RowJob& J = args.jobs[jid];
-  const int c0 = (tile - args.tile_prefix[jid]) * G;
+  const int c0 = (tile - args.tile_prefix[jid]) * GC;
   const int g = TPR >= 64 ? uniform(threadIdx.x / TPR) : threadIdx.x / TPR;
   const int t = threadIdx.x - g * TPR;
+  // The job's fields, read once here (before any store, so that they can be
+  // scalar loads) rather than at their uses inside the column loop.
   const int ncols = J.n_rows;
   const int n_in = J.n_in;
+  const int n_out = J.n_out;
+  const int mode = J.mode;
   const int in_ld = (int)J.in_ld;
+  const int out_ld = (int)J.out_ld;
+  const void* in = J.in;
+  float2* const out0 = static_cast<float2*>(J.out);
   const float2* __restrict__ pre = J.pre;
-  const bool real_in = (J.mode & kInReal) != 0;
-  // Column of the store staging loop for this thread (fixed: THREADS is a multiple of G).
-  const int gs = threadIdx.x & (G - 1);
-  const bool col_ok = c0 + gs < ncols;
-
-  // Column c0 + g of the column-major input copy, loaded like a row (a
-  // column past the grid's edge computes on the last one and stores nothing).
-  const int cl = c0 + g < ncols ? c0 + g : ncols - 1;
-  float2 v[R];
-  if constexpr (FAST) {
-    if (real_in) load_half<TPR, R, true>(v, static_cast<const float*>(J.in) + (int64_t)cl * in_ld, pre, t);
-    else load_half<TPR, R, false>(v, static_cast<const float2*>(J.in) + (int64_t)cl * in_ld, pre, t);
-  } else {
-    if (real_in)
-      load_row<TPR, R, true>(v, static_cast<const float*>(J.in) + (int64_t)cl * in_ld, pre, n_in, t);
-    else
-      load_row<TPR, R, false>(v, static_cast<const float2*>(J.in) + (int64_t)cl * in_ld, pre, n_in, t);
-  }
-
   const float2* __restrict__ H = J.H;
+  const float2* __restrict__ post = J.post;
+  const float2* __restrict__ colscale = J.colscale;
+  const bool real_in = FAST ? REAL : (mode & kInReal) != 0;
+
+  // Slot g runs columns c0 + p NS + g, p < P, each loaded like a row from the
+  // column-major input copy (a column past the grid's edge computes on the
+  // last one and stores nothing), with its colscale factor.
+  float2 v[R];
+  float2 x[PF ? R / 2 : 1];
+  float2 csn = make_float2(1.f, 0.f);
+  auto load = [&](int p, int t) {
+    const int c = c0 + p * NS + g;
+    const int cl = c < ncols ? c : ncols - 1;
+    const int64_t off = (int64_t)cl * in_ld;
+    if constexpr (PF) {
+      fetch_half<TPR, REAL>(x, in, off, t);
+    } else if constexpr (FAST) {
+      if constexpr (REAL) load_half<TPR, R, true>(v, static_cast<const float*>(in) + off, pre, t);
+      else load_half<TPR, R, false>(v, static_cast<const float2*>(in) + off, pre, t);
+    } else {
+      if (real_in) load_row<TPR, R, true>(v, static_cast<const float*>(in) + off, pre, n_in, t);
+      else load_row<TPR, R, false>(v, static_cast<const float2*>(in) + off, pre, n_in, t);
+    }
+    if (colscale) csn = gld(colscale, (unsigned)cl);
+  };
+  load(0, t);
+
   if constexpr (T::on) {
-    stage_tables<L, THREADS>(tws, hs, tw, H);
+    stage_tables<L, THREADS, PF>(tws, hs, ps, tw, H, pre);
     __syncthreads();
   }
   const float2* twx = T::on ? tws : tw;
   void* buf = xbuf + g * RB;
-  const int n_out = J.n_out;
-  float2* out = static_cast<float2*>(J.out) + c0 + gs;
-  const int out_ld = (int)J.out_ld;
   // HALF as in the row kernel; then only the first staging chunk exists.
   auto body = [&](auto half_c) {
     constexpr bool HALF = decltype(half_c)::value;
     constexpr int RL = HALF ? R / 2 : R;
     constexpr int NC = HALF ? 1 : 2;
-    fft_row<PassPlan<L>, false, kSplit, T::src, HALF>(v, buf, t, twx);
-    sched_fence();
+    // HALF: a round's staged values (R / 2 per thread) leave through a
+    // store resource of n_out rows from the round's first column cb: rows
+    // m >= n_out fall past its extent, columns past the grid's edge are sent
+    // past it.  With several rounds, a round's values stay staged until the
+    // next round's input has arrived, and are stored then (as in the row
+    // kernel).
+    auto flush = [&](int cb, int tid) {
+      if constexpr (HALF) {
+        const int gs = tid & (NS - 1);
+        const bool col_ok = cb + gs < ncols;
+        const auto rs = store_rsrc(out0 + cb, (uint32_t)(n_out * out_ld) * 8u);
 #pragma unroll
-    for (int i = 0; i < R; ++i) v[i] = cmul(v[i], T::on ? hs[t + TPR * i] : gld(H, (unsigned)(t + TPR * i)));
-    sched_fence();
-    fft_row<PassPlan<L>, true, kSplit, T::src, HALF>(v, buf, t, twx);
+        for (int k = 0; k < R / 2; ++k) {
+          const int m = (tid + k * THREADS) / NS;
+          bst(rs, col_ok ? (uint32_t)(m * out_ld + gs) * 8u : kDrop, st[gs * SST + m]);
+        }
+      }
+    };
+#pragma unroll 1
+    for (int p = 0; p < P; ++p) {
+      const int tl = P > 1 ? opaque(t) : t;
+      const int tid = P > 1 ? opaque((int)threadIdx.x) : (int)threadIdx.x;
+      // Column of the store staging loop for this thread (fixed: THREADS is a multiple of NS).
+      const int gs = tid & (NS - 1);
+      const int cb = c0 + p * NS;  // first column of this round
+      const bool col_ok = cb + gs < ncols;
+      float2* out = out0 + cb + gs;
+      float2 cs;
+      if constexpr (PF) {
+        cs = csn;
+        apply_half<TPR, R, REAL>(v, x, pre ? ps : nullptr, tl);
+        sched_fence();
+        if (p > 0) {
+          flush(cb - NS, tid);
+          // The exchanges below reuse the staging memory.
+          __syncthreads();
+        }
+        if (p + 1 < P) load(p + 1, tl);
+      } else {
+        if (p > 0) load(p, tl);
+        cs = csn;
+      }
+      fft_row<PassPlan<L>, false, kSplit, T::src, HALF>(v, buf, tl, twx);
+      sched_fence();
+#pragma unroll
+      for (int i = 0; i < R; ++i) v[i] = cmul(v[i], T::on ? hs[tl + TPR * i] : gld(H, (unsigned)(tl + TPR * i)));
+      sched_fence();
+      fft_row<PassPlan<L>, true, kSplit, T::src, HALF>(v, buf, tl, twx);
 
-    if (!NO_POST && (J.mode & kUsePost)) {
-      const float2* post = J.post;
+      if (!NO_POST && (mode & kUsePost)) {
 #pragma unroll
-      for (int i = 0; i < RL; ++i) {
-        const int m = t + TPR * i;
-        if (TPR * (i + 1) <= n_out || m < n_out) v[i] = cmul(v[i], gld(post, (unsigned)m));
+        for (int i = 0; i < RL; ++i) {
+          const int m = tl + TPR * i;
+          // HALF: a clamped (branch-free) load; entries past n_out are never stored.
+          if (HALF) v[i] = cmul(v[i], gld(post, (unsigned)(m < n_out ? m : n_out - 1)));
+          else if (TPR * (i + 1) <= n_out || m < n_out) v[i] = cmul(v[i], gld(post, (unsigned)m));
+        }
       }
-    }
-    if (J.colscale) {
-      const float2 cs = gld(J.colscale, (unsigned)cl);
+      if (colscale) {
 #pragma unroll
-      for (int i = 0; i < RL; ++i) v[i] = cmul(v[i], cs);
-    }
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      const int m_lo = c * C;
-      if (m_lo >= n_out) break;
-      __syncthreads();
-#pragma unroll
-      for (int i = c * (R / 2); i < (c + 1) * (R / 2); ++i) {
-        const int m = t + TPR * i;
-        if (TPR * (i + 1) <= n_out || m < n_out) st[g * SST + (m - m_lo)] = v[i];
+        for (int i = 0; i < RL; ++i) v[i] = cmul(v[i], cs);
       }
-      __syncthreads();
-      const int cnt = (n_out - m_lo < C ? n_out - m_lo : C) * G;
-      for (int e = threadIdx.x; e < cnt; e += THREADS) {
-        const int m = m_lo + e / G;
-        if (col_ok) gst(out, (unsigned)(m * out_ld), st[gs * SST + (m - m_lo)]);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const int m_lo = c * C;
+        if (m_lo >= n_out) break;
+        __syncthreads();
+#pragma unroll
+        for (int i = c * (R / 2); i < (c + 1) * (R / 2); ++i) {
+          const int m = tl + TPR * i;
+          if (TPR * (i + 1) <= n_out || m < n_out) st[g * SST + (m - m_lo)] = v[i];
+        }
+        __syncthreads();
+        if constexpr (HALF) {
+          if constexpr (!PF) flush(cb, tid);
+        } else {
+          const int cnt = (n_out - m_lo < C ? n_out - m_lo : C) * NS;
+          for (int e = tid; e < cnt; e += THREADS) {
+            const int m = m_lo + e / NS;
+            if (col_ok) gst(out, (unsigned)(m * out_ld), st[gs * SST + (m - m_lo)]);
+          }
+        }
       }
+      // The next round's exchanges reuse the staging memory (PF: after its flush).
+      if (!PF && p + 1 < P) __syncthreads();
     }
+    if constexpr (PF) flush(c0 + (P - 1) * NS, threadIdx.x);
   };
   if constexpr (FAST) body(std::true_type{});
   else body(std::false_type{});
@@ -722,24 +974,28 @@ __global__ void __launch_bounds__((PassShape<L, GC>::THREADS)) __attribute__((am
 
 bool supported_length(int L) { return twiddle_len(L, false) >= 0; }
 
-// Tile widths a pass can be launched with at each length (the workgroup is
-// G * TPR threads and G exchange rows must fit in LDS); the first entry is
-// the default.
+// Shapes a pass can be launched with at each length: X(L, G, P), G the tile
+// width (transforms per workgroup), P the transforms each slot runs in turn.
+// The workgroup is G / P slots of TPR threads, and their exchange rows must
+// fit in LDS; the first entry per length is the default.
 #define SFD_ROW_SHAPES(X) \
-  X(64, 32) X(64, 16) X(64, 64) X(128, 16) X(128, 8) X(128, 32) X(256, 8) X(256, 4) X(256, 16) \
-  X(512, 4) X(512, 2) X(512, 8) X(1024, 2) X(1024, 1) X(1024, 4) X(2048, 2) X(2048, 1) X(2048, 4) \
-  X(4096, 1) X(8192, 1)
+  X(64, 32, 1) X(64, 16, 1) X(64, 64, 1) X(128, 16, 1) X(128, 8, 1) X(128, 32, 1) X(256, 8, 1) X(256, 4, 1) \
+  X(256, 16, 1) X(512, 4, 1) X(512, 2, 1) X(512, 8, 1) X(1024, 2, 1) X(1024, 1, 1) X(1024, 4, 1) X(1024, 8, 2) \
+  X(1024, 16, 4) X(2048, 2, 1) X(2048, 1, 1) X(2048, 4, 1) X(2048, 8, 2) X(2048, 16, 4) X(4096, 1, 1) X(8192, 1, 1)
 #define SFD_COL_SHAPES(X) \
-  X(64, 32) X(64, 16) X(128, 16) X(128, 8) X(256, 8) X(256, 4) X(512, 8) X(512, 4) \
-  X(1024, 8) X(1024, 4) X(1024, 16) X(2048, 8) X(2048, 4) X(2048, 2) X(4096, 2) X(4096, 4) \
-  X(8192, 1) X(8192, 2)
+  X(64, 32, 1) X(64, 16, 1) X(128, 16, 1) X(128, 8, 1) X(256, 8, 1) X(256, 4, 1) X(512, 8, 1) X(512, 4, 1) \
+  X(1024, 8, 1) X(1024, 4, 1) X(1024, 16, 1) X(1024, 32, 2) X(2048, 8, 1) X(2048, 4, 1) X(2048, 2, 1) \
+  X(2048, 16, 2) X(2048, 32, 4) X(4096, 2, 1) X(4096, 4, 1) X(8192, 1, 1) X(8192, 2, 1)
 
-int pass_tile_widths(int L, bool col, int* widths, int cap) {
+int pass_tile_widths(int L, bool col, int* widths, int cap, int* per_slot) {
   int n = 0;
-#define SFD_PUSH(l, g) \
-  if (l == L) {        \
-    if (n < cap) widths[n] = g; \
-    ++n;               \
+#define SFD_PUSH(l, g, p)          \
+  if (l == L) {                    \
+    if (n < cap) {                 \
+      widths[n] = g;               \
+      if (per_slot) per_slot[n] = p; \
+    }                              \
+    ++n;                           \
   }
   if (col) {
     SFD_COL_SHAPES(SFD_PUSH)
@@ -845,21 +1101,22 @@ int spectra_per_block(int L) {
 
 hipError_t launch_pass(int L, bool col, int G, int var, const PassArgs& a, const float2* tw, hipStream_t s) {
   if (a.total_tiles <= 0) return hipSuccess;
-#define SFD_LAUNCH_V(kern, l, g, v) \
-  hipLaunchKernelGGL((kern<l, g, v>), dim3(a.total_tiles), dim3(PassShape<l, g>::THREADS), 0, s, a, tw)
-#define SFD_LAUNCH_ROW(l, g)                          \
-  if (!col && L == l && G == g) {                     \
-    if (var == 2) SFD_LAUNCH_V(row_kernel, l, g, 2);  \
-    else if (var == 1) SFD_LAUNCH_V(row_kernel, l, g, 1); \
-    else SFD_LAUNCH_V(row_kernel, l, g, 0);           \
-    return hipGetLastError();                         \
+#define SFD_LAUNCH_V(kern, l, g, p, v) \
+  hipLaunchKernelGGL((kern<l, g, v, p>), dim3(a.total_tiles), dim3(PassShape<l, g, p>::THREADS), 0, s, a, tw)
+#define SFD_LAUNCH_ROW(l, g, p)                             \
+  if (!col && L == l && G == g) {                           \
+    if (var == 2) SFD_LAUNCH_V(row_kernel, l, g, p, 2);     \
+    else if (var == 1) SFD_LAUNCH_V(row_kernel, l, g, p, 1); \
+    else SFD_LAUNCH_V(row_kernel, l, g, p, 0);              \
+    return hipGetLastError();                               \
   }
-#define SFD_LAUNCH_COL(l, g)                          \
-  if (col && L == l && G == g) {                      \
-    if (var == 2) SFD_LAUNCH_V(col_kernel, l, g, 2);  \
-    else if (var == 1) SFD_LAUNCH_V(col_kernel, l, g, 1); \
-    else SFD_LAUNCH_V(col_kernel, l, g, 0);           \
-    return hipGetLastError();                         \
+#define SFD_LAUNCH_COL(l, g, p)                             \
+  if (col && L == l && G == g) {                            \
+    if (var == 3) SFD_LAUNCH_V(col_kernel, l, g, p, 3);     \
+    else if (var == 2) SFD_LAUNCH_V(col_kernel, l, g, p, 2); \
+    else if (var == 1) SFD_LAUNCH_V(col_kernel, l, g, p, 1); \
+    else SFD_LAUNCH_V(col_kernel, l, g, p, 0);              \
+    return hipGetLastError();                               \
   }
   SFD_ROW_SHAPES(SFD_LAUNCH_ROW)
   SFD_COL_SHAPES(SFD_LAUNCH_COL)

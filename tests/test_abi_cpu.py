@@ -22,7 +22,7 @@ def lib():
 
 def declared_functions():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:sfd_status|const char\*)\s+(sfd_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:sfd_status|const char\*|int32_t)\s+(sfd_\w+)\s*\(", text, re.M)))
 
 
 def test_header_declares_the_boundary():
@@ -48,6 +48,30 @@ def test_library_exports_every_declared_symbol(lib):
     for n in declared_functions():
         assert hasattr(lib, n), f"{n} declared in include/sfd.h but not exported"
     assert sorted(declared_functions()) == sorted(lib_mod.EXPORTED)
+
+
+def test_tile_width_query(lib):
+    """Every supported length has kernels for both passes, the default first;
+    widths are distinct; transforms per slot divide the width; the argument
+    checks and the unsupported-length answer."""
+    for L in (64, 128, 256, 512, 1024, 2048, 4096, 8192):
+        for col in (0, 1):
+            w = (ctypes.c_int32 * 64)()
+            p = (ctypes.c_int32 * 64)()
+            n = lib.sfd_tile_widths(L, col, w, p, 64)
+            assert n >= 1
+            widths, per_slot = list(w[:n]), list(p[:n])
+            assert len(set(widths)) == n
+            assert all(g % q == 0 and q >= 1 for g, q in zip(widths, per_slot))
+            one = (ctypes.c_int32 * 1)()
+            assert lib.sfd_tile_widths(L, col, one, None, 1) == n and one[0] == widths[0]
+            assert lib.sfd_tile_widths(L, col, None, None, 0) == n
+    assert lib.sfd_tile_widths(1000, 0, None, None, 0) == 0
+    assert lib.sfd_tile_widths(2048, 0, None, None, 4) == -1
+    assert lib.sfd_tile_widths(2048, 0, None, None, -1) == -1
+    # Several transforms per slot exist at the paper's padded length.
+    assert any(q > 1 for _, q in lib_mod.tile_widths(2048, True))
+    assert any(q > 1 for _, q in lib_mod.tile_widths(2048, False))
 
 
 def _grid(nx=64, ny=48, px=4.65e-6, py=4.65e-6, ox=0.0, oy=0.0):
@@ -180,14 +204,14 @@ def test_schedule_queries_and_manual_setting(lib):
     assert lib.sfd_schedule(h, 1024, 1, ctypes.byref(g)) == lib_mod.SFD_ERR_INVALID_ARG
     n0 = ctypes.c_size_t()
     assert lib.sfd_workspace_size(h, ctypes.byref(n0)) == 0
-    for col, width in ((1, 4), (1, 2), (0, 1), (0, 4)):
+    for col, width in ((1, 4), (1, 2), (1, 16), (1, 32), (0, 1), (0, 4), (0, 8), (0, 16)):
         assert lib.sfd_set_schedule(h, 2048, col, width) == 0
         assert lib.sfd_schedule(h, 2048, col, ctypes.byref(g)) == 0 and g.value == width
         n = ctypes.c_size_t()
         assert lib.sfd_workspace_size(h, ctypes.byref(n)) == 0 and n.value == n0.value
     assert lib.sfd_set_schedule(h, 2048, 1, 3) == lib_mod.SFD_ERR_INVALID_ARG
     assert b"tile width 3" in lib.sfd_last_error()
-    assert lib.sfd_set_schedule(h, 2048, 0, 16) == lib_mod.SFD_ERR_INVALID_ARG
+    assert lib.sfd_set_schedule(h, 2048, 0, 32) == lib_mod.SFD_ERR_INVALID_ARG
     assert lib.sfd_set_schedule(h, 4096, 1, 2) == lib_mod.SFD_ERR_INVALID_ARG
     assert lib.sfd_destroy(h) == 0
 

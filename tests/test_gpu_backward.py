@@ -161,3 +161,42 @@ def test_autograd_function_config4_shape():
         ez = abs(float(z.grad[b]) - ref_gz[b]) / abs(ref_gz[b])
         print(f"field {b}: grad rel L2 {e:.3e}, dL/dz rel {ez:.2e}", flush=True)
         assert e <= TOL and ez <= TOL
+
+
+def test_backward_every_tile_width():
+    """Forward and backward at the differentiation workload's shape (1024^2
+    complex fields, L = 2048) under every tile width of both passes: the
+    forward outputs and the field gradient bit for bit equal to the default
+    schedule's; dL/dz, whose FP64 partial sums are grouped by tile, to 1e-12
+    relative."""
+    w = workloads.config4(batch=2)
+    p = _plan(w, "both")
+    holo = torch.from_numpy(w.holograms).to(DEV)
+    r = np.random.default_rng(9)
+    nv = len(w.views)
+    targets = [torch.from_numpy(r.uniform(0, 1e-9, (v.grid.ny, v.grid.nx)).astype(np.float32)).to(DEV)
+               for v in w.views]
+
+    def run():
+        res = p.reconstruct(holo)
+        gi = [2.0 * (res[v] - targets[v]) for v in range(nv)]
+        gin, gz = p.backward(gi, holo, field_out=res[nv:])
+        torch.cuda.synchronize()
+        return [t.clone() for t in res], gin.clone(), gz.clone()
+
+    ref_res, ref_gin, ref_gz = run()
+    lx, ly = p.lengths(0)
+    assert (lx, ly) == (2048, 2048)
+    for col, L in ((True, ly), (False, lx)):
+        default = p.schedule()[("col" if col else "row", L)]
+        for g, per_slot in sfd.sfd_tile_widths(L, col):
+            p.set_schedule(L, col, g)
+            res, gin, gz = run()
+            for a, b in zip(res, ref_res):
+                assert torch.equal(a, b), (col, g, per_slot)
+            assert torch.equal(gin, ref_gin), (col, g, per_slot)
+            rel = (gz - ref_gz).abs() / ref_gz.abs()
+            print(f"col={col} width {g} ({per_slot} per slot): dL/dz max rel change {float(rel.max()):.2e}",
+                  flush=True)
+            assert float(rel.max()) <= 1e-12, (col, g, per_slot)
+        p.set_schedule(L, col, default)

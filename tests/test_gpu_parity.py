@@ -181,27 +181,46 @@ def test_graph_replays_equal_eager_launches():
         assert torch.equal(a, b)
 
 
-@pytest.mark.parametrize("cfg", ["config1", "config2"])
-def test_every_tile_width_gives_identical_results(cfg):
-    """Each transform is computed the same way whichever workgroup holds it,
-    so every schedule must reproduce the default bit for bit."""
-    w = getattr(workloads, cfg)()
+def _ragged(kind):
+    """Padded length 2048 with a ragged side: ``out`` maps a 1024^2 hologram to
+    a 1000^2 view (half-padded input, 1000 output rows: a partial last tile
+    for every tile width); ``in`` maps a 1000^2 hologram to a 1024^2 view (no
+    half-padded input, so the general kernels run, with several transforms
+    per slot where the width has them)."""
+    n0, n1 = (1024, 1000) if kind == "out" else (1000, 1024)
+    r = np.random.default_rng(n0 + 7 * n1)
+    g0 = workloads.GridSpec(n0, n0, 4.65e-6, 4.65e-6, 20e-6, -10e-6)
+    g1 = workloads.GridSpec(n1, n1, 5.0e-6, 4.0e-6, 100e-6, -50e-6)
+    holo = r.uniform(0, 2, (1, n0, n0)).astype(np.float32)
+    return workloads.Workload(f"ragged-{kind}", workloads.WAVELENGTH, g0, holo, [workloads.ViewSpec(g1, 0.03, 0)])
+
+
+@pytest.mark.parametrize("outputs", ["both", "intensity"])
+@pytest.mark.parametrize("cfg", ["config1", "config2", "ragged-out", "ragged-in"])
+def test_every_tile_width_gives_identical_results(cfg, outputs):
+    """Each transform is computed the same way whichever workgroup holds it
+    (and whichever slot of it, in whichever turn), so every schedule must
+    reproduce the default bit for bit; the default is checked against the
+    oracle for the ragged shapes."""
+    w = _ragged(cfg.split("-")[1]) if cfg.startswith("ragged") else getattr(workloads, cfg)()
     holo = _holo(w)
-    p = _plan(w, outputs="both")
+    p = _plan(w, outputs=outputs)
     ref = [t.clone() for t in p.reconstruct(holo)]
+    torch.cuda.synchronize()
     lx, ly = p.lengths(0)
+    if cfg.startswith("ragged"):
+        assert (lx, ly) == (2048, 2048)
+        _check(w, outputs, ref, cfg)
     for col, L in ((True, ly), (False, lx)):
         default = p.schedule()[("col" if col else "row", L)]
-        widths = {1, 2, 4, 8, 16, 32, 64}
-        for g in sorted(widths):
-            try:
-                p.set_schedule(L, col, g)
-            except sfd.SfdError:
-                continue
+        shapes = sfd.sfd_tile_widths(L, col)
+        assert shapes and shapes[0][0] == default
+        for g, per_slot in shapes:
+            p.set_schedule(L, col, g)
             got = p.reconstruct(holo)
             torch.cuda.synchronize()
             for a, b in zip(got, ref):
-                assert torch.equal(a, b), (col, L, g)
+                assert torch.equal(a, b), (col, L, g, per_slot)
         p.set_schedule(L, col, default)
 
 
