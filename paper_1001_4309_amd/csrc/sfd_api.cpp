@@ -141,6 +141,7 @@ struct sfd_plan_s {
   std::vector<TileLayout> tiles;
   std::vector<int> lengths;           // distinct L values used
   std::map<int, size_t> tw_off;       // twiddle table of the passes' shape per L
+  std::map<int, size_t> tws_off;      // twiddle table of the kernel-spectrum shape per L
   void* tw_ready_ws = nullptr;        // workspace whose twiddle tables are current
   size_t desc_off = 0, desc_bytes = 0;
   size_t ws_bytes = 0;
@@ -275,6 +276,20 @@ size_t desc_capacity(int n_views, int n_lengths, int n_tiles) {
          align_up(sizeof(sfd::TileJob) * n_tiles) + align_up(sizeof(sfd::RowJob) * 2 * n_views);
 }
 
+// The twiddle tables of length L, both shapes: the passes' and the kernel
+// spectra's (built once per workspace).
+void add_twiddle_jobs(const sfd_plan_s* P, char* ws, int L, std::vector<sfd::TwiddleJob>* out) {
+  for (int spec = 0; spec < 2; ++spec) {
+    sfd::TwiddleJob t{};
+    t.tw = reinterpret_cast<float2*>(ws + (spec ? P->tws_off.at(L) : P->tw_off.at(L)));
+    t.L = L;
+    t.count = sfd::twiddle_len(L, spec != 0);
+    t.spec = spec;
+    out->push_back(t);
+  }
+}
+
+
 sfd_status build_descs(sfd_plan_s* P, const void* holo, const double* z, void* const* out, char* ws,
                        CallDescs* D) {
   const int V = (int)P->views.size();
@@ -331,14 +346,7 @@ sfd_status build_descs(sfd_plan_s* P, const void* holo, const double* z, void* c
     D->axis_L.push_back(a.L);
   }
   D->tw.clear();
-  for (int L : P->lengths) {
-    sfd::TwiddleJob t{};
-    t.tw = reinterpret_cast<float2*>(ws + P->tw_off.at(L));
-    t.L = L;
-    t.count = sfd::twiddle_len(L, false);
-    t.spec = 0;
-    D->tw.push_back(t);
-  }
+  for (int L : P->lengths) add_twiddle_jobs(P, ws, L, &D->tw);
   D->tiles.clear();
   for (const TileLayout& T : P->tiles) {
     sfd::TileJob j{};
@@ -498,7 +506,9 @@ sfd_status launch_setup_for(sfd_plan_s* P, const CallDescs& D, char* ws, const s
     while (j < a0 + ns && D.axis_L[j] == D.axis_L[i]) ++j;
     const int L = D.axis_L[i];
     const int per = sfd::spectra_per_block(L);
-    if ((st = add({sfd::kRoleSpectrum, 0, (j - i + per - 1) / per, L, i, j - i, nullptr})) != SFD_OK) return st;
+    if ((st = add({sfd::kRoleSpectrum, 0, (j - i + per - 1) / per, L, i, j - i,
+                   reinterpret_cast<const float2*>(ws + P->tws_off.at(L))})) != SFD_OK)
+      return st;
     i = j;
   }
   // Pre/post chirp tables.
@@ -692,14 +702,7 @@ sfd_status run_backward(sfd_plan_s* P, void* const* grad_out, void* const* field
     D.axis.push_back(a.j);
     D.axis_L.push_back(a.L);
   }
-  for (int L : P->lengths) {
-    sfd::TwiddleJob t{};
-    t.tw = reinterpret_cast<float2*>(ws + P->tw_off.at(L));
-    t.L = L;
-    t.count = sfd::twiddle_len(L, false);
-    t.spec = 0;
-    D.tw.push_back(t);
-  }
+  for (int L : P->lengths) add_twiddle_jobs(P, ws, L, &D.tw);
 
   // Tiles: the hologram's (for the z-moment passes) and each view's gradient.
   if (want_z)
@@ -1007,6 +1010,8 @@ sfd_status sfd_plan(sfd_plan_t* plan, double wavelength, const sfd_grid* holo_gr
   for (int L : ls) {
     P->tw_off[L] = off;
     off += align_up(sizeof(float2) * std::max(1, sfd::twiddle_len(L, false)));
+    P->tws_off[L] = off;
+    off += align_up(sizeof(float2) * std::max(1, sfd::twiddle_len(L, true)));
   }
   for (int v = 0; v < n_views; ++v) {
     ViewLayout& L = P->lay[v];

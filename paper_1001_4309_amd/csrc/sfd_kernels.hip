@@ -186,7 +186,9 @@ __device__ __forceinline__ void setup_spectrum(const SetupArgs& A, const SetupRo
 #pragma unroll
   for (int i = 0; i < R; ++i) v[i] = hs[g * L + t + TPR * i];
   __syncthreads();
-  fft_row<P, false, kSplit, kTwCompute>(v, static_cast<char*>(lds) + g * row_lds_bytes<L, kSplit>(), t, nullptr);
+  // Twiddles from the spectrum-shape table (built once per workspace),
+  // fetched a stage ahead.
+  fft_row<P, false, kSplit, kTwGlobal>(v, static_cast<char*>(lds) + g * row_lds_bytes<L, kSplit>(), t, Ro.tw);
   float2* Hg = Hout[0];
 #pragma unroll
   for (int gj = 1; gj < GS; ++gj)
@@ -197,37 +199,74 @@ __device__ __forceinline__ void setup_spectrum(const SetupArgs& A, const SetupRo
   for (int i = 0; i < R; ++i) gst(Hg, (unsigned)(t + TPR * i), make_float2(v[i].x * inv, v[i].y * inv));
 }
 
+// Stores through a buffer resource of a given extent in bytes: the hardware
+// drops a store whose offset lies at or past the extent (range checking of
+// raw buffer addressing).  A store that only some lanes make is then still
+// one unconditional instruction, so the number of memory operations in
+// flight does not depend on the predicate, and a later wait for an earlier
+// load does not have to wait for the stores too.  kDrop lies past every
+// extent used here: an extent covers at most one grid of complex entries
+// with sides below 8192 + padding, far below 2^31 bytes.
+constexpr uint32_t kDrop = 0x80000000u;
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t store_rsrc(void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)bytes, 0x00020000);
+}
+// AUX: the store's cache-policy bits.  kWriteThrough (sc0 sc1: system
+// scope) sends the data on to memory as it is stored, so that it leaves no
+// dirty lines behind for the cache write-back at the end of the kernel, which
+// the next kernel waits for.
+constexpr int kWriteThrough = 1 | 16;
+template <int AUX = 0>
+__device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t off, float x) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), r, (int)off, 0, AUX);
+}
+template <int AUX = 0>
+__device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t off, float2 x) {
+  const u32x2_t w = {__builtin_bit_cast(uint32_t, x.x), __builtin_bit_cast(uint32_t, x.y)};
+  __builtin_amdgcn_raw_buffer_store_b64(w, r, (int)off, 0, AUX);
+}
+
 // Column-major copy (see TileJob) of one kTrBlock x kTrBlock block: rows of
 // the block are read with consecutive threads on consecutive columns, and
 // written back as columns with consecutive threads on consecutive rows.
 template <typename T>
 __device__ __forceinline__ void transpose_block(const TileJob& J, int r0, int c0, T* buf) {
-  constexpr int B = kTrBlock, SP = B + 1, STEP = kSetupThreads / B;
+  constexpr int B = kTrBlock, SP = B + 1, STEP = kSetupThreads / B, K = B / STEP;
   const T* in = static_cast<const T*>(J.in);
-  T* out = static_cast<T*>(J.out);
   const int lo = threadIdx.x % B, hi = threadIdx.x / B;
+  // All loads first (clamped to the grid, so they are unconditional), then
+  // the LDS writes: the loads' latencies overlap.
+  T v[K];
+  const int c = c0 + lo < J.nx ? c0 + lo : J.nx - 1;
 #pragma unroll
-  for (int k = 0; k < B / STEP; ++k) {
-    const int rr = hi + STEP * k;
-    const int n = r0 + rr, c = c0 + lo;
-    T v{};
-    if (n < J.ny && c < J.nx) {
-      v = gld(in, (unsigned)(n * J.nx + c));
-      if constexpr (sizeof(T) == 8) {
-        if (J.in2) {
-          const float a = 2.0f * gld(J.in2, (unsigned)(n * J.nx + c));
-          v = make_float2(a * v.x, a * v.y);
-        }
+  for (int k = 0; k < K; ++k) {
+    const int n = r0 + hi + STEP * k < J.ny ? r0 + hi + STEP * k : J.ny - 1;
+    v[k] = gld(in, (unsigned)(n * J.nx + c));
+  }
+  if constexpr (sizeof(T) == 8) {
+    if (J.in2) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int n = r0 + hi + STEP * k < J.ny ? r0 + hi + STEP * k : J.ny - 1;
+        const float a = 2.0f * gld(J.in2, (unsigned)(n * J.nx + c));
+        v[k] = make_float2(a * v[k].x, a * v[k].y);
       }
     }
-    buf[rr * SP + lo] = v;
   }
-  __syncthreads();
 #pragma unroll
-  for (int k = 0; k < B / STEP; ++k) {
+  for (int k = 0; k < K; ++k) buf[(hi + STEP * k) * SP + lo] = v[k];
+  __syncthreads();
+  // Column cc of the block becomes row c0 + cc of the copy; entries outside
+  // the grid fall past the store resource's extent (rows) or are sent past
+  // it (columns).
+  const auto rs = store_rsrc(J.out, (uint32_t)J.nx * (uint32_t)J.ld * (uint32_t)sizeof(T));
+  const int n = r0 + lo;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
     const int cc = hi + STEP * k;
-    const int n = r0 + lo, c = c0 + cc;
-    if (n < J.ny && c < J.nx) gst(out, (unsigned)(c * J.ld + n), buf[lo * SP + cc]);
+    const bool ok = n < J.ny && c0 + cc < J.nx;
+    bst(rs, ok ? (uint32_t)((c0 + cc) * J.ld + n) * (uint32_t)sizeof(T) : kDrop, buf[lo * SP + cc]);
   }
 }
 
@@ -346,27 +385,6 @@ __device__ __forceinline__ int find_job(const PassArgs& args, int tile) {
     else hi = mid - 1;
   }
   return lo;
-}
-
-// Stores through a buffer resource of a given extent in bytes: the hardware
-// drops a store whose offset lies at or past the extent (range checking of
-// raw buffer addressing).  A store that only some lanes make is then still
-// one unconditional instruction, so the number of memory operations in
-// flight does not depend on the predicate, and a later wait for an earlier
-// load does not have to wait for the stores too.  kDrop lies past every
-// extent used here: extents are at most L/2 rows of a grid no wider than
-// 8192 + padding complex entries, far below 2^31 bytes.
-constexpr uint32_t kDrop = 0x80000000u;
-typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t store_rsrc(void* base, uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)bytes, 0x00020000);
-}
-__device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t off, float x) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), r, (int)off, 0, 0);
-}
-__device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t off, float2 x) {
-  const u32x2_t w = {__builtin_bit_cast(uint32_t, x.x), __builtin_bit_cast(uint32_t, x.y)};
-  __builtin_amdgcn_raw_buffer_store_b64(w, r, (int)off, 0, 0);
 }
 
 // Wave-uniform value (the compiler then keeps it, and addresses built from
@@ -894,7 +912,10 @@ __global__ void __launch_bounds__((PassShape<L, GC, P>::THREADS)) __attribute__(
 #pragma unroll
         for (int k = 0; k < R / 2; ++k) {
           const int m = (tid + k * THREADS) / NS;
-          bst(rs, col_ok ? (uint32_t)(m * out_ld + gs) * 8u : kDrop, st[gs * SST + m]);
+          // Write-through in the kernels whose slots run several transforms
+          // (measured: the row pass then starts sooner); the single-transform
+          // kernels measured faster with the default policy.
+          bst<PF ? kWriteThrough : 0>(rs, col_ok ? (uint32_t)(m * out_ld + gs) * 8u : kDrop, st[gs * SST + m]);
         }
       }
     };
