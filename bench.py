@@ -386,10 +386,14 @@ def main():
     if not args.no_per_view:
         pv = sfd.Plan(w.wavelength, w.holo_grid, len(w.holograms), w.views, device=dev, per_view_launch=True)
         pouts = pv.new_outputs()
+        if not args.no_autotune:
+            # Its own best tile widths: one view per launch favours narrower tiles.
+            pv.autotune(holo, reps=10, outs=pouts)
         for _ in range(args.warmup):
             pv.reconstruct(holo, outs=pouts)
         psec = time_steps(pv, holo, pouts, args.steps)
-        per_view = {"views_per_s": nv / psec, "ms_per_step": psec * 1e3, "batched_speedup": psec / sec}
+        per_view = {"views_per_s": nv / psec, "ms_per_step": psec * 1e3, "batched_speedup": psec / sec,
+                    "schedule": {f"{k[0]}{k[1]}": g for k, g in pv.schedule().items()}}
         log(f"per-view launch: {psec * 1e6:.1f} us/step, {nv / psec:.0f} views/s")
 
     backward = None

@@ -1086,7 +1086,7 @@ sfd_status sfd_plan(sfd_plan_t* plan, double wavelength, const sfd_grid* holo_gr
   // Start from the tuning table for these shapes, if an earlier autotune filled it.
   {
     std::string sig = std::to_string(h.nx) + "x" + std::to_string(h.ny) + "/" + std::to_string(n_holo) + "/" +
-                      std::to_string(flags & ~(uint32_t)(SFD_EAGER | SFD_PER_VIEW_LAUNCH));
+                      std::to_string(flags & ~(uint32_t)SFD_EAGER);
     for (int v = 0; v < n_views; ++v)
       sig += ";" + std::to_string(views[v].out.nx) + "x" + std::to_string(views[v].out.ny) + "@" +
              std::to_string(views[v].holo);
