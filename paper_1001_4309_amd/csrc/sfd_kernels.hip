@@ -629,11 +629,15 @@ __device__ __forceinline__ void apply_half(float2 (&v)[R], const float2 (&x)[R /
 // out + r * out_ld (contiguous), both straight from registers.
 // VAR selects a specialisation, which keeps the code of the common cases
 // small: 0 = any job; 1 = every job of the launch has an input of L/2
-// samples, an output of at most L/2 and no reduction (half loads, pruned
-// transforms, no reduction epilogue); 2 = as 1, and the jobs write only
-// intensities.  P > 1: each slot runs P rows of its tile in turn; in the
-// specialisations the next row's input is fetched while the current row is
-// transformed, and the pre-chirp is read from an LDS copy.
+// samples, a complex input, an output of at most L/2 and no reduction (half
+// loads, pruned transforms, no reduction epilogue); 2 = as 1, and the jobs
+// write only intensities.  P > 1: each slot runs several rows in turn.  In
+// the specialisations a slot (one wavefront) takes the rows of its tile one
+// at a time from a counter in LDS, so that a wavefront that gets more of its
+// SIMD takes more rows and the wavefronts of the workgroup finish together;
+// the next row's input is fetched while the current row is transformed, and
+// the pre-chirp is read from an LDS copy.  The general kernel runs rows
+// row0 + p NS, p < P, of its tile.
 template <int L, int GR, int VAR, int P>
 __global__ void __launch_bounds__((PassShape<L, GR, P>::THREADS)) __attribute__((amdgpu_waves_per_eu(SFD_ROW_WPE))) row_kernel(const PassArgs args, const float2* __restrict__ tw) {
   using S = PassShape<L, GR, P>;
@@ -646,10 +650,11 @@ __global__ void __launch_bounds__((PassShape<L, GR, P>::THREADS)) __attribute__(
   constexpr bool PF = FAST && P > 1;
   using T = SharedTables<L>;
   static_assert(P == 1 || (T::on && TPR <= 64), "slots of several transforms are single wavefronts with LDS tables");
+  static_assert(!PF || TPR == 64, "a queue slot is one whole wavefront");
   constexpr int PRE_BYTES = PF ? (L / 2) * 8 : 0;
   // Shared tables, the pre-chirp copy, exchange buffers, then room for the
   // epilogue reduction (4 doubles per wavefront).
-  __shared__ __align__(16) unsigned char lds[T::bytes + PRE_BYTES + NS * RB + S::NW * 32];
+  __shared__ __align__(16) unsigned char lds[T::bytes + PRE_BYTES + NS * RB + S::NW * 32 + (PF ? 16 : 0)];
   float2* tws = reinterpret_cast<float2*>(lds);
   float2* hs = tws + T::tw_n;
   float2* ps = reinterpret_cast<float2*>(lds + T::bytes);
@@ -683,6 +688,22 @@ __global__ void __launch_bounds__((PassShape<L, GR, P>::THREADS)) __attribute__(
   float* const out2 = J.out2;
   const float sc = J.iscale;
 
+  // Row counter of the tile (PF), after the reduction scratch.  A wavefront
+  // takes one row per LDS atomic, made by its first lane; the row is valid in
+  // that lane only until passed through uniform().
+  int* const counter = reinterpret_cast<int*>(xbuf + NS * RB + S::NW * 32);
+  const int tile_row0 = (tile - args.tile_prefix[jid]) * GR;
+  const int tile_rows = n_rows - tile_row0 < GR ? n_rows - tile_row0 : GR;
+  if constexpr (PF) {
+    if (threadIdx.x == 0) *counter = 0;
+    __syncthreads();
+  }
+  const bool lane0 = (threadIdx.x & 63) == 0;
+  auto grab = [&]() -> int {
+    int r = 0;
+    if (lane0) r = atomicAdd(counter, 1);
+    return r;
+  };
   float2 v[R];
   float2 x[PF ? R / 2 : 1];
   auto load = [&](int row, int t) {
@@ -696,7 +717,15 @@ __global__ void __launch_bounds__((PassShape<L, GR, P>::THREADS)) __attribute__(
       else load_row<TPR, R, false>(v, static_cast<const float2*>(in) + off, pre, n_in, t);
     }
   };
-  load(row0, t);
+  // PF: rows of the tile by their index in it (valid below tile_rows).
+  int r_cur = row0, r_next = 0;
+  if constexpr (PF) {
+    r_cur = uniform(grab());
+    if (r_cur < tile_rows) load(tile_row0 + r_cur, t);
+    r_next = r_cur < tile_rows ? uniform(grab()) : tile_rows;
+  } else {
+    load(row0, t);
+  }
 
   if constexpr (T::on) {
     stage_tables<L, S::THREADS, PF>(tws, hs, ps, tw, H, pre);
@@ -714,8 +743,10 @@ __global__ void __launch_bounds__((PassShape<L, GR, P>::THREADS)) __attribute__(
     // HALF with a row per wavefront: a row's outputs (field of, intensity
     // oi) leave through one store resource per row, of n_out entries (none
     // for a row past the job's end).  With several rows per slot, a row's
-    // outputs are stored only once the next row's input has arrived: the
-    // wait for that input then finds no store of this row in flight.
+    // outputs are stored only once the next row's input has arrived (the
+    // wait for that input then finds no store of this row in flight), and
+    // written through (measured: the next kernel starts sooner, as with the
+    // column kernel's intermediate).
     constexpr bool BUF = HALF && TPR >= 64;
     float2 of[BUF && !INT_ONLY ? RL : 1];
     float oi[BUF ? RL : 1];
@@ -725,27 +756,31 @@ __global__ void __launch_bounds__((PassShape<L, GR, P>::THREADS)) __attribute__(
         if (!INT_ONLY && (mode & kOutField)) {
           const auto rs = store_rsrc(static_cast<float2*>(out1) + (int64_t)r * out_ld, lim * 8u);
 #pragma unroll
-          for (int i = 0; i < RL; ++i) bst(rs, (uint32_t)(lane + TPR * i) * 8u, of[i]);
+          for (int i = 0; i < RL; ++i) bst<PF ? kWriteThrough : 0>(rs, (uint32_t)(lane + TPR * i) * 8u, of[i]);
         }
         if (mode & kOutIntensity) {
           float* o = ((!INT_ONLY && (mode & kOutField)) ? out2 : static_cast<float*>(out1)) + (int64_t)r * out_ld;
           const auto rs = store_rsrc(o, lim * 4u);
 #pragma unroll
-          for (int i = 0; i < RL; ++i) bst(rs, (uint32_t)(lane + TPR * i) * 4u, oi[i]);
+          for (int i = 0; i < RL; ++i) bst<PF ? kWriteThrough : 0>(rs, (uint32_t)(lane + TPR * i) * 4u, oi[i]);
         }
       }
     };
+    int prev = -1;  // PF: the row whose outputs wait in of / oi
+    int pend = 0;   // PF: the row after next (index in the tile), in the first lane
 #pragma unroll 1
-    for (int p = 0; p < P; ++p) {
+    for (int p = 0; PF ? r_cur < tile_rows : p < P; ++p) {
       const int tl = P > 1 ? opaque(t) : t;
-      const int row = row0 + p * NS;
+      const int row = PF ? tile_row0 + r_cur : row0 + p * NS;
       const bool valid = row < n_rows;
       if constexpr (PF) {
         apply_half<TPR, R, false>(v, x, pre ? ps : nullptr, tl);
         sched_fence();
-        if (p > 0) flush(row - NS, tl);
+        if (prev >= 0) flush(prev, tl);
         sched_fence();
-        if (p + 1 < P) load(row + NS, tl);
+        if (r_next < tile_rows) load(tile_row0 + r_next, tl);
+        // The row after next: taken now, read after this row's transforms.
+        pend = r_next < tile_rows ? grab() : tile_rows;
       } else if (p > 0) {
         load(row, tl);
       }
@@ -793,8 +828,15 @@ __global__ void __launch_bounds__((PassShape<L, GR, P>::THREADS)) __attribute__(
       if constexpr (!HALF) {
         if (mode & kReduce) row_accumulate<TPR, R>(J, v, row, valid, tl, acc);
       }
+      if constexpr (PF) {
+        prev = row;
+        r_cur = r_next;
+        r_next = uniform(pend);
+      }
     }
-    if constexpr (PF) flush(row0 + (P - 1) * NS, t);
+    if constexpr (PF) {
+      if (prev >= 0) flush(prev, t);
+    }
     if constexpr (!HALF) {
       if (mode & kReduce)
         reduce_tile<S::NW>(J, acc, tile - args.tile_prefix[jid], reinterpret_cast<double*>(xbuf + NS * RB));
@@ -1002,11 +1044,11 @@ bool supported_length(int L) { return twiddle_len(L, false) >= 0; }
 #define SFD_ROW_SHAPES(X) \
   X(64, 32, 1) X(64, 16, 1) X(64, 64, 1) X(128, 16, 1) X(128, 8, 1) X(128, 32, 1) X(256, 8, 1) X(256, 4, 1) \
   X(256, 16, 1) X(512, 4, 1) X(512, 2, 1) X(512, 8, 1) X(1024, 2, 1) X(1024, 1, 1) X(1024, 4, 1) X(1024, 8, 2) \
-  X(1024, 16, 4) X(2048, 2, 1) X(2048, 1, 1) X(2048, 4, 1) X(2048, 8, 2) X(2048, 16, 4) X(4096, 1, 1) X(8192, 1, 1)
+  X(1024, 16, 2) X(2048, 2, 1) X(2048, 1, 1) X(2048, 4, 1) X(2048, 8, 2) X(2048, 16, 2) X(4096, 1, 1) X(8192, 1, 1)
 #define SFD_COL_SHAPES(X) \
   X(64, 32, 1) X(64, 16, 1) X(128, 16, 1) X(128, 8, 1) X(256, 8, 1) X(256, 4, 1) X(512, 8, 1) X(512, 4, 1) \
   X(1024, 8, 1) X(1024, 4, 1) X(1024, 16, 1) X(1024, 32, 2) X(2048, 8, 1) X(2048, 4, 1) X(2048, 2, 1) \
-  X(2048, 16, 2) X(2048, 32, 4) X(4096, 2, 1) X(4096, 4, 1) X(8192, 1, 1) X(8192, 2, 1)
+  X(2048, 16, 2) X(4096, 2, 1) X(4096, 4, 1) X(8192, 1, 1) X(8192, 2, 1)
 
 int pass_tile_widths(int L, bool col, int* widths, int cap, int* per_slot) {
   int n = 0;

@@ -204,7 +204,7 @@ def test_schedule_queries_and_manual_setting(lib):
     assert lib.sfd_schedule(h, 1024, 1, ctypes.byref(g)) == lib_mod.SFD_ERR_INVALID_ARG
     n0 = ctypes.c_size_t()
     assert lib.sfd_workspace_size(h, ctypes.byref(n0)) == 0
-    for col, width in ((1, 4), (1, 2), (1, 16), (1, 32), (0, 1), (0, 4), (0, 8), (0, 16)):
+    for col, width in ((1, 4), (1, 2), (1, 16), (0, 1), (0, 4), (0, 8), (0, 16)):
         assert lib.sfd_set_schedule(h, 2048, col, width) == 0
         assert lib.sfd_schedule(h, 2048, col, ctypes.byref(g)) == 0 and g.value == width
         n = ctypes.c_size_t()
