@@ -266,6 +266,62 @@ def time_steps(plan, holo, outs, steps: int) -> float:
     return (time.perf_counter() - t0) / steps
 
 
+def bench_streaming(w, plan, steps: int, warmup: int):
+    """The real-time loop on the same workload: frames arrive in pinned host
+    memory, each is copied to the device on the plan's copy stream while the
+    previous one is reconstructed, and the tables and spectra are computed for
+    the first frame only (a plan made with reuse_tables, on the batched
+    plan's tile widths).  Reports frames/s of the overlapped loop, and beside
+    it the host-to-device copy alone and the reconstruction alone."""
+    import numpy as np
+    import torch
+
+    import paper_1001_4309_amd as sfd
+
+    dev = torch.device("cuda:0")
+    sp = sfd.Plan(w.wavelength, w.holo_grid, len(w.holograms), w.views, device=dev, reuse_tables=True)
+    for (kind, L), g in plan.schedule().items():
+        sp.set_schedule(L, kind == "col", g)
+    r = np.random.default_rng(5)
+    base = np.ascontiguousarray(w.holograms).astype(np.float32)
+    frames = [torch.from_numpy((base * r.uniform(0.9, 1.1, base.shape)).astype(np.float32)).pin_memory()
+              for _ in range(8)]
+    fs = sfd.FrameStream(sp)
+    for k in range(warmup):
+        fs.push(frames[k % len(frames)])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        fs.push(frames[k % len(frames)])
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    # The copy alone, on a side stream, and the reconstruction alone (tables kept).
+    side = torch.cuda.Stream()
+    dst = fs.dev[0]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(side):
+        for k in range(steps):
+            dst.copy_(frames[k % len(frames)], non_blocking=True)
+    torch.cuda.synchronize()
+    copy_sec = (time.perf_counter() - t0) / steps
+    outs = sp.new_outputs()
+    sp.reconstruct(dst, outs=outs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sp.reconstruct(dst, outs=outs)
+    torch.cuda.synchronize()
+    comp_sec = (time.perf_counter() - t0) / steps
+    nbytes = frames[0].numel() * 4
+    nv = len(w.views)
+    return {"frames_per_s": 1.0 / sec, "views_per_s": nv / sec, "ms_per_frame": sec * 1e3,
+            "h2d_ms_per_frame": copy_sec * 1e3, "h2d_GBps": nbytes / copy_sec / 1e9,
+            "reconstruct_ms_per_frame": comp_sec * 1e3,
+            "what": f"{len(frames)} pinned host frames cycled; copy of frame k+1 overlapped with the "
+                    f"reconstruction of frame k; tables and spectra from the first frame"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -277,6 +333,7 @@ def main():
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tile widths")
     ap.add_argument("--no-backward", action="store_true", help="skip the forward + backward measurement")
+    ap.add_argument("--no-streaming", action="store_true", help="skip the real-time loop measurement")
     ap.add_argument("--schedule", default="",
                     help="tile widths to use instead of autotuning, e.g. col2048=4,row2048=4")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -396,6 +453,13 @@ def main():
                     "schedule": {f"{k[0]}{k[1]}": g for k, g in pv.schedule().items()}}
         log(f"per-view launch: {psec * 1e6:.1f} us/step, {nv / psec:.0f} views/s")
 
+    streaming = None
+    if not args.no_streaming:
+        streaming = bench_streaming(w, plan, args.steps, args.warmup)
+        log(f"streaming: {streaming['ms_per_frame'] * 1e3:.1f} us/frame, {streaming['frames_per_s']:.0f} frames/s "
+            f"(copy alone {streaming['h2d_ms_per_frame'] * 1e3:.1f} us at {streaming['h2d_GBps']:.1f} GB/s, "
+            f"reconstruction alone {streaming['reconstruct_ms_per_frame'] * 1e3:.1f} us)")
+
     backward = None
     if not args.no_backward:
         backward = bench_backward(dev, max(1, min(args.steps, 50)), max(1, min(args.warmup, 5)))
@@ -430,6 +494,7 @@ def main():
         "hbm": hbm,
         "per_view_launch": per_view,
         "backward": backward,
+        "streaming": streaming,
         "kernels": kern,
         "cpu_baseline": cpu,
     }

@@ -83,8 +83,12 @@ enum {
   SFD_OUT_FIELD = 1u << 3,     /* outputs are the complex64 field u1 (Eq. 1 with C1) */
   SFD_PHASE_FP32 = 1u << 4,    /* evaluate chirp phases in FP32 instead of FP64 (comparison only) */
   SFD_PER_VIEW_LAUNCH = 1u << 5, /* launch the kernels one view at a time (baseline for batching) */
-  SFD_EAGER = 1u << 6            /* batched calls launch their kernels directly instead of replaying
+  SFD_EAGER = 1u << 6,           /* batched calls launch their kernels directly instead of replaying
                                     the plan's HIP graph */
+  SFD_REUSE_TABLES = 1u << 7     /* streaming (the repeated steps 1-11 of Section 2.2): the chirp
+                                    tables and kernel spectra of a call are kept for the next call on
+                                    the same workspace when its distances are the same, so that call
+                                    runs only the hologram copy and the two passes */
 };
 
 /*
@@ -138,6 +142,9 @@ sfd_status sfd_view_lengths(sfd_plan_t plan, int32_t v, int32_t* lx, int32_t* ly
  * ``stream``, only when they changed), so one graph serves every call.  When
  * ``stream`` is being captured by the caller, or kernel timing is on, the
  * kernels are launched directly instead.
+ * With SFD_REUSE_TABLES, a call whose distances equal those of the previous
+ * call on the same workspace reuses that call's tables and spectra (the
+ * workspace keeps them); sfd_backward on the workspace invalidates them.
  */
 sfd_status sfd_reconstruct(sfd_plan_t plan, const void* holo, const double* z_or_null,
                            void* const* out, void* workspace, size_t ws_bytes,
@@ -189,6 +196,29 @@ sfd_status sfd_schedule(sfd_plan_t plan, int32_t L, int32_t col, int32_t* tile_w
  * tile width at L.  Results do not depend on the tile width: every transform
  * is computed the same way whatever workgroup holds it. */
 sfd_status sfd_set_schedule(sfd_plan_t plan, int32_t L, int32_t col, int32_t tile_width);
+
+/*
+ * One frame of the real-time loop (Section 2.2: steps 1-11 repeated for every
+ * captured hologram).  Copies the frame from host memory into the next of
+ * two device buffers on the plan's own copy stream, then enqueues
+ * sfd_reconstruct of that buffer (with the plan's distances) on ``stream``,
+ * after the copy.  The call returns at once: the copy of frame k + 1 runs
+ * while frame k is reconstructed.  A frame's copy waits for the
+ * reconstruction that last read its buffer (frame k - 2).
+ *   host_frame  host, n_holo x [ny][nx] float32 or complex64 per the plan
+ *               flags; pinned (hipHostMalloc) for the copy to overlap, and
+ *               left unchanged until the copy is done
+ *   dev_holo    host array of two distinct device buffers of that size,
+ *               16-byte aligned, the same two on every call of the plan
+ *   out, workspace, ws_bytes, stream: as in sfd_reconstruct.  The outputs of
+ *               frame k may be overwritten by a later frame given the same
+ *               pointers: read them (in stream order) before that.
+ * With SFD_REUSE_TABLES the tables and spectra are computed for the first
+ * frame only.  Errors: SFD_ERR_INVALID_ARG for NULL or equal buffers or a
+ * per-view plan; the sfd_reconstruct errors.
+ */
+sfd_status sfd_stream_frame(sfd_plan_t plan, const void* host_frame, void* const* dev_holo, void* const* out,
+                            void* workspace, size_t ws_bytes, hipStream_t stream);
 
 /* Tile widths (transforms per workgroup) the column (col != 0) or row
  * (col == 0) pass has kernels for at transform length L, the default first

@@ -22,11 +22,12 @@ import torch
 
 from . import _lib
 from ._lib import (SFD_EAGER, SFD_IN_C64, SFD_IN_REAL_F32, SFD_OUT_FIELD, SFD_OUT_INTENSITY,  # noqa: F401
-                   SFD_PER_VIEW_LAUNCH, SFD_PHASE_FP32, SfdError, SfdGrid, SfdView)
+                   SFD_PER_VIEW_LAUNCH, SFD_PHASE_FP32, SFD_REUSE_TABLES, SfdError, SfdGrid, SfdView)
 
 __all__ = ["Plan", "SFDFunction", "sfd_plan", "sfd_workspace_size", "sfd_view_lengths", "sfd_reconstruct",
            "sfd_backward", "sfd_autotune", "sfd_schedule", "sfd_set_schedule", "sfd_tile_widths",
-           "sfd_profile_enable", "sfd_profile_report", "sfd_destroy", "SfdError"]
+           "sfd_stream_frame", "sfd_profile_enable", "sfd_profile_report", "sfd_destroy", "SfdError",
+           "FrameStream"]
 
 
 def _grid(g) -> SfdGrid:
@@ -94,6 +95,14 @@ def sfd_reconstruct(plan, holo: torch.Tensor, z, outs: Sequence[torch.Tensor], w
                                            _stream_handle(holo.device)))
 
 
+def sfd_stream_frame(plan, host_frame: torch.Tensor, dev_holo: Sequence[torch.Tensor], outs: Sequence[torch.Tensor],
+                     workspace: torch.Tensor) -> None:
+    arr = (ctypes.c_void_p * 2)(_ptr(dev_holo[0]), _ptr(dev_holo[1]))
+    _lib.check(_lib.load().sfd_stream_frame(plan, ctypes.c_void_p(host_frame.data_ptr()), arr, _ptr_array(outs),
+                                            _ptr(workspace), workspace.numel() * workspace.element_size(),
+                                            _stream_handle(dev_holo[0].device)))
+
+
 def sfd_backward(plan, grad_out: Sequence[torch.Tensor], field_out: Optional[Sequence[torch.Tensor]],
                  holo: torch.Tensor, z, grad_in: torch.Tensor, grad_z: Optional[torch.Tensor],
                  workspace: torch.Tensor) -> None:
@@ -155,7 +164,7 @@ class Plan:
 
     def __init__(self, wavelength: float, holo_grid, n_holo: int, views: Sequence, *,
                  outputs: str = "intensity", complex_input: bool = False, phase_fp32: bool = False,
-                 per_view_launch: bool = False, eager: bool = False, device=None):
+                 per_view_launch: bool = False, eager: bool = False, reuse_tables: bool = False, device=None):
         if outputs not in ("intensity", "field", "both"):
             raise ValueError("outputs must be 'intensity', 'field' or 'both'")
         self.device = torch.device(device if device is not None else "cuda")
@@ -174,6 +183,8 @@ class Plan:
             flags |= SFD_PER_VIEW_LAUNCH
         if eager:
             flags |= SFD_EAGER
+        if reuse_tables:
+            flags |= SFD_REUSE_TABLES
         self.flags = flags
         self.handle = None
         self.handle = sfd_plan(wavelength, holo_grid, n_holo, self.views, flags)
@@ -236,6 +247,23 @@ class Plan:
         sfd_reconstruct(self.handle, holo, z, outs, self.workspace)
         return outs
 
+    def stream_frame(self, host_frame: torch.Tensor, dev_holo: Sequence[torch.Tensor], outs) -> None:
+        """One frame of the real-time loop (``sfd_stream_frame``): copy
+        ``host_frame`` (pinned CPU) into the next of ``dev_holo`` (two device
+        buffers shaped like the holograms) and reconstruct it on the current
+        stream into ``outs``; returns before either is done."""
+        g = self.holo_grid
+        want = torch.complex64 if self.complex_input else torch.float32
+        shape = (self.n_holo, g.ny, g.nx)
+        if host_frame.dtype != want or host_frame.device.type != "cpu" or not host_frame.is_contiguous() \
+                or host_frame.numel() != self.n_holo * g.ny * g.nx:
+            raise ValueError(f"host_frame must be a contiguous CPU {want} tensor of shape {shape}")
+        for d in dev_holo:
+            self._check_holo(d)
+            if not d.is_contiguous():
+                raise ValueError("dev_holo buffers must be contiguous")
+        sfd_stream_frame(self.handle, host_frame, dev_holo, outs, self.workspace)
+
     def backward(self, grad_out, holo, z=None, field_out=None, grad_z: bool = True):
         holo = self._check_holo(holo)
         self._check_z(z)
@@ -293,3 +321,29 @@ class SFDFunction(torch.autograd.Function):
         grad_in, gz = plan.backward([g.to(torch.float32) for g in gi], fields, ctx.zl, field_out=ctx.u1)
         zdev, zdtype = ctx.z_meta
         return grad_in.view_as(fields), gz.to(zdev, zdtype), None
+
+
+class FrameStream:
+    """The real-time loop (Section 2.2, steps 1-11 for every captured frame):
+    a plan made with ``reuse_tables=True`` (tables and spectra computed for
+    the first frame only), two device hologram buffers and two sets of output
+    buffers.  ``push(host_frame)`` enqueues one frame (its copy overlaps the
+    previous frame's reconstruction) and returns the outputs it will write,
+    valid once the current stream reaches them and until the frame after next
+    is pushed."""
+
+    def __init__(self, plan: "Plan"):
+        if not plan.flags & SFD_REUSE_TABLES:
+            raise ValueError("FrameStream needs a plan made with reuse_tables=True")
+        self.plan = plan
+        g = plan.holo_grid
+        dt = torch.complex64 if plan.complex_input else torch.float32
+        self.dev = [torch.empty((plan.n_holo, g.ny, g.nx), dtype=dt, device=plan.device) for _ in range(2)]
+        self.outs = [plan.new_outputs() for _ in range(2)]
+        self.count = 0
+
+    def push(self, host_frame: torch.Tensor):
+        outs = self.outs[self.count & 1]
+        self.plan.stream_frame(host_frame, self.dev, outs)
+        self.count += 1
+        return outs

@@ -24,10 +24,11 @@ SFD_OUT_FIELD = 1 << 3
 SFD_PHASE_FP32 = 1 << 4
 SFD_PER_VIEW_LAUNCH = 1 << 5
 SFD_EAGER = 1 << 6
+SFD_REUSE_TABLES = 1 << 7
 
 EXPORTED = ["sfd_plan", "sfd_workspace_size", "sfd_view_lengths", "sfd_reconstruct",
             "sfd_backward", "sfd_autotune", "sfd_schedule", "sfd_set_schedule", "sfd_tile_widths",
-            "sfd_profile_enable", "sfd_profile_report", "sfd_destroy", "sfd_last_error"]
+            "sfd_stream_frame", "sfd_profile_enable", "sfd_profile_report", "sfd_destroy", "sfd_last_error"]
 
 SFD_KERNEL_TABLES = 0
 SFD_KERNEL_SPECTRA = 1
@@ -84,6 +85,7 @@ def load() -> ctypes.CDLL:
     lib.sfd_tile_widths.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                     ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
     lib.sfd_tile_widths.restype = ctypes.c_int32
+    lib.sfd_stream_frame.argtypes = [vp, vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp, ctypes.c_size_t, vp]
     lib.sfd_profile_enable.argtypes = [vp, ctypes.c_int32]
     lib.sfd_profile_report.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
                                        ctypes.POINTER(ctypes.c_double)]
@@ -91,8 +93,8 @@ def load() -> ctypes.CDLL:
     lib.sfd_last_error.argtypes = []
     lib.sfd_last_error.restype = ctypes.c_char_p
     for name in ("sfd_plan", "sfd_workspace_size", "sfd_view_lengths", "sfd_reconstruct", "sfd_backward",
-                 "sfd_autotune", "sfd_schedule", "sfd_set_schedule", "sfd_profile_enable", "sfd_profile_report",
-                 "sfd_destroy"):
+                 "sfd_autotune", "sfd_schedule", "sfd_set_schedule", "sfd_stream_frame", "sfd_profile_enable",
+                 "sfd_profile_report", "sfd_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib

@@ -191,17 +191,43 @@ struct sfd_plan_s {
   hipGraphExec_t gexec = nullptr;
   void* graph_ws = nullptr;
 
+  // The same sequence without the tables and spectra (SFD_REUSE_TABLES).
+  hipGraph_t graph_r = nullptr;
+  hipGraphExec_t gexec_r = nullptr;
+  // SFD_REUSE_TABLES: the workspace whose tables and spectra hold the
+  // distances tables_z.
+  void* tables_ws = nullptr;
+  std::vector<double> tables_z;
+
   void drop_graph() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
+    if (gexec_r) (void)hipGraphExecDestroy(gexec_r);
+    if (graph_r) (void)hipGraphDestroy(graph_r);
     gexec = nullptr;
     graph = nullptr;
+    gexec_r = nullptr;
+    graph_r = nullptr;
     graph_ws = nullptr;
   }
+
+  // sfd_stream_frame: the copy stream and, per device buffer, the events
+  // that order a frame's copy after the reconstruction that last read the
+  // buffer, and that reconstruction after the copy.
+  hipStream_t copy_stream = nullptr;
+  hipEvent_t copied[2] = {nullptr, nullptr};
+  hipEvent_t consumed[2] = {nullptr, nullptr};
+  bool consumed_set[2] = {false, false};
+  int64_t frames = 0;
 
   ~sfd_plan_s() {
     drop_graph();
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (copy_stream) (void)hipStreamDestroy(copy_stream);
+    for (int b = 0; b < 2; ++b) {
+      if (copied[b]) (void)hipEventDestroy(copied[b]);
+      if (consumed[b]) (void)hipEventDestroy(consumed[b]);
+    }
     for (auto& r : recs) {
       (void)hipEventDestroy(r.a);
       (void)hipEventDestroy(r.b);
@@ -584,13 +610,14 @@ void apply_schedule(sfd_plan_s* P) {
 }
 
 // The batched forward sequence: every view's tables, spectra and hologram
-// tiles, then all column passes, then all row passes.
+// tiles (tables = false: the tiles only), then all column passes, then all
+// row passes.
 sfd_status launch_forward(sfd_plan_s* P, const CallDescs& D, char* ws, const sfd::AxisJob* d_axis,
                           const sfd::TwiddleJob* d_tw, const sfd::TileJob* d_tiles, const sfd::RowJob* d_rows,
-                          hipStream_t stream) {
+                          hipStream_t stream, bool tables = true) {
   sfd_status st;
-  if ((st = launch_setup_for(P, D, ws, d_axis, d_tw, d_tiles, 0, (int)D.axis.size(), false, 0, (int)D.tiles.size(),
-                             stream)) != SFD_OK)
+  if ((st = launch_setup_for(P, D, ws, d_axis, d_tw, d_tiles, 0, tables ? (int)D.axis.size() : 0, false, 0,
+                             (int)D.tiles.size(), stream)) != SFD_OK)
     return st;
   if ((st = launch_rows(D, d_rows, 0, D.n_pass_x, P, ws, stream, SFD_KERNEL_PASS_Y)) != SFD_OK) return st;
   return launch_rows(D, d_rows, D.n_pass_x, (int)D.rows.size() - D.n_pass_x, P, ws, stream, SFD_KERNEL_PASS_X);
@@ -950,7 +977,7 @@ sfd_status sfd_plan(sfd_plan_t* plan, double wavelength, const sfd_grid* holo_gr
   if (n_views < 1) return fail(SFD_ERR_INVALID_ARG, "n_views must be >= 1");
   if (n_views > 65536) return fail(SFD_ERR_UNSUPPORTED, "at most 65536 views per plan");
   const uint32_t known = SFD_IN_REAL_F32 | SFD_IN_C64 | SFD_OUT_INTENSITY | SFD_OUT_FIELD | SFD_PHASE_FP32 |
-                         SFD_PER_VIEW_LAUNCH | SFD_EAGER;
+                         SFD_PER_VIEW_LAUNCH | SFD_EAGER | SFD_REUSE_TABLES;
   if (flags & ~known) return fail(SFD_ERR_INVALID_ARG, "unknown flag bits");
   if (((flags & SFD_IN_REAL_F32) != 0) == ((flags & SFD_IN_C64) != 0))
     return fail(SFD_ERR_INVALID_ARG, "exactly one of SFD_IN_REAL_F32 and SFD_IN_C64 must be set");
@@ -1169,33 +1196,48 @@ sfd_status sfd_reconstruct(sfd_plan_t plan, const void* holo, const double* z_or
     }
     return SFD_OK;
   }
+  // SFD_REUSE_TABLES: this call needs no tables or spectra when the
+  // workspace holds those of the same distances.
+  bool tables = true;
+  if (plan->flags & SFD_REUSE_TABLES) {
+    std::vector<double> zz(V);
+    for (int v = 0; v < V; ++v) zz[v] = z_or_null ? z_or_null[v] : plan->views[v].z;
+    tables = !(plan->tables_ws == ws && plan->tables_z == zz);
+    plan->tables_ws = nullptr;  // set again once this call's launches are enqueued
+    plan->tables_z = std::move(zz);
+  }
   const bool use_graph = !(plan->flags & SFD_EAGER) && !plan->profiling;
   if (use_graph) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     SFD_HIP_TRY(hipStreamIsCapturing(stream, &cs));
     if (cs == hipStreamCaptureStatusNone) {
-      if (plan->graph_ws != ws) {
+      if (plan->graph_ws != ws) plan->drop_graph();
+      hipGraph_t& graph = tables ? plan->graph : plan->graph_r;
+      hipGraphExec_t& gexec = tables ? plan->gexec : plan->gexec_r;
+      if (!gexec) {
         // Record on a private stream: the caller's stream is never put in
         // capture mode.
-        plan->drop_graph();
         if (!plan->cap_stream) SFD_HIP_TRY(hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking));
         SFD_HIP_TRY(hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal));
-        st = launch_forward(plan, D, ws, d_axis, d_tw, d_tiles, d_rows, plan->cap_stream);
+        st = launch_forward(plan, D, ws, d_axis, d_tw, d_tiles, d_rows, plan->cap_stream, tables);
         hipGraph_t g = nullptr;
         const hipError_t e = hipStreamEndCapture(plan->cap_stream, &g);
         if (st != SFD_OK || e != hipSuccess) {
           if (g) (void)hipGraphDestroy(g);
           return st != SFD_OK ? st : fail(SFD_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
         }
-        plan->graph = g;
-        SFD_HIP_TRY(hipGraphInstantiate(&plan->gexec, g, nullptr, nullptr, 0));
+        graph = g;
+        SFD_HIP_TRY(hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0));
         plan->graph_ws = ws;
       }
-      SFD_HIP_TRY(hipGraphLaunch(plan->gexec, stream));
+      SFD_HIP_TRY(hipGraphLaunch(gexec, stream));
+      if (plan->flags & SFD_REUSE_TABLES) plan->tables_ws = ws;
       return SFD_OK;
     }
   }
-  return launch_forward(plan, D, ws, d_axis, d_tw, d_tiles, d_rows, stream);
+  st = launch_forward(plan, D, ws, d_axis, d_tw, d_tiles, d_rows, stream, tables);
+  if (st == SFD_OK && (plan->flags & SFD_REUSE_TABLES)) plan->tables_ws = ws;
+  return st;
 }
 
 sfd_status sfd_backward(sfd_plan_t plan, void* const* grad_out, void* const* field_out, const void* holo,
@@ -1220,6 +1262,7 @@ sfd_status sfd_backward(sfd_plan_t plan, void* const* grad_out, void* const* fie
       return fail(SFD_ERR_INVALID_ARG, "field_out[" + std::to_string(v) + "] must be non-NULL and 16-byte aligned");
   }
   if ((st = check_z(plan, z_or_null)) != SFD_OK) return st;
+  plan->tables_ws = nullptr;  // the backward rewrites the workspace's tables
   return run_backward(plan, grad_out, field_out, holo, z_or_null, grad_in, grad_z, static_cast<char*>(workspace),
                       stream);
 }
@@ -1365,6 +1408,38 @@ sfd_status sfd_profile_report(sfd_plan_t plan, int32_t kind, int64_t* launches, 
   }
   *launches = n;
   *total_ms = ms;
+  return SFD_OK;
+}
+
+sfd_status sfd_stream_frame(sfd_plan_t plan, const void* host_frame, void* const* dev_holo, void* const* out,
+                            void* workspace, size_t ws_bytes, hipStream_t stream) {
+  g_err.clear();
+  sfd_status st = check_common(plan, workspace, ws_bytes);
+  if (st != SFD_OK) return st;
+  if (!host_frame) return fail(SFD_ERR_INVALID_ARG, "host_frame is NULL");
+  if (!dev_holo || !dev_holo[0] || !dev_holo[1] || dev_holo[0] == dev_holo[1])
+    return fail(SFD_ERR_INVALID_ARG, "dev_holo must hold two distinct device buffers");
+  if (plan->flags & SFD_PER_VIEW_LAUNCH)
+    return fail(SFD_ERR_INVALID_ARG, "sfd_stream_frame needs a batched plan (no SFD_PER_VIEW_LAUNCH)");
+  const sfd_grid& h = plan->holo;
+  const size_t bytes = (size_t)plan->n_holo * h.nx * h.ny * ((plan->flags & SFD_IN_REAL_F32) ? 4 : 8);
+  if (!plan->copy_stream) {
+    SFD_HIP_TRY(hipStreamCreateWithFlags(&plan->copy_stream, hipStreamNonBlocking));
+    for (int b = 0; b < 2; ++b) {
+      SFD_HIP_TRY(hipEventCreateWithFlags(&plan->copied[b], hipEventDisableTiming));
+      SFD_HIP_TRY(hipEventCreateWithFlags(&plan->consumed[b], hipEventDisableTiming));
+    }
+  }
+  const int b = (int)(plan->frames & 1);
+  // The copy waits for the reconstruction that last read this buffer.
+  if (plan->consumed_set[b]) SFD_HIP_TRY(hipStreamWaitEvent(plan->copy_stream, plan->consumed[b], 0));
+  SFD_HIP_TRY(hipMemcpyAsync(dev_holo[b], host_frame, bytes, hipMemcpyHostToDevice, plan->copy_stream));
+  SFD_HIP_TRY(hipEventRecord(plan->copied[b], plan->copy_stream));
+  SFD_HIP_TRY(hipStreamWaitEvent(stream, plan->copied[b], 0));
+  if ((st = sfd_reconstruct(plan, dev_holo[b], nullptr, out, workspace, ws_bytes, stream)) != SFD_OK) return st;
+  SFD_HIP_TRY(hipEventRecord(plan->consumed[b], stream));
+  plan->consumed_set[b] = true;
+  ++plan->frames;
   return SFD_OK;
 }
 

@@ -229,3 +229,30 @@ def test_autotune_validates_before_any_hip_call(lib):
     assert lib.sfd_autotune(h, ctypes.c_void_p(4096), out, ctypes.c_void_p(256), 0, 3, None) == \
         lib_mod.SFD_ERR_WORKSPACE
     assert lib.sfd_destroy(h) == 0
+
+
+def test_stream_frame_validates_before_any_hip_call(lib):
+    flags = lib_mod.SFD_IN_REAL_F32 | lib_mod.SFD_OUT_INTENSITY | lib_mod.SFD_REUSE_TABLES
+    st, h = _plan(lib, flags=flags)
+    assert st == 0
+    n = ctypes.c_size_t()
+    lib.sfd_workspace_size(h, ctypes.byref(n))
+    out = (ctypes.c_void_p * 1)(4096)
+    ws = ctypes.c_void_p(256)
+    two = (ctypes.c_void_p * 2)(4096, 8192)
+    same = (ctypes.c_void_p * 2)(4096, 4096)
+    host = ctypes.c_void_p(4096)
+    assert lib.sfd_stream_frame(h, None, two, out, ws, n.value, None) == lib_mod.SFD_ERR_INVALID_ARG
+    assert lib.sfd_stream_frame(h, host, None, out, ws, n.value, None) == lib_mod.SFD_ERR_INVALID_ARG
+    assert lib.sfd_stream_frame(h, host, same, out, ws, n.value, None) == lib_mod.SFD_ERR_INVALID_ARG
+    assert b"two distinct" in lib.sfd_last_error()
+    assert lib.sfd_stream_frame(h, host, two, out, ws, 0, None) == lib_mod.SFD_ERR_WORKSPACE
+    assert lib.sfd_destroy(h) == 0
+    st, h = _plan(lib, flags=flags | lib_mod.SFD_PER_VIEW_LAUNCH)
+    assert st == 0
+    lib.sfd_workspace_size(h, ctypes.byref(n))
+    assert lib.sfd_stream_frame(h, host, two, out, ws, n.value, None) == lib_mod.SFD_ERR_INVALID_ARG
+    assert lib.sfd_destroy(h) == 0
+    # Unknown flag bits are still refused.
+    st, _ = _plan(lib, flags=lib_mod.SFD_IN_REAL_F32 | lib_mod.SFD_OUT_INTENSITY | (1 << 8))
+    assert st == lib_mod.SFD_ERR_INVALID_ARG
