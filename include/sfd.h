@@ -175,9 +175,10 @@ sfd_status sfd_backward(sfd_plan_t plan, void* const* grad_out, void* const* fie
 /*
  * Schedule autotuner.  Times every tile width (transforms per workgroup) the
  * column (y) and row (x) passes support at each of the plan's transform
- * lengths, one pass and length at a time with the others fixed, by running
- * the plan's whole batched forward ``reps`` times per candidate on the
- * caller's data; keeps the fastest in the plan and in a process-wide table
+ * lengths, one pass and length at a time with the others fixed (two sweeps),
+ * by running the plan's whole forward ``reps`` times per candidate on the
+ * caller's data, launched as the plan's calls are (graph replays for batched
+ * plans); keeps the fastest in the plan and in a process-wide table
  * that later plans with the same hologram grid, view sizes and flags start
  * from.  Arguments as in sfd_reconstruct; outputs are overwritten.
  * Synchronises ``stream``.  The workspace layout does not change, so the same

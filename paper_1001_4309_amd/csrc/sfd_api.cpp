@@ -1274,14 +1274,9 @@ sfd_status sfd_autotune(sfd_plan_t plan, const void* holo, void* const* out, voi
   if (st != SFD_OK) return st;
   if (reps < 1 || reps > 1000) return fail(SFD_ERR_INVALID_ARG, "reps must be in [1, 1000]");
   if (plan->profiling) return fail(SFD_ERR_INVALID_ARG, "turn kernel timing off before autotuning");
-  // Time direct launches (a graph replay runs the same kernels); restore the
-  // flags on every exit.
-  struct FlagGuard {
-    sfd_plan_s* p;
-    uint32_t f;
-    ~FlagGuard() { p->flags = f; }
-  } guard{plan, plan->flags};
-  plan->flags |= SFD_EAGER;
+  // Candidates run the way the plan runs its calls (graph replays unless
+  // the plan is eager or launches per view): the launch gaps between the
+  // kernels are part of what a tile width changes.
   hipEvent_t e0 = nullptr, e1 = nullptr;
   struct EventGuard {
     hipEvent_t* a;
@@ -1311,6 +1306,10 @@ sfd_status sfd_autotune(sfd_plan_t plan, const void* holo, void* const* out, voi
   }
   std::sort(passes.begin(), passes.end());
   passes.erase(std::unique(passes.begin(), passes.end()), passes.end());
+  // Two sweeps over the passes: a pass's best width can depend on the
+  // others'.
+  const size_t n_passes = passes.size();
+  for (size_t k = 0; k < n_passes; ++k) passes.push_back(passes[k]);
   for (const auto& pl : passes) {
     const int col = pl.first, L = pl.second;
     int widths[16];
