@@ -221,6 +221,21 @@ sfd_status sfd_set_schedule(sfd_plan_t plan, int32_t L, int32_t col, int32_t til
 sfd_status sfd_stream_frame(sfd_plan_t plan, const void* host_frame, void* const* dev_holo, void* const* out,
                             void* workspace, size_t ws_bytes, hipStream_t stream);
 
+/*
+ * Raw camera frames (the paper resizes its 1360 x 1024 CCD frames to the
+ * hologram grid before reconstructing, Section 3).  After this call the
+ * plan's holograms arrive as n_holo x [ny][nx_raw] float32 samples and are
+ * resized along x to the plan's hologram grid (nx samples of pitch px) as
+ * they are copied for the column pass: bilinear interpolation with
+ * half-pixel centres, sample c read at s = (c + 1/2) nx_raw / nx - 1/2,
+ * clamped to [0, nx_raw - 1].  nx_raw = 0 (or nx) turns it off.  The pitch
+ * of the plan's grid stays the caller's (nx_raw / nx times the camera's).
+ * Real-input plans only; affects sfd_reconstruct, sfd_autotune and
+ * sfd_stream_frame.  Errors: SFD_ERR_INVALID_ARG (complex plan, nx_raw out
+ * of [0, 65536]), SFD_ERR_UNSUPPORTED (frame above 2^28 samples).
+ */
+sfd_status sfd_set_raw_input(sfd_plan_t plan, int32_t nx_raw);
+
 /* Tile widths (transforms per workgroup) the column (col != 0) or row
  * (col == 0) pass has kernels for at transform length L, the default first
  * (host query, no plan needed).  Writes up to cap widths to ``widths`` and,

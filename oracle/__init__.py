@@ -32,4 +32,5 @@ from .sfd_oracle import (  # noqa: F401
     adjoint,
     dfield_dz,
     grads,
+    resize_x,
 )

@@ -33,6 +33,12 @@ R6 (FFT convention).  Forward FFT with exp(-2 pi i jk/L), inverse scaled by
    1/L per axis (numpy's convention).  The result does not depend on it.
 R7 (sign of z).  z is the signed distance from plane 0 to plane 1; z < 0 is
    allowed and means back-propagation.  For a real hologram I(z) = I(-z).
+R8 (the CCD resize, Section 3).  The 1360 x 1024 camera frame is resized to
+   1024 x 1024 before reconstruction; the method is not named.  We take
+   bilinear interpolation along x only (rows unchanged) with half-pixel
+   centres: output sample c reads the frame at s = (c + 1/2) n_in / n_out - 1/2,
+   clamped to [0, n_in - 1], so the output pitch is n_in / n_out times the
+   camera's.
 """
 
 from __future__ import annotations
@@ -254,3 +260,20 @@ def grads(u0: np.ndarray, src: Grid, dst: Grid, wavelength: float, z: float,
         gu = gu.real
     gz = float(np.real(np.sum(np.conj(g) * dfield_dz(u0, src, dst, wavelength, z))))
     return gu, gz
+
+
+def resize_x(frame: np.ndarray, n_out: int) -> np.ndarray:
+    """The camera frame resized along x to n_out samples per row (Section 3's
+    1360 -> 1024 resize; reading R8), in FP64: each output sample is the
+    linear blend of the two input samples around its source position."""
+    f = np.asarray(frame, dtype=np.float64)
+    n_in = f.shape[-1]
+    out = np.empty(f.shape[:-1] + (n_out,), dtype=np.float64)
+    for c in range(n_out):
+        s = (c + 0.5) * n_in / n_out - 0.5
+        s = min(max(s, 0.0), n_in - 1.0)
+        i0 = int(np.floor(s))
+        i1 = min(i0 + 1, n_in - 1)
+        t = s - i0
+        out[..., c] = (1.0 - t) * f[..., i0] + t * f[..., i1]
+    return out

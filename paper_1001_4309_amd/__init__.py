@@ -26,8 +26,8 @@ from ._lib import (SFD_EAGER, SFD_IN_C64, SFD_IN_REAL_F32, SFD_OUT_FIELD, SFD_OU
 
 __all__ = ["Plan", "SFDFunction", "sfd_plan", "sfd_workspace_size", "sfd_view_lengths", "sfd_reconstruct",
            "sfd_backward", "sfd_autotune", "sfd_schedule", "sfd_set_schedule", "sfd_tile_widths",
-           "sfd_stream_frame", "sfd_profile_enable", "sfd_profile_report", "sfd_destroy", "SfdError",
-           "FrameStream"]
+           "sfd_stream_frame", "sfd_set_raw_input", "sfd_profile_enable", "sfd_profile_report", "sfd_destroy",
+           "SfdError", "FrameStream"]
 
 
 def _grid(g) -> SfdGrid:
@@ -103,6 +103,10 @@ def sfd_stream_frame(plan, host_frame: torch.Tensor, dev_holo: Sequence[torch.Te
                                             _stream_handle(dev_holo[0].device)))
 
 
+def sfd_set_raw_input(plan, nx_raw: int) -> None:
+    _lib.check(_lib.load().sfd_set_raw_input(plan, int(nx_raw)))
+
+
 def sfd_backward(plan, grad_out: Sequence[torch.Tensor], field_out: Optional[Sequence[torch.Tensor]],
                  holo: torch.Tensor, z, grad_in: torch.Tensor, grad_z: Optional[torch.Tensor],
                  workspace: torch.Tensor) -> None:
@@ -164,7 +168,8 @@ class Plan:
 
     def __init__(self, wavelength: float, holo_grid, n_holo: int, views: Sequence, *,
                  outputs: str = "intensity", complex_input: bool = False, phase_fp32: bool = False,
-                 per_view_launch: bool = False, eager: bool = False, reuse_tables: bool = False, device=None):
+                 per_view_launch: bool = False, eager: bool = False, reuse_tables: bool = False,
+                 raw_width: Optional[int] = None, device=None):
         if outputs not in ("intensity", "field", "both"):
             raise ValueError("outputs must be 'intensity', 'field' or 'both'")
         self.device = torch.device(device if device is not None else "cuda")
@@ -188,6 +193,10 @@ class Plan:
         self.flags = flags
         self.handle = None
         self.handle = sfd_plan(wavelength, holo_grid, n_holo, self.views, flags)
+        # Raw camera frames: rows of raw_width samples, resized along x on the GPU.
+        self.raw_width = int(raw_width) if raw_width else holo_grid.nx
+        if raw_width:
+            sfd_set_raw_input(self.handle, self.raw_width)
         self.ws_bytes = sfd_workspace_size(self.handle)
         self.workspace = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=self.device)
 
@@ -231,8 +240,9 @@ class Plan:
             raise TypeError(f"holograms must be {want}, got {holo.dtype}")
         if holo.device != self.device and not (holo.is_cuda and self.device.index is None):
             raise ValueError("holograms must be on the plan's device")
-        if tuple(holo.shape[-2:]) != (g.ny, g.nx) or holo.numel() != self.n_holo * g.ny * g.nx:
-            raise ValueError(f"holograms must be [{self.n_holo}, {g.ny}, {g.nx}], got {tuple(holo.shape)}")
+        nx = self.raw_width
+        if tuple(holo.shape[-2:]) != (g.ny, nx) or holo.numel() != self.n_holo * g.ny * nx:
+            raise ValueError(f"holograms must be [{self.n_holo}, {g.ny}, {nx}], got {tuple(holo.shape)}")
         return holo.contiguous()
 
     def _check_z(self, z):
@@ -254,9 +264,9 @@ class Plan:
         stream into ``outs``; returns before either is done."""
         g = self.holo_grid
         want = torch.complex64 if self.complex_input else torch.float32
-        shape = (self.n_holo, g.ny, g.nx)
+        shape = (self.n_holo, g.ny, self.raw_width)
         if host_frame.dtype != want or host_frame.device.type != "cpu" or not host_frame.is_contiguous() \
-                or host_frame.numel() != self.n_holo * g.ny * g.nx:
+                or host_frame.numel() != self.n_holo * g.ny * self.raw_width:
             raise ValueError(f"host_frame must be a contiguous CPU {want} tensor of shape {shape}")
         for d in dev_holo:
             self._check_holo(d)
@@ -338,7 +348,7 @@ class FrameStream:
         self.plan = plan
         g = plan.holo_grid
         dt = torch.complex64 if plan.complex_input else torch.float32
-        self.dev = [torch.empty((plan.n_holo, g.ny, g.nx), dtype=dt, device=plan.device) for _ in range(2)]
+        self.dev = [torch.empty((plan.n_holo, g.ny, plan.raw_width), dtype=dt, device=plan.device) for _ in range(2)]
         self.outs = [plan.new_outputs() for _ in range(2)]
         self.count = 0
 

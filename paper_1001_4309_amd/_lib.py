@@ -28,7 +28,8 @@ SFD_REUSE_TABLES = 1 << 7
 
 EXPORTED = ["sfd_plan", "sfd_workspace_size", "sfd_view_lengths", "sfd_reconstruct",
             "sfd_backward", "sfd_autotune", "sfd_schedule", "sfd_set_schedule", "sfd_tile_widths",
-            "sfd_stream_frame", "sfd_profile_enable", "sfd_profile_report", "sfd_destroy", "sfd_last_error"]
+            "sfd_stream_frame", "sfd_set_raw_input", "sfd_profile_enable", "sfd_profile_report", "sfd_destroy",
+            "sfd_last_error"]
 
 SFD_KERNEL_TABLES = 0
 SFD_KERNEL_SPECTRA = 1
@@ -86,6 +87,7 @@ def load() -> ctypes.CDLL:
                                     ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
     lib.sfd_tile_widths.restype = ctypes.c_int32
     lib.sfd_stream_frame.argtypes = [vp, vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp, ctypes.c_size_t, vp]
+    lib.sfd_set_raw_input.argtypes = [vp, ctypes.c_int32]
     lib.sfd_profile_enable.argtypes = [vp, ctypes.c_int32]
     lib.sfd_profile_report.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
                                        ctypes.POINTER(ctypes.c_double)]
@@ -93,8 +95,8 @@ def load() -> ctypes.CDLL:
     lib.sfd_last_error.argtypes = []
     lib.sfd_last_error.restype = ctypes.c_char_p
     for name in ("sfd_plan", "sfd_workspace_size", "sfd_view_lengths", "sfd_reconstruct", "sfd_backward",
-                 "sfd_autotune", "sfd_schedule", "sfd_set_schedule", "sfd_stream_frame", "sfd_profile_enable",
-                 "sfd_profile_report", "sfd_destroy"):
+                 "sfd_autotune", "sfd_schedule", "sfd_set_schedule", "sfd_stream_frame", "sfd_set_raw_input",
+                 "sfd_profile_enable", "sfd_profile_report", "sfd_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib

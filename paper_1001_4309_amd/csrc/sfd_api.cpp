@@ -142,6 +142,7 @@ struct sfd_plan_s {
   std::vector<int> lengths;           // distinct L values used
   std::map<int, size_t> tw_off;       // twiddle table of the passes' shape per L
   std::map<int, size_t> tws_off;      // twiddle table of the kernel-spectrum shape per L
+  int raw_nx = 0;                     // sfd_set_raw_input: camera samples per hologram row (0: none)
   void* tw_ready_ws = nullptr;        // workspace whose twiddle tables are current
   size_t desc_off = 0, desc_bytes = 0;
   size_t ws_bytes = 0;
@@ -324,7 +325,7 @@ sfd_status build_descs(sfd_plan_s* P, const void* holo, const double* z, void* c
   const int32_t pflags = (P->flags & SFD_PHASE_FP32) ? sfd::kPhaseFp32 : 0;
   const sfd_grid& h = P->holo;
   const size_t in_elem = in_real ? sizeof(float) : sizeof(float2);
-  const size_t holo_stride = (size_t)h.nx * h.ny * in_elem;
+  const size_t holo_stride = (size_t)(P->raw_nx > 0 ? P->raw_nx : h.nx) * h.ny * in_elem;
 
   struct AxisTmp {
     sfd::AxisJob j;
@@ -382,6 +383,7 @@ sfd_status build_descs(sfd_plan_s* P, const void* holo, const double* z, void* c
     j.ny = h.ny;
     j.ld = col_ld(h.ny);
     j.complex_in = in_real ? 0 : 1;
+    j.nx_src = P->raw_nx;
     D->tiles.push_back(j);
   }
 
@@ -1421,7 +1423,8 @@ sfd_status sfd_stream_frame(sfd_plan_t plan, const void* host_frame, void* const
   if (plan->flags & SFD_PER_VIEW_LAUNCH)
     return fail(SFD_ERR_INVALID_ARG, "sfd_stream_frame needs a batched plan (no SFD_PER_VIEW_LAUNCH)");
   const sfd_grid& h = plan->holo;
-  const size_t bytes = (size_t)plan->n_holo * h.nx * h.ny * ((plan->flags & SFD_IN_REAL_F32) ? 4 : 8);
+  const size_t bytes = (size_t)plan->n_holo * (plan->raw_nx > 0 ? plan->raw_nx : h.nx) * h.ny *
+                       ((plan->flags & SFD_IN_REAL_F32) ? 4 : 8);
   if (!plan->copy_stream) {
     SFD_HIP_TRY(hipStreamCreateWithFlags(&plan->copy_stream, hipStreamNonBlocking));
     for (int b = 0; b < 2; ++b) {
@@ -1439,6 +1442,17 @@ sfd_status sfd_stream_frame(sfd_plan_t plan, const void* host_frame, void* const
   SFD_HIP_TRY(hipEventRecord(plan->consumed[b], stream));
   plan->consumed_set[b] = true;
   ++plan->frames;
+  return SFD_OK;
+}
+
+sfd_status sfd_set_raw_input(sfd_plan_t plan, int32_t nx_raw) {
+  g_err.clear();
+  if (!plan) return fail(SFD_ERR_INVALID_ARG, "plan is NULL");
+  if (!(plan->flags & SFD_IN_REAL_F32)) return fail(SFD_ERR_INVALID_ARG, "raw camera input needs a real-input plan");
+  if (nx_raw < 0 || nx_raw > 65536) return fail(SFD_ERR_INVALID_ARG, "nx_raw must be in [0, 65536]");
+  if ((long)nx_raw * plan->holo.ny > (1L << 28)) return fail(SFD_ERR_UNSUPPORTED, "raw frame larger than 2^28 samples");
+  plan->raw_nx = nx_raw == plan->holo.nx ? 0 : nx_raw;
+  plan->drop_graph();
   return SFD_OK;
 }
 

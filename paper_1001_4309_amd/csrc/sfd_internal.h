@@ -108,13 +108,18 @@ struct TwiddleJob {
 // in[n * nx + c] (n < ny, c < nx), so that each column is contiguous and the
 // column pass loads it like a row.
 struct TileJob {
-  const void* in;   // [ny][nx] float32 or complex64
+  const void* in;   // [ny][nx] float32 or complex64 ([ny][nx_src] float32 when nx_src > 0)
   const float* in2; // complex input only: if set, the copy holds 2 in2 * in (a gradient
                     // with respect to the field formed from dL/dI and the field)
   void* out;
   int32_t nx, ny;
   int32_t ld;       // elements between consecutive columns of the copy (>= ny)
   int32_t complex_in;
+  // Real input only: > 0 when the input rows hold nx_src camera samples,
+  // resized to nx along x as they are copied (bilinear, half-pixel centres:
+  // sample c is read at s = (c + 1/2) nx_src / nx - 1/2, clamped to the row).
+  int32_t nx_src;
+  int32_t pad_;
 };
 constexpr int kTrBlock = 32;  // square block one setup workgroup transposes
 

@@ -239,10 +239,35 @@ __device__ __forceinline__ void transpose_block(const TileJob& J, int r0, int c0
   // the LDS writes: the loads' latencies overlap.
   T v[K];
   const int c = c0 + lo < J.nx ? c0 + lo : J.nx - 1;
+  if constexpr (sizeof(T) == 4) {
+    if (J.nx_src > 0) {
+      // Resized from rows of nx_src samples: the two neighbours of the
+      // sample's source position, blended.
+      const int ns = J.nx_src;
+      double sx = ((double)c + 0.5) * (double)ns / (double)J.nx - 0.5;
+      sx = fmin(fmax(sx, 0.0), (double)(ns - 1));
+      const int i0 = (int)sx;
+      const int i1 = i0 + 1 < ns ? i0 + 1 : ns - 1;
+      const float wt = (float)(sx - (double)i0);
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int n = r0 + hi + STEP * k < J.ny ? r0 + hi + STEP * k : J.ny - 1;
-    v[k] = gld(in, (unsigned)(n * J.nx + c));
+      for (int k = 0; k < K; ++k) {
+        const int n = r0 + hi + STEP * k < J.ny ? r0 + hi + STEP * k : J.ny - 1;
+        const float a = gld(in, (unsigned)(n * ns + i0)), b = gld(in, (unsigned)(n * ns + i1));
+        v[k] = fmaf(wt, b - a, a);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int n = r0 + hi + STEP * k < J.ny ? r0 + hi + STEP * k : J.ny - 1;
+        v[k] = gld(in, (unsigned)(n * J.nx + c));
+      }
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int n = r0 + hi + STEP * k < J.ny ? r0 + hi + STEP * k : J.ny - 1;
+      v[k] = gld(in, (unsigned)(n * J.nx + c));
+    }
   }
   if constexpr (sizeof(T) == 8) {
     if (J.in2) {

@@ -268,3 +268,30 @@ def test_prefactor_and_intensity_definitions():
         assert abs(abs(c) - 3e-6 * 7e-6 / (LAM * abs(z))) < 1e-18
     u = np.array([[3 + 4j]])
     assert oracle.intensity(u)[0, 0] == 25.0
+
+
+# P10: the camera-frame resize (Section 3, reading R8) against a library
+# routine with the same definition (bilinear, half-pixel centres), and its
+# invariants: constants stay constant, a ramp stays a ramp away from the
+# clamped ends, equal sizes are the identity.
+@pytest.mark.parametrize("n_in,n_out", [(1360, 1024), (17, 40), (40, 17), (8, 8)])
+def test_p10_resize_matches_library_bilinear(n_in, n_out):
+    import torch
+    r = np.random.default_rng(n_in + n_out)
+    f = r.normal(size=(5, n_in))
+    got = oracle.resize_x(f, n_out)
+    ref = torch.nn.functional.interpolate(torch.from_numpy(f)[None, None], size=(5, n_out), mode="bilinear",
+                                          align_corners=False)[0, 0].numpy()
+    assert np.max(np.abs(got - ref)) < 1e-12
+    assert np.allclose(oracle.resize_x(np.full((3, n_in), 2.5), n_out), 2.5, rtol=0, atol=1e-14)
+    if n_in == n_out:
+        assert np.array_equal(oracle.resize_x(f, n_out), f)
+
+
+def test_p10_resize_keeps_ramps_inside():
+    n_in, n_out = 1360, 1024
+    ramp = 3.0 + 0.25 * np.arange(n_in)[None, :]
+    got = oracle.resize_x(ramp, n_out)[0]
+    s = (np.arange(n_out) + 0.5) * n_in / n_out - 0.5
+    inside = (s >= 0) & (s <= n_in - 1)
+    assert np.max(np.abs(got[inside] - (3.0 + 0.25 * s[inside]))) < 1e-10

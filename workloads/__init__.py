@@ -112,7 +112,8 @@ def config1() -> Workload:
 
 def config2() -> Workload:
     """Paper-shaped: a 1360 x 1024 CCD field of 64 scatterers (z_j drawn from
-    {3, 6, 10} cm), bilinearly resized along x to 1024^2, and four 1024^2 views."""
+    {3, 6, 10} cm), bilinearly resized along x to 1024^2, and four 1024^2 views.
+    ``extra["ccd"]`` keeps the unresized frame (1 x 1024 x 1360)."""
     rng = _spawn(2, 1)[0]
     ccd = gabor_hologram(rng, 1360, 1024, CCD_PITCH, 64,
                          lambda r, k: r.choice([0.03, 0.06, 0.10], k))
@@ -126,7 +127,8 @@ def config2() -> Workload:
         ViewSpec(GridSpec(n, n, 4.65e-6, 4.65e-6), 0.06, 0),
         ViewSpec(GridSpec(n, n, 2e-6, 2e-6, 200e-6, 200e-6), 0.10, 0),
     ]
-    return Workload("config2-paper-4view-1024", WAVELENGTH, hg, holo[None], views)
+    return Workload("config2-paper-4view-1024", WAVELENGTH, hg, holo[None], views,
+                    extra={"ccd": ccd[None].astype(np.float32)})
 
 
 def config3(n_holo: int = 8, views_per_holo: int = 8, n: int = 1024) -> Workload:
