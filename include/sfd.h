@@ -205,7 +205,8 @@ sfd_status sfd_set_schedule(sfd_plan_t plan, int32_t L, int32_t col, int32_t til
  * sfd_reconstruct of that buffer (with the plan's distances) on ``stream``,
  * after the copy.  The call returns at once: the copy of frame k + 1 runs
  * while frame k is reconstructed.  A frame's copy waits for the
- * reconstruction that last read its buffer (frame k - 2).
+ * reconstruction that last read its buffer (frame k - 2), and so does the
+ * call itself (on the host): at most two frames are in flight.
  *   host_frame  host, n_holo x [ny][nx] float32 or complex64 per the plan
  *               flags; pinned (hipHostMalloc) for the copy to overlap, and
  *               left unchanged until the copy is done
@@ -224,17 +225,20 @@ sfd_status sfd_stream_frame(sfd_plan_t plan, const void* host_frame, void* const
 /*
  * Raw camera frames (the paper resizes its 1360 x 1024 CCD frames to the
  * hologram grid before reconstructing, Section 3).  After this call the
- * plan's holograms arrive as n_holo x [ny][nx_raw] float32 samples and are
- * resized along x to the plan's hologram grid (nx samples of pitch px) as
- * they are copied for the column pass: bilinear interpolation with
- * half-pixel centres, sample c read at s = (c + 1/2) nx_raw / nx - 1/2,
- * clamped to [0, nx_raw - 1].  nx_raw = 0 (or nx) turns it off.  The pitch
- * of the plan's grid stays the caller's (nx_raw / nx times the camera's).
- * Real-input plans only; affects sfd_reconstruct, sfd_autotune and
- * sfd_stream_frame.  Errors: SFD_ERR_INVALID_ARG (complex plan, nx_raw out
- * of [0, 65536]), SFD_ERR_UNSUPPORTED (frame above 2^28 samples).
+ * plan's holograms arrive as n_holo x [ny][nx_raw] camera samples of
+ * sample_bits bits: 32 for float32, 8 or 16 for unsigned integers (taken at
+ * their value).  They are converted and resized along x to the plan's
+ * hologram grid (nx samples of pitch px) as they are copied for the column
+ * pass: bilinear interpolation with half-pixel centres, sample c read at
+ * s = (c + 1/2) nx_raw / nx - 1/2, clamped to [0, nx_raw - 1] (the identity
+ * when nx_raw == nx).  nx_raw = 0 turns it off.  The pitch of the plan's
+ * grid stays the caller's (nx_raw / nx times the camera's).  Real-input plans
+ * only; affects sfd_reconstruct, sfd_autotune and sfd_stream_frame (whose
+ * copies then move the camera samples).  Errors: SFD_ERR_INVALID_ARG
+ * (complex plan, nx_raw outside [0, 65536], sample_bits not 8, 16 or 32),
+ * SFD_ERR_UNSUPPORTED (frame above 2^28 samples).
  */
-sfd_status sfd_set_raw_input(sfd_plan_t plan, int32_t nx_raw);
+sfd_status sfd_set_raw_input(sfd_plan_t plan, int32_t nx_raw, int32_t sample_bits);
 
 /* Tile widths (transforms per workgroup) the column (col != 0) or row
  * (col == 0) pass has kernels for at transform length L, the default first

@@ -103,8 +103,11 @@ def sfd_stream_frame(plan, host_frame: torch.Tensor, dev_holo: Sequence[torch.Te
                                             _stream_handle(dev_holo[0].device)))
 
 
-def sfd_set_raw_input(plan, nx_raw: int) -> None:
-    _lib.check(_lib.load().sfd_set_raw_input(plan, int(nx_raw)))
+def sfd_set_raw_input(plan, nx_raw: int, sample_bits: int = 32) -> None:
+    _lib.check(_lib.load().sfd_set_raw_input(plan, int(nx_raw), int(sample_bits)))
+
+
+_RAW_DTYPES = {32: torch.float32, 16: torch.uint16, 8: torch.uint8}
 
 
 def sfd_backward(plan, grad_out: Sequence[torch.Tensor], field_out: Optional[Sequence[torch.Tensor]],
@@ -169,7 +172,7 @@ class Plan:
     def __init__(self, wavelength: float, holo_grid, n_holo: int, views: Sequence, *,
                  outputs: str = "intensity", complex_input: bool = False, phase_fp32: bool = False,
                  per_view_launch: bool = False, eager: bool = False, reuse_tables: bool = False,
-                 raw_width: Optional[int] = None, device=None):
+                 raw_width: Optional[int] = None, raw_bits: int = 32, device=None):
         if outputs not in ("intensity", "field", "both"):
             raise ValueError("outputs must be 'intensity', 'field' or 'both'")
         self.device = torch.device(device if device is not None else "cuda")
@@ -193,10 +196,15 @@ class Plan:
         self.flags = flags
         self.handle = None
         self.handle = sfd_plan(wavelength, holo_grid, n_holo, self.views, flags)
-        # Raw camera frames: rows of raw_width samples, resized along x on the GPU.
+        # Raw camera frames: rows of raw_width samples of raw_bits bits (float32,
+        # or uint16 / uint8), converted and resized along x on the GPU.
+        if raw_bits not in _RAW_DTYPES:
+            raise ValueError("raw_bits must be 8, 16 or 32")
         self.raw_width = int(raw_width) if raw_width else holo_grid.nx
-        if raw_width:
-            sfd_set_raw_input(self.handle, self.raw_width)
+        self.input_dtype = torch.complex64 if complex_input else torch.float32
+        if raw_width or raw_bits != 32:
+            sfd_set_raw_input(self.handle, self.raw_width, raw_bits)
+            self.input_dtype = _RAW_DTYPES[raw_bits]
         self.ws_bytes = sfd_workspace_size(self.handle)
         self.workspace = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=self.device)
 
@@ -235,7 +243,7 @@ class Plan:
 
     def _check_holo(self, holo: torch.Tensor) -> torch.Tensor:
         g = self.holo_grid
-        want = torch.complex64 if self.complex_input else torch.float32
+        want = self.input_dtype
         if holo.dtype != want:
             raise TypeError(f"holograms must be {want}, got {holo.dtype}")
         if holo.device != self.device and not (holo.is_cuda and self.device.index is None):
@@ -263,7 +271,7 @@ class Plan:
         buffers shaped like the holograms) and reconstruct it on the current
         stream into ``outs``; returns before either is done."""
         g = self.holo_grid
-        want = torch.complex64 if self.complex_input else torch.float32
+        want = self.input_dtype
         shape = (self.n_holo, g.ny, self.raw_width)
         if host_frame.dtype != want or host_frame.device.type != "cpu" or not host_frame.is_contiguous() \
                 or host_frame.numel() != self.n_holo * g.ny * self.raw_width:
@@ -347,8 +355,8 @@ class FrameStream:
             raise ValueError("FrameStream needs a plan made with reuse_tables=True")
         self.plan = plan
         g = plan.holo_grid
-        dt = torch.complex64 if plan.complex_input else torch.float32
-        self.dev = [torch.empty((plan.n_holo, g.ny, plan.raw_width), dtype=dt, device=plan.device) for _ in range(2)]
+        self.dev = [torch.empty((plan.n_holo, g.ny, plan.raw_width), dtype=plan.input_dtype, device=plan.device)
+                    for _ in range(2)]
         self.outs = [plan.new_outputs() for _ in range(2)]
         self.count = 0
 

@@ -87,7 +87,7 @@ def load() -> ctypes.CDLL:
                                     ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
     lib.sfd_tile_widths.restype = ctypes.c_int32
     lib.sfd_stream_frame.argtypes = [vp, vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp, ctypes.c_size_t, vp]
-    lib.sfd_set_raw_input.argtypes = [vp, ctypes.c_int32]
+    lib.sfd_set_raw_input.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
     lib.sfd_profile_enable.argtypes = [vp, ctypes.c_int32]
     lib.sfd_profile_report.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
                                        ctypes.POINTER(ctypes.c_double)]

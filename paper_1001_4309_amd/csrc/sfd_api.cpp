@@ -143,6 +143,7 @@ struct sfd_plan_s {
   std::map<int, size_t> tw_off;       // twiddle table of the passes' shape per L
   std::map<int, size_t> tws_off;      // twiddle table of the kernel-spectrum shape per L
   int raw_nx = 0;                     // sfd_set_raw_input: camera samples per hologram row (0: none)
+  int raw_bits = 32;                  // and their size
   void* tw_ready_ws = nullptr;        // workspace whose twiddle tables are current
   size_t desc_off = 0, desc_bytes = 0;
   size_t ws_bytes = 0;
@@ -325,7 +326,8 @@ sfd_status build_descs(sfd_plan_s* P, const void* holo, const double* z, void* c
   const int32_t pflags = (P->flags & SFD_PHASE_FP32) ? sfd::kPhaseFp32 : 0;
   const sfd_grid& h = P->holo;
   const size_t in_elem = in_real ? sizeof(float) : sizeof(float2);
-  const size_t holo_stride = (size_t)(P->raw_nx > 0 ? P->raw_nx : h.nx) * h.ny * in_elem;
+  const size_t holo_stride =
+      P->raw_nx > 0 ? (size_t)P->raw_nx * h.ny * (P->raw_bits / 8) : (size_t)h.nx * h.ny * in_elem;
 
   struct AxisTmp {
     sfd::AxisJob j;
@@ -384,6 +386,7 @@ sfd_status build_descs(sfd_plan_s* P, const void* holo, const double* z, void* c
     j.ld = col_ld(h.ny);
     j.complex_in = in_real ? 0 : 1;
     j.nx_src = P->raw_nx;
+    j.src_bits = P->raw_bits;
     D->tiles.push_back(j);
   }
 
@@ -1423,8 +1426,8 @@ sfd_status sfd_stream_frame(sfd_plan_t plan, const void* host_frame, void* const
   if (plan->flags & SFD_PER_VIEW_LAUNCH)
     return fail(SFD_ERR_INVALID_ARG, "sfd_stream_frame needs a batched plan (no SFD_PER_VIEW_LAUNCH)");
   const sfd_grid& h = plan->holo;
-  const size_t bytes = (size_t)plan->n_holo * (plan->raw_nx > 0 ? plan->raw_nx : h.nx) * h.ny *
-                       ((plan->flags & SFD_IN_REAL_F32) ? 4 : 8);
+  const size_t bytes = plan->raw_nx > 0 ? (size_t)plan->n_holo * plan->raw_nx * h.ny * (plan->raw_bits / 8)
+                                        : (size_t)plan->n_holo * h.nx * h.ny * ((plan->flags & SFD_IN_REAL_F32) ? 4 : 8);
   if (!plan->copy_stream) {
     SFD_HIP_TRY(hipStreamCreateWithFlags(&plan->copy_stream, hipStreamNonBlocking));
     for (int b = 0; b < 2; ++b) {
@@ -1433,8 +1436,14 @@ sfd_status sfd_stream_frame(sfd_plan_t plan, const void* host_frame, void* const
     }
   }
   const int b = (int)(plan->frames & 1);
-  // The copy waits for the reconstruction that last read this buffer.
-  if (plan->consumed_set[b]) SFD_HIP_TRY(hipStreamWaitEvent(plan->copy_stream, plan->consumed[b], 0));
+  // The copy waits for the reconstruction that last read this buffer (frame
+  // k - 2).  The host waits for it too: at most two frames are in flight.
+  // Measured: letting the host run further ahead (queues of many frames with
+  // their cross-stream waits) made the loop several times slower.
+  if (plan->consumed_set[b]) {
+    SFD_HIP_TRY(hipEventSynchronize(plan->consumed[b]));
+    SFD_HIP_TRY(hipStreamWaitEvent(plan->copy_stream, plan->consumed[b], 0));
+  }
   SFD_HIP_TRY(hipMemcpyAsync(dev_holo[b], host_frame, bytes, hipMemcpyHostToDevice, plan->copy_stream));
   SFD_HIP_TRY(hipEventRecord(plan->copied[b], plan->copy_stream));
   SFD_HIP_TRY(hipStreamWaitEvent(stream, plan->copied[b], 0));
@@ -1445,13 +1454,16 @@ sfd_status sfd_stream_frame(sfd_plan_t plan, const void* host_frame, void* const
   return SFD_OK;
 }
 
-sfd_status sfd_set_raw_input(sfd_plan_t plan, int32_t nx_raw) {
+sfd_status sfd_set_raw_input(sfd_plan_t plan, int32_t nx_raw, int32_t sample_bits) {
   g_err.clear();
   if (!plan) return fail(SFD_ERR_INVALID_ARG, "plan is NULL");
   if (!(plan->flags & SFD_IN_REAL_F32)) return fail(SFD_ERR_INVALID_ARG, "raw camera input needs a real-input plan");
   if (nx_raw < 0 || nx_raw > 65536) return fail(SFD_ERR_INVALID_ARG, "nx_raw must be in [0, 65536]");
+  if (sample_bits != 8 && sample_bits != 16 && sample_bits != 32)
+    return fail(SFD_ERR_INVALID_ARG, "sample_bits must be 8, 16 or 32");
   if ((long)nx_raw * plan->holo.ny > (1L << 28)) return fail(SFD_ERR_UNSUPPORTED, "raw frame larger than 2^28 samples");
-  plan->raw_nx = nx_raw == plan->holo.nx ? 0 : nx_raw;
+  plan->raw_nx = nx_raw;
+  plan->raw_bits = nx_raw > 0 ? sample_bits : 32;
   plan->drop_graph();
   return SFD_OK;
 }

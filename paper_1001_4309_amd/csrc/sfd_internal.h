@@ -108,18 +108,20 @@ struct TwiddleJob {
 // in[n * nx + c] (n < ny, c < nx), so that each column is contiguous and the
 // column pass loads it like a row.
 struct TileJob {
-  const void* in;   // [ny][nx] float32 or complex64 ([ny][nx_src] float32 when nx_src > 0)
+  const void* in;   // [ny][nx] float32 or complex64 ([ny][nx_src] camera samples when nx_src > 0)
   const float* in2; // complex input only: if set, the copy holds 2 in2 * in (a gradient
                     // with respect to the field formed from dL/dI and the field)
   void* out;
   int32_t nx, ny;
   int32_t ld;       // elements between consecutive columns of the copy (>= ny)
   int32_t complex_in;
-  // Real input only: > 0 when the input rows hold nx_src camera samples,
-  // resized to nx along x as they are copied (bilinear, half-pixel centres:
-  // sample c is read at s = (c + 1/2) nx_src / nx - 1/2, clamped to the row).
+  // Real input only: > 0 when the input rows hold nx_src camera samples of
+  // src_bits bits each (32: float32; 8, 16: unsigned integers, taken at their
+  // value), resized to nx along x as they are copied (bilinear, half-pixel
+  // centres: sample c is read at s = (c + 1/2) nx_src / nx - 1/2, clamped to
+  // the row; the identity when nx_src == nx).
   int32_t nx_src;
-  int32_t pad_;
+  int32_t src_bits;
 };
 constexpr int kTrBlock = 32;  // square block one setup workgroup transposes
 

@@ -230,6 +230,26 @@ __device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t off, floa
 // Column-major copy (see TileJob) of one kTrBlock x kTrBlock block: rows of
 // the block are read with consecutive threads on consecutive columns, and
 // written back as columns with consecutive threads on consecutive rows.
+// Camera samples of type S resized along x (see TileJob): for column c of
+// the grid, the two neighbours of its source position in rows r0 + hi + STEP k,
+// blended.
+template <typename S, int K, int STEP>
+__device__ __forceinline__ void resample_loads(const TileJob& J, int r0, int hi, int c, float (&v)[K]) {
+  const S* in = static_cast<const S*>(J.in);
+  const int ns = J.nx_src;
+  double sx = ((double)c + 0.5) * (double)ns / (double)J.nx - 0.5;
+  sx = fmin(fmax(sx, 0.0), (double)(ns - 1));
+  const int i0 = (int)sx;
+  const int i1 = i0 + 1 < ns ? i0 + 1 : ns - 1;
+  const float wt = (float)(sx - (double)i0);
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int n = r0 + hi + STEP * k < J.ny ? r0 + hi + STEP * k : J.ny - 1;
+    const float a = (float)gld(in, (unsigned)(n * ns + i0)), b = (float)gld(in, (unsigned)(n * ns + i1));
+    v[k] = fmaf(wt, b - a, a);
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ void transpose_block(const TileJob& J, int r0, int c0, T* buf) {
   constexpr int B = kTrBlock, SP = B + 1, STEP = kSetupThreads / B, K = B / STEP;
@@ -241,20 +261,9 @@ __device__ __forceinline__ void transpose_block(const TileJob& J, int r0, int c0
   const int c = c0 + lo < J.nx ? c0 + lo : J.nx - 1;
   if constexpr (sizeof(T) == 4) {
     if (J.nx_src > 0) {
-      // Resized from rows of nx_src samples: the two neighbours of the
-      // sample's source position, blended.
-      const int ns = J.nx_src;
-      double sx = ((double)c + 0.5) * (double)ns / (double)J.nx - 0.5;
-      sx = fmin(fmax(sx, 0.0), (double)(ns - 1));
-      const int i0 = (int)sx;
-      const int i1 = i0 + 1 < ns ? i0 + 1 : ns - 1;
-      const float wt = (float)(sx - (double)i0);
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const int n = r0 + hi + STEP * k < J.ny ? r0 + hi + STEP * k : J.ny - 1;
-        const float a = gld(in, (unsigned)(n * ns + i0)), b = gld(in, (unsigned)(n * ns + i1));
-        v[k] = fmaf(wt, b - a, a);
-      }
+      if (J.src_bits == 8) resample_loads<unsigned char, K, STEP>(J, r0, hi, c, v);
+      else if (J.src_bits == 16) resample_loads<unsigned short, K, STEP>(J, r0, hi, c, v);
+      else resample_loads<float, K, STEP>(J, r0, hi, c, v);
     } else {
 #pragma unroll
       for (int k = 0; k < K; ++k) {

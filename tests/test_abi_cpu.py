@@ -261,13 +261,16 @@ def test_stream_frame_validates_before_any_hip_call(lib):
 def test_raw_input_validation(lib):
     st, h = _plan(lib)
     assert st == 0
-    assert lib.sfd_set_raw_input(h, -1) == lib_mod.SFD_ERR_INVALID_ARG
-    assert lib.sfd_set_raw_input(h, 70000) == lib_mod.SFD_ERR_INVALID_ARG
-    assert lib.sfd_set_raw_input(h, 85) == 0
-    assert lib.sfd_set_raw_input(h, 0) == 0
+    assert lib.sfd_set_raw_input(h, -1, 32) == lib_mod.SFD_ERR_INVALID_ARG
+    assert lib.sfd_set_raw_input(h, 70000, 32) == lib_mod.SFD_ERR_INVALID_ARG
+    assert lib.sfd_set_raw_input(h, 85, 12) == lib_mod.SFD_ERR_INVALID_ARG
+    assert b"sample_bits" in lib.sfd_last_error()
+    for bits in (8, 16, 32):
+        assert lib.sfd_set_raw_input(h, 85, bits) == 0
+    assert lib.sfd_set_raw_input(h, 0, 32) == 0
     assert lib.sfd_destroy(h) == 0
     st, h = _plan(lib, flags=lib_mod.SFD_IN_C64 | lib_mod.SFD_OUT_FIELD)
     assert st == 0
-    assert lib.sfd_set_raw_input(h, 85) == lib_mod.SFD_ERR_INVALID_ARG
+    assert lib.sfd_set_raw_input(h, 85, 32) == lib_mod.SFD_ERR_INVALID_ARG
     assert b"real-input" in lib.sfd_last_error()
     assert lib.sfd_destroy(h) == 0

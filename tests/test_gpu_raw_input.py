@@ -80,3 +80,30 @@ def test_raw_widths_rectangular(n_in):
     e = rel_l2(res[0].cpu().numpy(), oracle.intensity(_oracle_views(w, frame)[0]))
     print(f"raw width {n_in}: intensity rel L2 {e:.3e}", flush=True)
     assert e <= TOL
+
+
+@pytest.mark.parametrize("bits", [8, 16])
+def test_integer_camera_samples(bits):
+    """8- and 16-bit camera frames (the samples taken at their value),
+    converted and resized on the GPU, against the oracle on the same samples;
+    and through the streaming entry point, whose copies then move 1 or 2
+    bytes per sample."""
+    w = workloads.config2()
+    ccd = w.extra["ccd"]
+    top = 255.0 if bits == 8 else 4095.0  # a 12-bit sensor in 16-bit words
+    dt = np.uint8 if bits == 8 else np.uint16
+    frame = np.clip(np.rint(ccd / ccd.max() * top), 0, top).astype(dt)
+    p = sfd.Plan(w.wavelength, w.holo_grid, 1, w.views, raw_width=1360, raw_bits=bits, reuse_tables=True,
+                 device=DEV)
+    res = [t.clone() for t in p.reconstruct(torch.from_numpy(frame).to(DEV))]
+    torch.cuda.synchronize()
+    refs = _oracle_views(w, frame.astype(np.float64))
+    for v in range(len(w.views)):
+        e = rel_l2(res[v].cpu().numpy(), oracle.intensity(refs[v]))
+        print(f"{bits}-bit frame view {v}: intensity rel L2 {e:.3e}", flush=True)
+        assert e <= TOL
+    fs = sfd.FrameStream(p)
+    got = fs.push(torch.from_numpy(frame).pin_memory())
+    torch.cuda.synchronize()
+    for a, b in zip(got, res):
+        assert torch.equal(a, b)
