@@ -151,9 +151,7 @@ template <int L>
 struct SpecShape {
   using P = SpecPlan<L>;
   static constexpr int GS = kSetupThreads / P::TPR;  // spectra per workgroup
-  static constexpr int STAGE = GS * L * 8;
-  static constexpr int EXCH = GS * row_lds_bytes<L, kSplit>();
-  static constexpr int BYTES = STAGE > EXCH ? STAGE : EXCH;
+  static constexpr int BYTES = GS * row_lds_bytes<L, kSplit>();  // exchange rows
 };
 
 template <int L>
@@ -162,37 +160,27 @@ __device__ __forceinline__ void setup_spectrum(const SetupArgs& A, const SetupRo
   constexpr int TPR = P::TPR;
   constexpr int R = P::R;
   constexpr int GS = SpecShape<L>::GS;
-  float2* hs = static_cast<float2*>(lds);
-  // The job is the same for every thread of a transform: its fields are read
-  // once (scalar loads) before the loop rather than per element, and its
-  // output pointer is kept for the end.
-  float2* Hout[GS];
-#pragma unroll
-  for (int gj = 0; gj < GS; ++gj) {
-    const int k = rb * GS + gj;
-    Hout[gj] = nullptr;
-    if (k < Ro.c) {
-      const AxisJob J = A.axis[Ro.b + k];
-      Hout[gj] = J.H;
-      for (int i = threadIdx.x; i < L; i += kSetupThreads) hs[gj * L + i] = kernel_value(J, i);
-    } else {
-      for (int i = threadIdx.x; i < L; i += kSetupThreads) hs[gj * L + i] = make_float2(0.f, 0.f);
-    }
-  }
-  __syncthreads();
-  const int g = threadIdx.x / TPR;
+  // Each thread evaluates h straight into its FFT input slots (element
+  // t + TPR i).  The job is the same for every thread of a transform: its
+  // fields are read once (scalar loads when a transform spans whole
+  // wavefronts), and its output pointer is kept for the end.
+  const int g = TPR >= 64 ? __builtin_amdgcn_readfirstlane(threadIdx.x / TPR) : threadIdx.x / TPR;
   const int t = threadIdx.x - g * TPR;
+  const int k = rb * GS + g;
+  float2* Hg = nullptr;
   float2 v[R];
+  if (k < Ro.c) {
+    const AxisJob J = A.axis[Ro.b + k];
+    Hg = J.H;
 #pragma unroll
-  for (int i = 0; i < R; ++i) v[i] = hs[g * L + t + TPR * i];
-  __syncthreads();
+    for (int i = 0; i < R; ++i) v[i] = kernel_value(J, t + TPR * i);
+  } else {
+#pragma unroll
+    for (int i = 0; i < R; ++i) v[i] = make_float2(0.f, 0.f);
+  }
   // Twiddles from the spectrum-shape table (built once per workspace),
   // fetched a stage ahead.
   fft_row<P, false, kSplit, kTwGlobal>(v, static_cast<char*>(lds) + g * row_lds_bytes<L, kSplit>(), t, Ro.tw);
-  float2* Hg = Hout[0];
-#pragma unroll
-  for (int gj = 1; gj < GS; ++gj)
-    if (g == gj) Hg = Hout[gj];
   if (!Hg) return;
   const float inv = 1.0f / (float)L;
 #pragma unroll
