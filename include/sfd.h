@@ -141,7 +141,10 @@ sfd_status sfd_view_lengths(sfd_plan_t plan, int32_t v, int32_t* lx, int32_t* ly
  * from descriptors that each call copies into the workspace first (on
  * ``stream``, only when they changed), so one graph serves every call.  When
  * ``stream`` is being captured by the caller, or kernel timing is on, the
- * kernels are launched directly instead.
+ * kernels are launched directly instead; a caller's captured graph then reads
+ * the descriptors from the workspace when it is replayed, so make one
+ * uncaptured call with the same arguments first (which writes them), and no
+ * call with other pointers or distances on that workspace between replays.
  * With SFD_REUSE_TABLES, a call whose distances equal those of the previous
  * call on the same workspace reuses that call's tables and spectra (the
  * workspace keeps them); sfd_backward on the workspace invalidates them.

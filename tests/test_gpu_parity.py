@@ -236,3 +236,32 @@ def test_autotune_keeps_results_and_seeds_new_plans():
     for a, b in zip(got, ref):
         assert torch.equal(a, b)
     assert _plan(w).schedule() == sched
+
+
+def test_caller_captured_graph_replays():
+    """A caller that captures a reconstruction into its own graph (the
+    library then launches into the capture): every replay, with eager work
+    and synchronisations between replays, equals the eager result."""
+    w = workloads.config1()
+    holo = _holo(w)
+    p = _plan(w, outputs="both")
+    outs = p.new_outputs()
+    ref = [t.clone() for t in p.reconstruct(holo, outs=outs)]
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        p.reconstruct(holo, outs=outs)
+    torch.cuda.synchronize()
+    junk = torch.randn(1 << 16, device=DEV)
+    for rep in range(4):
+        for t in outs:
+            t.zero_()
+        _ = float(junk.sum())
+        g.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(outs, ref):
+            assert torch.equal(a, b), rep
+        eager = p.reconstruct(holo)
+        torch.cuda.synchronize()
+        for a, b in zip(eager, ref):
+            assert torch.equal(a, b), rep
