@@ -7,13 +7,14 @@
 // (step 2), FFT (step 4), multiply by the kernel spectrum (step 7), inverse
 // FFT (step 8), crop (step 9), then the post-chirp or |.|^2 (step 10, Eq. 5).
 //
-//  tables_kernel   chirp tables of Eqs. (2)-(4) per view and axis, phases in
-//                  FP64 reduced to [-1, 1] half-turns before sin/cos, plus the
-//                  FFT twiddle tables.
-//  spectrum_kernel FFT_L(h) / L per view and axis (steps 5-6, per axis since
-//                  h of Eq. 4 is separable).
-//  col_kernel      the y transforms: G columns per workgroup, loaded and
-//                  stored through LDS staging so that global accesses are
+//  setup_kernel    everything a batch needs before the passes, by role:
+//                  kernel spectra FFT_L(h)/L per view and axis (steps 5-6,
+//                  per axis since h of Eq. 4 is separable), the pre/post
+//                  chirp tables of Eqs. (2)-(3) (phases reduced in FP64),
+//                  the FFT twiddle tables, and the column-major hologram
+//                  copies the column pass reads.
+//  col_kernel      the y transforms: G columns per workgroup, stores
+//                  leaving through LDS staging so that global accesses are
 //                  G elements wide; writes the N1y x N0x intermediate.
 //  row_kernel      the x transforms: one row per TPR threads, contiguous
 //                  loads and stores straight from registers.
@@ -26,8 +27,6 @@
 
 namespace sfd {
 
-// exp(i pi v) with v reduced to [-1, 1] in FP64 first, then evaluated in FP64
-// and rounded once to complex64.
 // exp(i pi v) for a large phase v (in half-turns).  The reduction to
 // [-1, 1] is done in FP64, exact enough for phases of 10^5 half-turns and
 // more.  The reduced argument r is split as r_hi + r_lo with r_hi its FP32

@@ -5,8 +5,11 @@ explicit conjugate-transpose product; the dot test <A u, g> = <u, A^H g>
 between the GPU forward and backward; and the gradients of the intensity
 loss L = sum (I - T)^2 with respect to the complex input field and to z,
 against the oracle's product-rule derivative (itself pinned to finite
-differences on the CPU).  Bar: relative L2 <= 1e-4 for the field gradient,
-relative error <= 1e-4 for dL/dz.
+differences on the CPU).  Bar: relative L2 <= 1e-4 and max |error| /
+max |oracle| <= 1e-4 for the adjoint and the field gradient (the gradient
+of an intensity loss is formed from differences I - T of nearly equal
+values, which raises the relative error of its small samples), relative
+error <= 1e-4 for dL/dz.
 """
 
 import numpy as np
@@ -15,7 +18,7 @@ import torch
 
 import oracle
 import workloads
-from tests.helpers import TOL, ogrid, rel_l2
+from tests.helpers import TOL, check, ogrid
 
 pytestmark = pytest.mark.gpu
 
@@ -57,9 +60,7 @@ def test_adjoint_of_complex_gradient_matches_oracle(seed):
     for h in range(len(w.holograms)):
         ref = sum(oracle.adjoint(gs[v], src, ogrid(view.grid), LAM, view.z)
                   for v, view in enumerate(w.views) if view.holo == h)
-        e = rel_l2(grad_in[h].cpu().numpy(), ref)
-        print(f"seed {seed} holo {h}: adjoint rel L2 {e:.3e}", flush=True)
-        assert e <= TOL
+        check(grad_in[h].cpu().numpy(), ref, f"seed {seed} holo {h}: adjoint", elem_tol=TOL)
 
 
 def test_dot_product_between_gpu_forward_and_backward():
@@ -109,9 +110,7 @@ def test_intensity_loss_gradients_match_oracle(seed):
     gi = [2.0 * (inten[v] - torch.from_numpy(targets[v].astype(np.float32)).to(DEV)) for v in range(nv)]
     grad_in, gz = p.backward(gi, holo, field_out=u1)
     torch.cuda.synchronize()
-    e = rel_l2(grad_in.cpu().numpy(), ref_gu)
-    print(f"seed {seed}: field gradient rel L2 {e:.3e}", flush=True)
-    assert e <= TOL
+    check(grad_in.cpu().numpy(), ref_gu, f"seed {seed}: field gradient", elem_tol=TOL)
     gz = gz.cpu().numpy()
     for v in range(nv):
         ez = abs(gz[v] - ref_gz[v]) / abs(ref_gz[v])
@@ -138,11 +137,13 @@ def test_complex_gradient_mode_z_derivative():
         assert abs(got - ref) / abs(ref) <= TOL
 
 
-def test_autograd_function_config4_shape():
-    """The autograd path at the differentiation workload's shape (four 1024^2
-    complex object fields, pitch 2.325 um -> 4.65 um, z in [3, 8] cm)
-    against the oracle, field by field."""
-    w = workloads.config4(batch=4)
+def test_autograd_function_config4():
+    """The autograd path on the differentiation workload (sixteen 1024^2
+    complex object fields, pitch 2.325 um -> 4.65 um, z in [3, 8] cm, the
+    batch the bench times) against the oracle, field by field: the
+    intensities, the field gradients and dL/dz."""
+    w = workloads.config4()
+    assert len(w.views) == 16
     src = ogrid(w.holo_grid)
     targets = []
     for b, view in enumerate(w.views):
@@ -156,11 +157,13 @@ def test_autograd_function_config4_shape():
     loss.backward()
     torch.cuda.synchronize()
     ref_gu, ref_gz = _intensity_loss_grads(w, targets)
-    for b in range(len(w.views)):
-        e = rel_l2(fields.grad[b].cpu().numpy(), ref_gu[b])
+    for b, view in enumerate(w.views):
+        u1 = oracle.direct(w.holograms[view.holo], src, ogrid(view.grid), LAM, view.z)
+        check(inten[b].detach().cpu().numpy(), oracle.intensity(u1), f"field {b}: intensity")
+        check(fields.grad[b].cpu().numpy(), ref_gu[b], f"field {b}: field gradient", elem_tol=TOL)
         ez = abs(float(z.grad[b]) - ref_gz[b]) / abs(ref_gz[b])
-        print(f"field {b}: grad rel L2 {e:.3e}, dL/dz rel {ez:.2e}", flush=True)
-        assert e <= TOL and ez <= TOL
+        print(f"field {b}: dL/dz {float(z.grad[b]):.6e} oracle {ref_gz[b]:.6e} rel {ez:.2e}", flush=True)
+        assert ez <= TOL
 
 
 def test_backward_every_tile_width():

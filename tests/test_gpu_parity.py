@@ -1,7 +1,7 @@
 """HIP path vs the FP64 oracle, element by element, through the C-ABI (GPU).
 
-Bar: relative L2 <= 1e-4 per view for the intensity and, in field mode, for
-the complex field.  Sizes span several row tiles, ragged tails, odd and
+Bar per view, for the intensity and, in field mode, for the complex field:
+relative L2 <= 1e-4 and max |error| / max |oracle| <= 1e-5.  Sizes span several row tiles, ragged tails, odd and
 rectangular grids, anisotropic pitches, shifts on both planes, N0 != N1 and
 either sign of z; the paper-shaped 1024^2 views are compared in full.
 """
@@ -12,7 +12,7 @@ import torch
 
 import oracle
 import workloads
-from tests.helpers import TOL, ogrid, oracle_field, rel_l2
+from tests.helpers import check, ogrid, oracle_field, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -39,20 +39,18 @@ def _random_workload(seed, n0=(5, 90), n1=(5, 90), complex_input=False, n_views=
 
 
 def _check(w, outputs, res, label):
+    """Every view against the oracle: relative L2 and the element-wise bound,
+    for the intensity and, in field mode, the complex field."""
     nv = len(w.views)
     worst = 0.0
     for v in range(nv):
         ref = oracle_field(w, v)
         if outputs in ("intensity", "both"):
-            e = rel_l2(res[v].cpu().numpy(), oracle.intensity(ref))
-            print(f"{label} view {v} intensity rel L2 {e:.3e}", flush=True)
-            assert e <= TOL, (label, v, e)
+            e, _ = check(res[v].cpu().numpy(), oracle.intensity(ref), f"{label} view {v} intensity")
             worst = max(worst, e)
         if outputs in ("field", "both"):
             k = v if outputs == "field" else nv + v
-            e = rel_l2(res[k].cpu().numpy(), ref)
-            print(f"{label} view {v} field rel L2 {e:.3e}", flush=True)
-            assert e <= TOL, (label, v, e)
+            e, _ = check(res[k].cpu().numpy(), ref, f"{label} view {v} field")
             worst = max(worst, e)
     return worst
 
@@ -121,7 +119,7 @@ def test_z_override_and_repeated_calls():
     third = p.reconstruct(holo)[0]
     torch.cuda.synchronize()
     ref2 = oracle_field(w, 0, z=z2)
-    assert rel_l2(second.cpu().numpy(), ref2) <= TOL
+    check(second.cpu().numpy(), ref2, "config1 z override")
     # Plan z again: bitwise identical to the first call.
     assert torch.equal(first, third)
 
@@ -136,10 +134,9 @@ def test_fp32_phase_variant_runs_and_is_reported():
     torch.cuda.synchronize()
     for v in range(len(w.views)):
         ref = oracle_field(w, v)
-        ea = rel_l2(a[v].cpu().numpy(), ref)
+        check(a[v].cpu().numpy(), ref, f"config2 view {v} FP64-reduced phases")
         eb = rel_l2(b[v].cpu().numpy(), ref)
-        print(f"config2 view {v}: FP64-reduced phases {ea:.3e}, all-FP32 phases {eb:.3e}", flush=True)
-        assert ea <= TOL
+        print(f"config2 view {v}: all-FP32 phases rel L2 {eb:.3e}", flush=True)
         assert np.isfinite(eb)
 
 

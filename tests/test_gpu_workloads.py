@@ -3,14 +3,14 @@
 * padded lengths 4096 and 8192 on rectangular grids, where the x and y
   transforms of one view have different lengths, compared in full;
 * the batched uneven workload (8 holograms of 1024^2, 64 views with
-  N1 in {256, 512, 768, 1024}): every view from one batched call, a seeded
-  sample of two views per size class against the oracle, and all 64 views
-  bitwise against one launch sequence per view;
+  N1 in {256, 512, 768, 1024}): every view from one batched call against
+  the oracle, and bitwise against one launch sequence per view;
 * the large workload (4096^2 hologram, eight 4096^2 views, L = 8192): two
   512^2 crops per view (centre and a seeded corner) against the oracle, for
   the FP64-reduced default and, reported only, the all-FP32 phase variant.
 
-Bar: relative L2 <= 1e-4 per view (per crop) for the default path.
+Bar: relative L2 <= 1e-4 and max |error| / max |oracle| <= 1e-5 per view (per
+crop) for the default path.
 """
 
 import numpy as np
@@ -19,7 +19,7 @@ import torch
 
 import oracle
 import workloads
-from tests.helpers import TOL, oracle_field, rel_l2
+from tests.helpers import check, oracle_field, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -48,25 +48,14 @@ def test_long_transforms_rectangular(shape, lengths):
     res = p.reconstruct(_holo(w))
     torch.cuda.synchronize()
     ref = oracle_field(w, 0)
-    ei = rel_l2(res[0].cpu().numpy(), oracle.intensity(ref))
-    ef = rel_l2(res[1].cpu().numpy(), ref)
-    print(f"L={lengths}: intensity rel L2 {ei:.3e}, field rel L2 {ef:.3e}", flush=True)
-    assert ei <= TOL and ef <= TOL
-
-
-def _sample_views(w, per_class=2, seed=3):
-    """Two views per output size class, seeded."""
-    r = np.random.default_rng(seed)
-    by_size = {}
-    for v, view in enumerate(w.views):
-        by_size.setdefault(view.grid.nx, []).append(v)
-    picked = []
-    for n in sorted(by_size):
-        picked += sorted(r.choice(by_size[n], size=min(per_class, len(by_size[n])), replace=False).tolist())
-    return picked
+    check(res[0].cpu().numpy(), oracle.intensity(ref), f"L={lengths} intensity")
+    check(res[1].cpu().numpy(), ref, f"L={lengths} field")
 
 
 def test_config3_batched_uneven_views():
+    """All 64 views of one batched call against the oracle (relative L2 and
+    the element-wise bound per view), and bit for bit against one launch
+    sequence per view."""
     w = workloads.config3()
     assert len(w.views) == 64 and len(w.holograms) == 8
     holo = _holo(w)
@@ -75,14 +64,12 @@ def test_config3_batched_uneven_views():
     torch.cuda.synchronize()
     for x, y in zip(a, b):
         assert torch.equal(x, y)
-    worst = 0.0
-    for v in _sample_views(w):
-        e = rel_l2(a[v].cpu().numpy(), oracle.intensity(oracle_field(w, v)))
-        print(f"config3 view {v} (N1 {w.views[v].grid.nx}, holo {w.views[v].holo}): intensity rel L2 {e:.3e}",
-              flush=True)
-        worst = max(worst, e)
-        assert e <= TOL
-    print(f"config3 worst sampled rel L2 {worst:.3e}", flush=True)
+    worst = (0.0, 0.0)
+    for v, view in enumerate(w.views):
+        e = check(a[v].cpu().numpy(), oracle.intensity(oracle_field(w, v)),
+                  f"config3 view {v} (N1 {view.grid.nx}, holo {view.holo})")
+        worst = (max(worst[0], e[0]), max(worst[1], e[1]))
+    print(f"config3 worst over 64 views: rel L2 {worst[0]:.3e}, max elem {worst[1]:.3e}", flush=True)
 
 
 def test_config5_large_crops_and_fp32_phase_report():
@@ -106,10 +93,8 @@ def test_config5_large_crops_and_fp32_phase_report():
             ref = oracle_field(w, v, rows=rows, cols=cols)
             refs[(v, r0, c0)] = ref
             got = u_a[v][r0:r0 + c, c0:c0 + c].cpu().numpy()
-            ef = rel_l2(got, ref)
-            ei = rel_l2(np.abs(got) ** 2, oracle.intensity(ref))
-            print(f"config5 view {v} crop ({r0},{c0}): field {ef:.3e} intensity {ei:.3e}", flush=True)
-            assert ef <= TOL and ei <= TOL
+            check(got, ref, f"config5 view {v} crop ({r0},{c0}) field")
+            check(np.abs(got) ** 2, oracle.intensity(ref), f"config5 view {v} crop ({r0},{c0}) intensity")
     del u_a
     torch.cuda.empty_cache()
     fp32 = sfd.Plan(w.wavelength, w.holo_grid, 1, w.views, outputs="field", phase_fp32=True, device=DEV)

@@ -80,11 +80,18 @@ def m_dz_drop_inv_z(u0, src, dst, wavelength, z):
 
 
 def m_fft_path_wrong_n(u0, src, dst, wavelength, z, lx=None, ly=None):
-    # Uses the output size where Eq. (2) needs the hologram size.
-    swapped = so.Grid(src.nx, src.ny, src.px, src.py,
-                      src.ox + (src.nx // 2 - dst.nx // 2) * src.px * 0.5,
-                      src.oy)
-    return _ORIG["fft_path"](u0, swapped, dst, wavelength, z, lx, ly)
+    # Eq. (2)'s linear term built with the output size N1 where the
+    # hologram size N0 belongs: (-N1/2 + O0/p0) p0 instead of
+    # (-N0/2 + O0/p0) p0.  The constant C1 multiplies the cropped result, so
+    # the slip is the correct result times
+    # exp(-2 pi i (N0/2 - N1/2) p0 x1 / (lambda z)) per axis.
+    good = _ORIG["fft_path"](u0, src, dst, wavelength, z, lx, ly)
+    x1 = so.coords(dst.nx, dst.px, dst.ox)
+    y1 = so.coords(dst.ny, dst.py, dst.oy)
+    dx = (src.nx // 2 - dst.nx // 2) * src.px
+    dy = (src.ny // 2 - dst.ny // 2) * src.py
+    lz = wavelength * z
+    return good * np.exp(-2j * np.pi / lz * (dx * x1[None, :] + dy * y1[:, None]))
 
 
 _ORIG = {n: getattr(so, n) for n in ("fresnel_matrix", "prefactor", "coords", "direct",
