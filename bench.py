@@ -61,7 +61,9 @@ def pass_costs(w, plan):
     return cost
 
 
-KERNEL_SOURCES = ("paper_1001_4309_amd/csrc/sfd_kernels.hip", "paper_1001_4309_amd/csrc/fft_core.h",
+KERNEL_SOURCES = ("paper_1001_4309_amd/csrc/sfd_kernels.hip", "paper_1001_4309_amd/csrc/sfd_rows.hip",
+                  "paper_1001_4309_amd/csrc/sfd_cols.hip", "paper_1001_4309_amd/csrc/sfd_persist.hip",
+                  "paper_1001_4309_amd/csrc/sfd_device.h", "paper_1001_4309_amd/csrc/fft_core.h",
                   "paper_1001_4309_amd/csrc/sfd_internal.h")
 
 
@@ -429,15 +431,23 @@ def main():
     costs = pass_costs(w, plan)
     kern = {k: {"launches": n, "avg_us": (ms / n * 1e3) if n else 0.0} for k, (n, ms) in rep.items() if n}
     log("kernels:", json.dumps(kern))
-    dom = max(("pass_x", "pass_y"), key=lambda k: rep[k][1])
+    if rep.get("persist", (0, 0.0))[0] > 0:
+        # One persistent launch per step holds every pass.
+        dom = "persist"
+        costs["persist"] = [costs["pass_x"][0] + costs["pass_y"][0], costs["pass_x"][1] + costs["pass_y"][1]]
+    else:
+        dom = max(("pass_x", "pass_y"), key=lambda k: rep[k][1])
     n_launch, tot_ms = rep[dom]
     avg_s = tot_ms / n_launch / 1e3
     launches_per_step = n_launch / prof_steps
     flops = costs[dom][1] / launches_per_step
     lx0, ly0 = plan.lengths(0)
-    dom_L = lx0 if dom == "pass_x" else ly0
-    dom_name = kernel_name(dom, dom_L, plan.schedule()[("row" if dom == "pass_x" else "col", dom_L)],
-                           pass_variant(w, plan, dom))
+    if dom == "persist":
+        dom_name = "persist_kernel"
+    else:
+        dom_L = lx0 if dom == "pass_x" else ly0
+        dom_name = kernel_name(dom, dom_L, plan.schedule()[("row" if dom == "pass_x" else "col", dom_L)],
+                               pass_variant(w, plan, dom))
     traffic = read_traffic(args.config, dom_name)  # HBM bytes per launch, from the committed counters
     roofline = {"bound": "alu", "achieved": flops / avg_s / 1e12, "peak": FP32_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": flops / avg_s / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
@@ -517,7 +527,8 @@ def main():
         "config": {"workload": w.name, "holograms": len(w.holograms), "views_per_step": nv,
                    "hologram": [g.ny, g.nx], "views": [[v.grid.ny, v.grid.nx] for v in w.views],
                    "padded_length": [lx, ly], "phase": "fp64-reduced", "output": "intensity",
-                   "schedule": schedule, "launch": "hip-graph replay"},
+                   "schedule": schedule, "launch": "hip-graph replay",
+                   "launch_mode": plan.launch_mode()[0]},
         "roofline": roofline,
         "hbm": hbm,
         "per_view_launch": per_view,

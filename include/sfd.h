@@ -260,8 +260,68 @@ enum {
   SFD_KERNEL_PASS_X = 2,   /* fused x transforms of the rows, crop, post-chirp or |.|^2 (steps 2-4, 7-10) */
   SFD_KERNEL_PASS_Y = 3,   /* fused y transforms of the hologram columns (steps 2-4, 7-9) */
   SFD_KERNEL_OTHER = 4,    /* backward-only reductions and gathers */
-  SFD_KERNEL_KINDS = 5
+  SFD_KERNEL_PERSIST = 5,  /* the persistent launch: every step of a batched forward in one kernel */
+  SFD_KERNEL_KINDS = 6
 };
+
+/*
+ * Launch schedule of a batched forward (Section 2.2, steps 2-10 for every
+ * view of every hologram).
+ *   SFD_LAUNCH_PASSES      three launches per call: setup (tables, spectra,
+ *                          hologram copies), every column pass, every row
+ *                          pass, with the tile widths of sfd_set_schedule.
+ *   SFD_LAUNCH_PERSISTENT  one launch per call.  Its workgroups take work
+ *                          items in a fixed order from a ticket counter: per
+ *                          view a setup item (spectra and chirp tables), the
+ *                          hologram copies in strips of 16 columns, the
+ *                          column tiles, the row tiles.  An item waits on
+ *                          completion counters for the items it reads (a
+ *                          column tile for its view's setup and its strip, a
+ *                          row tile for every column tile of its view), and
+ *                          those always hold smaller tickets, so the launch
+ *                          completes however many of its workgroups are
+ *                          resident.  The counters live in the workspace; the
+ *                          first call on a workspace zeroes them and the last
+ *                          workgroup of every launch resets them, so graph
+ *                          replays need no memset.  Two calls on one
+ *                          workspace must not run concurrently (they would
+ *                          share the counters, as they share the tables).
+ *                          Available for batched plans where every view's
+ *                          padded lengths are 1024, 1280, 1536, 1792 or 2048
+ *                          with the hologram filling half of each at 1024
+ *                          and 2048 (the paper's doubled grid), 1024 samples
+ *                          at the smooth lengths, and the view no larger.
+ * Plans start persistent where it is available; sfd_autotune keeps the
+ * faster of the two.  Errors: SFD_ERR_INVALID_ARG (unknown mode),
+ * SFD_ERR_UNSUPPORTED (persistent mode not available for the plan).
+ */
+enum { SFD_LAUNCH_PASSES = 0, SFD_LAUNCH_PERSISTENT = 1 };
+sfd_status sfd_set_launch(sfd_plan_t plan, int32_t mode);
+sfd_status sfd_launch_mode(sfd_plan_t plan, int32_t* mode, int32_t* persistent_available);
+
+/*
+ * Length policy (the radix choice of the schedule).  Any padded length
+ * L >= N0 + N1 - 1 evaluates the same linear convolution (Section 2.2,
+ * steps 2 and 9).  smooth != 0 (the default): the smallest supported length,
+ * which between 1024 and 2048 may be 1280 = 2^8 5, 1536 = 2^9 3 or
+ * 1792 = 2^8 7 (transforms closing with a radix-20, -24 or -28 stage);
+ * smooth == 0: powers of two only (the paper's doubled grid).  The
+ * workspace is sized for both, so the same workspace stays valid.
+ * sfd_autotune keeps the faster policy.
+ */
+sfd_status sfd_set_length_policy(sfd_plan_t plan, int32_t smooth);
+sfd_status sfd_length_policy(sfd_plan_t plan, int32_t* smooth);
+
+/*
+ * Dependency faults of persistent launches on a workspace: a wait that gave
+ * up after about two seconds (a counter that never reached its target, which
+ * would otherwise hang the device) sets an error word in the workspace; the
+ * call's results are then undefined.  Copies the word to *faults
+ * (synchronises ``stream``) and clears it when ``clear`` is set.  Diagnostic
+ * and test use.
+ */
+sfd_status sfd_sync_faults(sfd_plan_t plan, void* workspace, size_t ws_bytes, int32_t clear, uint32_t* faults,
+                           hipStream_t stream);
 
 /* Benchmark timing.  While enabled, each kernel the plan launches is
  * bracketed by two HIP events recorded on the launch stream.  Enabling (or

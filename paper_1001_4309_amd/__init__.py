@@ -27,6 +27,7 @@ from ._lib import (SFD_EAGER, SFD_IN_C64, SFD_IN_REAL_F32, SFD_OUT_FIELD, SFD_OU
 __all__ = ["Plan", "SFDFunction", "sfd_plan", "sfd_workspace_size", "sfd_view_lengths", "sfd_reconstruct",
            "sfd_backward", "sfd_autotune", "sfd_schedule", "sfd_set_schedule", "sfd_tile_widths",
            "sfd_stream_frame", "sfd_set_raw_input", "sfd_profile_enable", "sfd_profile_report", "sfd_destroy",
+           "sfd_set_launch", "sfd_launch_mode", "sfd_sync_faults", "sfd_set_length_policy", "sfd_length_policy",
            "SfdError", "FrameStream"]
 
 
@@ -155,6 +156,37 @@ def sfd_profile_report(plan, kind: int):
     return int(n.value), float(ms.value)
 
 
+def sfd_set_launch(plan, mode: int) -> None:
+    _lib.check(_lib.load().sfd_set_launch(plan, int(mode)))
+
+
+def sfd_launch_mode(plan):
+    """(mode, persistent launch available) with mode SFD_LAUNCH_PASSES (0) or
+    SFD_LAUNCH_PERSISTENT (1)."""
+    m, a = ctypes.c_int32(), ctypes.c_int32()
+    _lib.check(_lib.load().sfd_launch_mode(plan, ctypes.byref(m), ctypes.byref(a)))
+    return int(m.value), bool(a.value)
+
+
+def sfd_set_length_policy(plan, smooth: bool) -> None:
+    _lib.check(_lib.load().sfd_set_length_policy(plan, 1 if smooth else 0))
+
+
+def sfd_length_policy(plan) -> bool:
+    """True when the plan uses the smooth lengths (1280, 1536, 1792) where
+    they are shorter than the next power of two."""
+    v = ctypes.c_int32()
+    _lib.check(_lib.load().sfd_length_policy(plan, ctypes.byref(v)))
+    return bool(v.value)
+
+
+def sfd_sync_faults(plan, workspace: torch.Tensor, clear: bool = False) -> int:
+    f = ctypes.c_uint32()
+    _lib.check(_lib.load().sfd_sync_faults(plan, _ptr(workspace), workspace.numel() * workspace.element_size(),
+                                           1 if clear else 0, ctypes.byref(f), _stream_handle(workspace.device)))
+    return int(f.value)
+
+
 def sfd_destroy(plan) -> None:
     if plan:
         _lib.check(_lib.load().sfd_destroy(plan))
@@ -221,6 +253,28 @@ class Plan:
 
     def set_schedule(self, L: int, col: bool, tile_width: int) -> None:
         sfd_set_schedule(self.handle, L, col, tile_width)
+
+    def set_launch(self, persistent: bool) -> None:
+        """One persistent launch per call, or the three pass launches."""
+        sfd_set_launch(self.handle, _lib.SFD_LAUNCH_PERSISTENT if persistent else _lib.SFD_LAUNCH_PASSES)
+
+    def launch_mode(self):
+        """("persistent" | "passes", persistent launch available)."""
+        m, avail = sfd_launch_mode(self.handle)
+        return ("persistent" if m == _lib.SFD_LAUNCH_PERSISTENT else "passes"), avail
+
+    def set_lengths(self, smooth: bool) -> None:
+        """Length policy: smooth lengths (1280, 1536, 1792) where shorter, or
+        powers of two only; the workspace stays valid."""
+        sfd_set_length_policy(self.handle, smooth)
+
+    def length_policy(self) -> str:
+        return "smooth" if sfd_length_policy(self.handle) else "pow2"
+
+    def sync_faults(self, clear: bool = False) -> int:
+        """Dependency waits of persistent launches that gave up on this
+        workspace (0 in a correct run); synchronises."""
+        return sfd_sync_faults(self.handle, self.workspace, clear)
 
     def schedule(self):
         """{(pass, L): tile width} with pass "col" (y transforms) or "row" (x transforms)."""

@@ -29,15 +29,20 @@ SFD_REUSE_TABLES = 1 << 7
 EXPORTED = ["sfd_plan", "sfd_workspace_size", "sfd_view_lengths", "sfd_reconstruct",
             "sfd_backward", "sfd_autotune", "sfd_schedule", "sfd_set_schedule", "sfd_tile_widths",
             "sfd_stream_frame", "sfd_set_raw_input", "sfd_profile_enable", "sfd_profile_report", "sfd_destroy",
-            "sfd_last_error"]
+            "sfd_last_error", "sfd_set_launch", "sfd_launch_mode", "sfd_sync_faults", "sfd_set_length_policy",
+            "sfd_length_policy"]
 
 SFD_KERNEL_TABLES = 0
 SFD_KERNEL_SPECTRA = 1
 SFD_KERNEL_PASS_X = 2
 SFD_KERNEL_PASS_Y = 3
 SFD_KERNEL_OTHER = 4
-SFD_KERNEL_KINDS = 5
-KERNEL_KIND_NAMES = {0: "tables", 1: "spectra", 2: "pass_x", 3: "pass_y", 4: "other"}
+SFD_KERNEL_PERSIST = 5
+SFD_KERNEL_KINDS = 6
+KERNEL_KIND_NAMES = {0: "tables", 1: "spectra", 2: "pass_x", 3: "pass_y", 4: "other", 5: "persist"}
+
+SFD_LAUNCH_PASSES = 0
+SFD_LAUNCH_PERSISTENT = 1
 
 
 class SfdGrid(ctypes.Structure):
@@ -91,12 +96,18 @@ def load() -> ctypes.CDLL:
     lib.sfd_profile_enable.argtypes = [vp, ctypes.c_int32]
     lib.sfd_profile_report.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
                                        ctypes.POINTER(ctypes.c_double)]
+    lib.sfd_set_launch.argtypes = [vp, ctypes.c_int32]
+    lib.sfd_launch_mode.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    lib.sfd_sync_faults.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint32), vp]
+    lib.sfd_set_length_policy.argtypes = [vp, ctypes.c_int32]
+    lib.sfd_length_policy.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     lib.sfd_destroy.argtypes = [vp]
     lib.sfd_last_error.argtypes = []
     lib.sfd_last_error.restype = ctypes.c_char_p
     for name in ("sfd_plan", "sfd_workspace_size", "sfd_view_lengths", "sfd_reconstruct", "sfd_backward",
                  "sfd_autotune", "sfd_schedule", "sfd_set_schedule", "sfd_stream_frame", "sfd_set_raw_input",
-                 "sfd_profile_enable", "sfd_profile_report", "sfd_destroy"):
+                 "sfd_profile_enable", "sfd_profile_report", "sfd_destroy", "sfd_set_launch", "sfd_launch_mode",
+                 "sfd_sync_faults", "sfd_set_length_policy", "sfd_length_policy"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib

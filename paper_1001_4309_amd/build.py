@@ -15,7 +15,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsfd.so")
 
-SOURCES = ["sfd_api.cpp", "sfd_kernels.hip"]
+SOURCES = ["sfd_api.cpp", "sfd_kernels.hip", "sfd_rows.hip", "sfd_cols.hip", "sfd_persist.hip"]
 
 # Packed FP32 instructions are disabled for every device compile: some of their
 # forms have produced silently wrong results on this hardware.
@@ -30,21 +30,28 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False, extra=None) -> str:
-    objs = []
+    """Compile every source (in parallel: the kernel translation units take
+    the longest) and link libsfd.so."""
     tmp = os.path.join(PKG, "_build")
     os.makedirs(tmp, exist_ok=True)
     common = [hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
               "-I", os.path.join(ROOT, "include"), "-I", CSRC] + (extra or [])
+    jobs = []
     for src in SOURCES:
         obj = os.path.join(tmp, src + ".o")
         cmd = common + DEVICE_FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        r = subprocess.run(cmd, capture_output=True, text=True)
-        if r.returncode != 0:
-            sys.stderr.write(r.stdout + r.stderr)
-            raise RuntimeError(f"hipcc failed on {src}")
+        jobs.append((src, obj, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
+    objs, failed = [], []
+    for src, obj, proc in jobs:
+        out, _ = proc.communicate()
+        if proc.returncode != 0:
+            sys.stderr.write(out)
+            failed.append(src)
         objs.append(obj)
+    if failed:
+        raise RuntimeError(f"hipcc failed on {', '.join(failed)}")
     tmp_lib = LIB + ".tmp"
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp_lib] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -40,37 +40,52 @@ __device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
   return make_float2(fmaf(a.x, b.x, a.y * b.y), fmaf(a.y, b.x, -(a.x * b.y)));
 }
 
-// cos(2 pi k / 32) for k = 0..8; other angles follow by symmetry.
-constexpr double kCos32[9] = {1.0,
-                              0.98078528040323044912618223613424,
-                              0.92387953251128675612818318939679,
-                              0.83146961230254523707878837761791,
-                              0.70710678118654752440084436210485,
-                              0.55557023301960222474283081394853,
-                              0.38268343236508977172845998403040,
-                              0.19509032201612826784828486847702,
-                              0.0};
-
-constexpr double cos32(int k) {
-  k = ((k % 32) + 32) % 32;
-  return k <= 8 ? kCos32[k] : k <= 16 ? -kCos32[16 - k] : k <= 24 ? -kCos32[k - 16] : kCos32[32 - k];
+// cos and sin of 2 pi k / n as compile-time constants (double, rounded to
+// float where used).  The angle is reduced exactly with integers to the
+// nearest quarter turn q/4 plus a remainder f in [-1/8, 1/8] turn; sin and
+// cos of 2 pi f come from their Taylor series (|2 pi f| <= pi/4: 14 terms
+// reach double precision), then rotate by q quarter turns.
+constexpr double kPi = 3.14159265358979323846264338327950288;
+struct SinCos {
+  double s, c;
+};
+constexpr SinCos sincos_turn(long k, long n) {
+  const long m = ((k % n) + n) % n;         // angle 2 pi m / n, m in [0, n)
+  const long q = (4 * m + n / 2) / n;       // nearest quarter turn (0..4)
+  const double f = (double)(4 * m - q * n) / (double)(4 * n);  // remainder in turns
+  const double t = 2.0 * kPi * f, t2 = t * t;
+  double sn = t, cs = 1.0, ts = t, tc = 1.0;
+  for (int i = 1; i < 14; ++i) {
+    ts *= -t2 / (double)((2 * i) * (2 * i + 1));
+    tc *= -t2 / (double)((2 * i - 1) * (2 * i));
+    sn += ts;
+    cs += tc;
+  }
+  switch (q % 4) {
+    case 0: return {sn, cs};
+    case 1: return {cs, -sn};
+    case 2: return {-sn, -cs};
+    default: return {-cs, sn};
+  }
 }
-constexpr double sin32(int k) { return cos32(k - 8); }
 
-// a * exp(sgn 2 pi i K / N), sgn = -1 forward, +1 inverse; N divides 32.
+// a * exp(sgn 2 pi i K / N), sgn = -1 forward, +1 inverse.  Multiples of a
+// quarter turn are exact sign/swap operations, odd multiples of an eighth
+// turn use the common factor 1/sqrt(2).
 template <int N, int K, bool INV>
 __device__ __forceinline__ float2 mul_w(float2 a) {
-  constexpr int k32 = ((K * (32 / N)) % 32 + 32) % 32;
-  constexpr float c = static_cast<float>(cos32(k32));
-  constexpr float s = static_cast<float>(INV ? sin32(k32) : -sin32(k32));
-  if constexpr (k32 == 0) {
+  constexpr int k = ((K % N) + N) % N;
+  constexpr SinCos w = sincos_turn(k, N);
+  constexpr float c = static_cast<float>(w.c);
+  constexpr float s = static_cast<float>(INV ? w.s : -w.s);
+  if constexpr (k == 0) {
     return a;
-  } else if constexpr (k32 == 16) {
+  } else if constexpr (2 * k == N) {
     return make_float2(-a.x, -a.y);
-  } else if constexpr (k32 == 8 || k32 == 24) {
+  } else if constexpr (4 * k == N || 4 * k == 3 * N) {
     if constexpr (s > 0) return make_float2(-a.y, a.x);
     else return make_float2(a.y, -a.x);
-  } else if constexpr (k32 % 8 == 4) {
+  } else if constexpr ((8 * k) % N == 0) {
     constexpr float h = 0.70710678118654752440f;
     constexpr float sc = c > 0 ? 1.f : -1.f;
     constexpr float ss = s > 0 ? 1.f : -1.f;
@@ -90,12 +105,70 @@ __device__ __forceinline__ void combine(float2 (&out)[N], const float2 (&e)[N / 
   }
 }
 
-// In-place length-N DFT of a register array (natural order in and out),
-// radix-2 decimation in time down to a length-4 kernel.
+// Length-N DFT for odd N from its symmetric pairs: with s_k = a_k + a_{N-k}
+// and d_k = a_k - a_{N-k} (k = 1 .. (N-1)/2),
+//   X_0 = a_0 + sum s_k,
+//   X_m, X_{N-m} = a_0 + sum_k cos(2 pi k m / N) s_k  -/+ i sgn sum_k sin(2 pi k m / N) d_k,
+// sgn = +1 forward, -1 inverse (the direct definition, regrouped).
+template <int N, int M, int K = 0>
+__device__ __forceinline__ void odd_sums(float2& re, float2& im, const float2 (&sp)[(N - 1) / 2],
+                                         const float2 (&dp)[(N - 1) / 2]) {
+  if constexpr (K < (N - 1) / 2) {
+    constexpr SinCos w = sincos_turn((K + 1) * M, N);
+    constexpr float c = static_cast<float>(w.c), s = static_cast<float>(w.s);
+    re = make_float2(fmaf(c, sp[K].x, re.x), fmaf(c, sp[K].y, re.y));
+    im = make_float2(fmaf(s, dp[K].x, im.x), fmaf(s, dp[K].y, im.y));
+    odd_sums<N, M, K + 1>(re, im, sp, dp);
+  }
+}
+template <int N, bool INV, int M = 1>
+__device__ __forceinline__ void odd_outputs(float2 (&out)[N], float2 a0, const float2 (&sp)[(N - 1) / 2],
+                                            const float2 (&dp)[(N - 1) / 2]) {
+  if constexpr (M <= (N - 1) / 2) {
+    float2 re = a0, im = make_float2(0.f, 0.f);
+    odd_sums<N, M>(re, im, sp, dp);
+    // Forward: X_m = re - i im, X_{N-m} = re + i im; inverse the other way.
+    const float2 mi = INV ? make_float2(-im.y, im.x) : make_float2(im.y, -im.x);
+    out[M] = cadd(re, mi);
+    out[N - M] = csub(re, mi);
+    odd_outputs<N, INV, M + 1>(out, a0, sp, dp);
+  }
+}
+
+// Length-N DFT for odd N from its symmetric pairs: with s_k = a_k + a_{N-k}
+// and d_k = a_k - a_{N-k} (k = 1 .. (N-1)/2) and t = 2 pi k m / N,
+//   X_0 = a_0 + sum s_k,
+//   X_m, X_{N-m} = (a_0 + sum_k cos(t) s_k) -/+ i sgn sum_k sin(t) d_k,
+// sgn = +1 forward, -1 inverse (the definition with the terms k and N - k
+// taken together).
+template <int N, bool INV>
+__device__ __forceinline__ void dft_odd(float2 (&a)[N]) {
+  constexpr int H = (N - 1) / 2;
+  float2 sp[H], dp[H];
+#pragma unroll
+  for (int k = 1; k <= H; ++k) {
+    sp[k - 1] = cadd(a[k], a[N - k]);
+    dp[k - 1] = csub(a[k], a[N - k]);
+  }
+  float2 out[N];
+  float2 x0 = a[0];
+#pragma unroll
+  for (int k = 0; k < H; ++k) x0 = cadd(x0, sp[k]);
+  out[0] = x0;
+  odd_outputs<N, INV>(out, a[0], sp, dp);
+#pragma unroll
+  for (int i = 0; i < N; ++i) a[i] = out[i];
+}
+
+// In-place length-N DFT of a register array (natural order in and out):
+// radix-2 decimation in time for even N, down to a length-4 kernel, or to
+// an odd length (3, 5, 7) evaluated from its symmetric pairs.
 template <int N, bool INV>
 __device__ __forceinline__ void dft(float2 (&a)[N]) {
   if constexpr (N == 1) {
     return;
+  } else if constexpr (N % 2 == 1) {
+    dft_odd<N, INV>(a);
   } else if constexpr (N == 2) {
     const float2 t = a[0];
     a[0] = cadd(t, a[1]);
@@ -212,6 +285,12 @@ template <> struct PassPlan<256> : FftShape<256, 16, Radices<16, 16>> {};
 template <> struct PassPlan<512> : FftShape<512, 32, Radices<16, 8, 4>> {};
 template <> struct PassPlan<1024> : FftShape<1024, 64, Radices<16, 8, 8>> {};
 template <> struct PassPlan<2048> : FftShape<2048, 64, Radices<32, 8, 8>> {};
+// Smooth lengths between 1024 and 2048 (a hologram of 1024 samples with a
+// view of 256, 512 or 768 needs L >= 1279, 1535, 1791): power-of-two stages
+// first, the stage with the odd factor last (see stage_compute).
+template <> struct PassPlan<1280> : FftShape<1280, 64, Radices<4, 4, 4, 20>> {};
+template <> struct PassPlan<1536> : FftShape<1536, 64, Radices<8, 8, 24>> {};
+template <> struct PassPlan<1792> : FftShape<1792, 64, Radices<4, 4, 4, 28>> {};
 template <> struct PassPlan<4096> : FftShape<4096, 128, Radices<32, 16, 8>> {};
 template <> struct PassPlan<8192> : FftShape<8192, 256, Radices<32, 16, 16>> {};
 
@@ -225,6 +304,9 @@ template <> struct SpecPlan<256> : FftShape<256, 32, Radices<8, 8, 4>> {};
 template <> struct SpecPlan<512> : FftShape<512, 64, Radices<8, 8, 8>> {};
 template <> struct SpecPlan<1024> : FftShape<1024, 128, Radices<8, 8, 8, 2>> {};
 template <> struct SpecPlan<2048> : FftShape<2048, 256, Radices<8, 8, 8, 4>> {};
+template <> struct SpecPlan<1280> : PassPlan<1280> {};
+template <> struct SpecPlan<1536> : PassPlan<1536> {};
+template <> struct SpecPlan<1792> : PassPlan<1792> {};
 template <> struct SpecPlan<4096> : FftShape<4096, 256, Radices<16, 16, 16>> {};
 template <> struct SpecPlan<8192> : FftShape<8192, 256, Radices<32, 16, 16>> {};
 
@@ -411,7 +493,11 @@ __device__ __forceinline__ void stage_compute(float2 (&v)[L / TPR], void* __rest
   constexpr int R = L / TPR;
   constexpr int nb = R / r;
   static_assert(R % r == 0, "radix must divide the values per thread");
-  static_assert(r <= 32 && (32 % r) == 0, "radices are powers of two up to 32");
+  // A radix that is not a power of two may only close a transform: the last
+  // stage writes no exchange, and its twiddle index j mod Ns needs Ns a power
+  // of two.
+  static_assert((r <= 32 && (32 % r) == 0) || (LAST && (Ns & (Ns - 1)) == 0),
+                "radices are powers of two up to 32, except in the last stage");
   float2* cbuf = static_cast<float2*>(buf);
 #pragma unroll
   for (int q = 0; q < nb; ++q) {

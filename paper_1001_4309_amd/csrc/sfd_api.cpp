@@ -56,12 +56,17 @@ bool grid_ok(const sfd_grid& g, std::string* why, const char* what) {
   return true;
 }
 
+// Padded lengths the transforms support, ascending: powers of two and the
+// smooth lengths 1280 = 2^8 5, 1536 = 2^9 3, 1792 = 2^8 7.
+constexpr int kLengths[] = {64, 128, 256, 512, 1024, 1280, 1536, 1792, 2048, 4096, 8192};
+
 // Smallest supported padded length for a linear convolution of n0 inputs
 // onto n1 outputs (reading of steps 2 and 9: any L >= n0 + n1 - 1 is exact).
-int choose_length(int n0, int n1) {
+// smooth = false: powers of two only (the paper's doubling).
+int choose_length(int n0, int n1, bool smooth = true) {
   const long need = (long)n0 + (long)n1 - 1;
-  for (int L = 64; L <= 8192; L *= 2)
-    if (L >= need) return L;
+  for (int L : kLengths)
+    if (L >= need && (smooth || (L & (L - 1)) == 0)) return L;
   return -1;
 }
 
@@ -177,6 +182,18 @@ struct sfd_plan_s {
   std::vector<Rec> recs;
   std::vector<hipEvent_t> event_pool;
 
+  // Persistent launch (batched plans whose passes all have persistent
+  // shapes): counters in the workspace, zeroed once per workspace.
+  bool smooth = true;        // length policy (see set_lengths)
+  bool persist_ok = false;   // the plan's shapes allow it
+  bool persist = false;      // the schedule uses it
+  size_t sync_off = 0;
+  int sync_words = 0;
+  int nstrips = 0;
+  int col_tiles = 0;         // column tiles per view
+  void* sync_ready_ws = nullptr;
+  int persist_grid = 0;
+
   // Schedule: tile width per transform length of the column (y) and row (x)
   // passes; lengths not listed use the default.
   std::map<int, int> gcol, grow;
@@ -290,6 +307,9 @@ struct CallDescs {
   std::vector<int> axis_L;             // L of each axis job
   std::vector<int> row_L;              // L of each row job
   int n_pass_x = 0;
+  // Persistent launch: device address of its arguments and its item count.
+  const sfd::PersistArgs* d_pa = nullptr;
+  int persist_total = 0;
 };
 
 size_t bwd_desc_capacity(int n_views, int n_holo, int n_lengths, int n_tiles) {
@@ -299,9 +319,18 @@ size_t bwd_desc_capacity(int n_views, int n_holo, int n_lengths, int n_tiles) {
          align_up(sizeof(void*) * n_views);
 }
 
+// Persistent launch descriptors after the row jobs: the launch arguments,
+// one PassArgs per pass segment, column tiles per view, twiddle tables per
+// view and axis.
+size_t persist_desc_bytes(int n_views) {
+  return align_up(sizeof(sfd::PersistArgs)) + align_up(sizeof(sfd::PassArgs) * sfd::kMaxSegments) +
+         align_up(sizeof(int32_t) * n_views) + align_up(sizeof(void*) * 2 * n_views);
+}
+
 size_t desc_capacity(int n_views, int n_lengths, int n_tiles) {
   return align_up(sizeof(sfd::AxisJob) * 2 * n_views) + align_up(sizeof(sfd::TwiddleJob) * 2 * n_lengths) +
-         align_up(sizeof(sfd::TileJob) * n_tiles) + align_up(sizeof(sfd::RowJob) * 2 * n_views);
+         align_up(sizeof(sfd::TileJob) * n_tiles) + align_up(sizeof(sfd::RowJob) * 2 * n_views) +
+         persist_desc_bytes(n_views);
 }
 
 // The twiddle tables of length L, both shapes: the passes' and the kernel
@@ -366,7 +395,9 @@ sfd_status build_descs(sfd_plan_s* P, const void* holo, const double* z, void* c
       ax.push_back({j, j.L});
     }
   }
-  if (!(P->flags & SFD_PER_VIEW_LAUNCH))
+  // The setup launch groups the spectra by length; the persistent launch's
+  // setup items take a view's two axis jobs at 2v and 2v + 1.
+  if (!(P->flags & SFD_PER_VIEW_LAUNCH) && !P->persist)
     std::stable_sort(ax.begin(), ax.end(), [](const AxisTmp& a, const AxisTmp& b) { return a.L < b.L; });
   D->axis.clear();
   D->axis_L.clear();
@@ -419,6 +450,8 @@ sfd_status build_descs(sfd_plan_s* P, const void* holo, const double* z, void* c
     jc.in = ws + P->tiles[L.tile].off;
     jc.in_ld = col_ld(h.ny);
     jc.colscale = reinterpret_cast<const float2*>(ws + L.prex);
+    jc.view = v;
+    jc.copy = L.tile;
     py.push_back({L.ly, jc});
 
     sfd::RowJob jr{};
@@ -436,6 +469,8 @@ sfd_status build_descs(sfd_plan_s* P, const void* holo, const double* z, void* c
     jr.in_ld = ldw;
     jr.out_ld = w.out.nx;
     jr.mode = (field ? (sfd::kUsePost | sfd::kOutField) : 0) | (inten ? sfd::kOutIntensity : 0);
+    jr.view = v;
+    jr.copy = L.tile;
     px.push_back({L.lx, jr});
   }
   auto by_len = [](const std::pair<int, sfd::RowJob>& a, const std::pair<int, sfd::RowJob>& b) {
@@ -457,13 +492,32 @@ sfd_status build_descs(sfd_plan_s* P, const void* holo, const double* z, void* c
   return SFD_OK;
 }
 
+// Kernel specialisation of a pass over row jobs [i, j) of length L (the
+// rule of launch_pass, see sfd_internal.h).
+int pass_var(const CallDescs& D, int i, int j, int L, bool col) {
+  bool fast = true, no_post = true, int_only = true, all_real = true, all_complex = true;
+  for (int k = i; k < j; ++k) {
+    const sfd::RowJob& r = D.rows[k];
+    const int F = sfd::fast_input(L);
+    fast = fast && r.n_in == F && r.n_out <= F && !(r.mode & sfd::kReduce);
+    no_post = no_post && !(r.mode & sfd::kUsePost);
+    int_only = int_only && (r.mode & sfd::kOutIntensity) && !(r.mode & sfd::kOutField);
+    all_real = all_real && (r.mode & sfd::kInReal);
+    all_complex = all_complex && !(r.mode & sfd::kInReal);
+  }
+  if (fast && col) return all_complex ? 1 : !all_real ? 0 : no_post ? 2 : 3;
+  if (fast && all_complex) return no_post && int_only ? 2 : 1;
+  return 0;
+}
+
 // Serialise descriptors into the workspace layout; returns the byte image.
 void pack_descs(const sfd_plan_s* P, const CallDescs& D, std::vector<unsigned char>* img, size_t* off_axis,
-                size_t* off_tw, size_t* off_rows) {
+                size_t* off_tw, size_t* off_rows, size_t* off_tiles_out = nullptr) {
   const int V = (int)P->views.size();
   *off_axis = 0;
   *off_tw = align_up(sizeof(sfd::AxisJob) * 2 * V);
   const size_t off_tiles = *off_tw + align_up(sizeof(sfd::TwiddleJob) * 2 * P->lengths.size());
+  if (off_tiles_out) *off_tiles_out = off_tiles;
   *off_rows = off_tiles + align_up(sizeof(sfd::TileJob) * P->tiles.size());
   const size_t total = *off_rows + sizeof(sfd::RowJob) * D.rows.size();
   img->assign(total, 0);
@@ -471,6 +525,104 @@ void pack_descs(const sfd_plan_s* P, const CallDescs& D, std::vector<unsigned ch
   std::memcpy(img->data() + *off_tw, D.tw.data(), sizeof(sfd::TwiddleJob) * D.tw.size());
   std::memcpy(img->data() + off_tiles, D.tiles.data(), sizeof(sfd::TileJob) * D.tiles.size());
   std::memcpy(img->data() + *off_rows, D.rows.data(), sizeof(sfd::RowJob) * D.rows.size());
+}
+
+// Runs of jobs [first, end) with equal L and at most kMaxJobsPerLaunch jobs.
+template <typename F>
+void for_length_runs(const CallDescs& D, int first, int end, F f) {
+  int i = first;
+  while (i < end) {
+    const int L = D.row_L[i];
+    int j = i;
+    while (j < end && D.row_L[j] == L && j - i < sfd::kMaxJobsPerLaunch) ++j;
+    f(i, j, L);
+    i = j;
+  }
+}
+
+// Segments of a persistent launch for the plan's shapes (setup when
+// ``tables``, strips, then a column and a row segment per length run).
+int persist_segments(const sfd_plan_s* P, const CallDescs& D, bool tables) {
+  int n = (tables ? 1 : 0) + 1;
+  for_length_runs(D, 0, D.n_pass_x, [&](int, int, int) { ++n; });
+  for_length_runs(D, D.n_pass_x, (int)D.rows.size(), [&](int, int, int) { ++n; });
+  (void)P;
+  return n;
+}
+
+// Append the persistent launch's descriptors to the image (after the row
+// jobs) and set D->d_pa and D->persist_total.  Every pointer they hold is a
+// workspace address, so the image only changes with the plan's schedule,
+// the call's tables flag and the call's pointers.
+void pack_persist(const sfd_plan_s* P, CallDescs* D, char* ws, bool tables, std::vector<unsigned char>* img,
+                  size_t off_axis, size_t off_tiles, size_t off_rows) {
+  const int V = (int)P->views.size();
+  char* dbase = ws + P->desc_off;
+  const size_t off_pa = align_up(off_rows + sizeof(sfd::RowJob) * D->rows.size());
+  const size_t off_pass = off_pa + align_up(sizeof(sfd::PersistArgs));
+  const size_t off_ct = off_pass + align_up(sizeof(sfd::PassArgs) * sfd::kMaxSegments);
+  const size_t off_twv = off_ct + align_up(sizeof(int32_t) * V);
+  const size_t end = off_twv + align_up(sizeof(void*) * 2 * V);
+  img->resize(end, 0);
+  sfd::PersistArgs pa{};
+  std::vector<sfd::PassArgs> pass;
+  int t = 0;
+  auto add = [&](int kind, int count, int L, int var, const sfd::PassArgs* args, const float2* tw) {
+    sfd::Segment& g = pa.seg[pa.nseg++];
+    g.kind = kind;
+    g.first = t;
+    g.count = count;
+    g.L = L;
+    g.var = var;
+    g.args = args;
+    g.tw = tw;
+    t += count;
+  };
+  if (tables) add(sfd::kItemSetup, V, 0, 0, nullptr, nullptr);
+  add(sfd::kItemStrip, P->nstrips, 0, 0, nullptr, nullptr);
+  const auto* d_rows = reinterpret_cast<const sfd::RowJob*>(dbase + off_rows);
+  const auto* d_pass = reinterpret_cast<const sfd::PassArgs*>(dbase + off_pass);
+  for (int col = 1; col >= 0; --col) {
+    const int first = col ? 0 : D->n_pass_x, last = col ? D->n_pass_x : (int)D->rows.size();
+    for_length_runs(*D, first, last, [&](int i, int j, int L) {
+      sfd::PassArgs a{};
+      a.jobs = d_rows + i;
+      a.njobs = j - i;
+      int acc = 0;
+      for (int k = i; k < j; ++k) {
+        a.tile_prefix[k - i] = acc;
+        acc += (D->rows[k].n_rows + sfd::kStripW - 1) / sfd::kStripW;
+      }
+      a.tile_prefix[j - i] = acc;
+      a.total_tiles = acc;
+      add(col ? sfd::kItemCol : sfd::kItemRow, acc, L, pass_var(*D, i, j, L, col != 0), d_pass + pass.size(),
+          reinterpret_cast<const float2*>(ws + P->tw_off.at(L)));
+      pass.push_back(a);
+    });
+  }
+  pa.total = t;
+  pa.grid = std::max(1, std::min(t, P->persist_grid));
+  pa.nview = V;
+  pa.wait_setup = tables ? 1 : 0;
+  pa.ncopy = (int)P->tiles.size();
+  pa.nstrips = P->nstrips;
+  pa.axis = reinterpret_cast<const sfd::AxisJob*>(dbase + off_axis);
+  pa.tiles = reinterpret_cast<const sfd::TileJob*>(dbase + off_tiles);
+  pa.col_tiles = reinterpret_cast<const int32_t*>(dbase + off_ct);
+  pa.tw_view = reinterpret_cast<const float2* const*>(dbase + off_twv);
+  pa.sync = reinterpret_cast<uint32_t*>(ws + P->sync_off);
+  std::vector<int32_t> ct(V, P->col_tiles);
+  std::vector<const float2*> twv(2 * V);
+  for (int v = 0; v < V; ++v) {
+    twv[2 * v] = reinterpret_cast<const float2*>(ws + P->tws_off.at(P->lay[v].lx));
+    twv[2 * v + 1] = reinterpret_cast<const float2*>(ws + P->tws_off.at(P->lay[v].ly));
+  }
+  std::memcpy(img->data() + off_pa, &pa, sizeof pa);
+  std::memcpy(img->data() + off_pass, pass.data(), sizeof(sfd::PassArgs) * pass.size());
+  std::memcpy(img->data() + off_ct, ct.data(), sizeof(int32_t) * V);
+  std::memcpy(img->data() + off_twv, twv.data(), sizeof(void*) * 2 * V);
+  D->d_pa = reinterpret_cast<const sfd::PersistArgs*>(dbase + off_pa);
+  D->persist_total = t;
 }
 
 // Copy a descriptor image into the workspace at ``dst_off`` (slot 0:
@@ -581,19 +733,7 @@ sfd_status launch_rows(const CallDescs& D, const sfd::RowJob* d_rows, int first,
     }
     a.tile_prefix[j - i] = acc;
     a.total_tiles = acc;
-    // Kernel specialisation (see launch_pass).
-    bool fast = true, no_post = true, int_only = true, all_real = true, all_complex = true;
-    for (int k = i; k < j; ++k) {
-      const sfd::RowJob& r = D.rows[k];
-      fast = fast && 2 * r.n_in == L && 2 * r.n_out <= L && !(r.mode & sfd::kReduce);
-      no_post = no_post && !(r.mode & sfd::kUsePost);
-      int_only = int_only && (r.mode & sfd::kOutIntensity) && !(r.mode & sfd::kOutField);
-      all_real = all_real && (r.mode & sfd::kInReal);
-      all_complex = all_complex && !(r.mode & sfd::kInReal);
-    }
-    int var = 0;
-    if (fast && col) var = all_complex ? 1 : !all_real ? 0 : no_post ? 2 : 3;
-    else if (fast && all_complex) var = no_post && int_only ? 2 : 1;
+    const int var = pass_var(D, i, j, L, col);
     const float2* tw = reinterpret_cast<const float2*>(ws + P->tw_off.at(L));
     SFD_TIMED(P, kind, stream, sfd::launch_pass(L, col, G, var, a, tw, stream));
     i = j;
@@ -614,6 +754,37 @@ void apply_schedule(sfd_plan_s* P) {
   P->drop_graph();
 }
 
+// Whether the persistent launch serves the plan's current lengths: a batched
+// plan whose passes all run the persistent shapes (fast inputs, see
+// fast_input, at a persistent length) in few enough segments.
+bool persist_eligible(const sfd_plan_s* P) {
+  if (P->flags & SFD_PER_VIEW_LAUNCH) return false;
+  const sfd_grid& h = P->holo;
+  std::map<int, int> per_len;
+  for (size_t v = 0; v < P->views.size(); ++v) {
+    const sfd_grid& o = P->views[v].out;
+    const int lx = P->lay[v].lx, ly = P->lay[v].ly;
+    if (!(sfd::persist_length(lx) && sfd::persist_length(ly) && h.nx == sfd::fast_input(lx) &&
+          o.nx <= sfd::fast_input(lx) && h.ny == sfd::fast_input(ly) && o.ny <= sfd::fast_input(ly)))
+      return false;
+    per_len[ly]++;
+    per_len[-lx]++;
+  }
+  int segs = 2;
+  for (const auto& kv : per_len) segs += (kv.second + sfd::kMaxJobsPerLaunch - 1) / sfd::kMaxJobsPerLaunch;
+  return segs <= sfd::kMaxSegments;
+}
+
+// Length policy: smooth lengths where they are shorter (default), or the
+// paper's powers of two.  Per-view arrays are sized for the longer choice.
+void set_lengths(sfd_plan_s* P, bool smooth) {
+  P->smooth = smooth;
+  for (size_t v = 0; v < P->views.size(); ++v) {
+    P->lay[v].lx = choose_length(P->holo.nx, P->views[v].out.nx, smooth);
+    P->lay[v].ly = choose_length(P->holo.ny, P->views[v].out.ny, smooth);
+  }
+}
+
 // The batched forward sequence: every view's tables, spectra and hologram
 // tiles (tables = false: the tiles only), then all column passes, then all
 // row passes.
@@ -621,6 +792,11 @@ sfd_status launch_forward(sfd_plan_s* P, const CallDescs& D, char* ws, const sfd
                           const sfd::TwiddleJob* d_tw, const sfd::TileJob* d_tiles, const sfd::RowJob* d_rows,
                           hipStream_t stream, bool tables = true) {
   sfd_status st;
+  if (P->persist) {
+    SFD_TIMED(P, SFD_KERNEL_PERSIST, stream,
+              sfd::launch_persist(D.d_pa, std::max(1, std::min(D.persist_total, P->persist_grid)), stream));
+    return SFD_OK;
+  }
   if ((st = launch_setup_for(P, D, ws, d_axis, d_tw, d_tiles, 0, tables ? (int)D.axis.size() : 0, false, 0,
                              (int)D.tiles.size(), stream)) != SFD_OK)
     return st;
@@ -1009,11 +1185,16 @@ sfd_status sfd_plan(sfd_plan_t* plan, double wavelength, const sfd_grid* holo_gr
   P->flags = flags;
   const bool field = (flags & SFD_OUT_FIELD) != 0;
 
+  // Padded lengths of both length policies (smooth lengths where they are
+  // shorter, or powers of two only): the workspace holds the twiddle tables
+  // of both, and every per-view array is sized for the longer choice, so the
+  // schedule can switch policies on the same workspace.
   std::vector<int> ls;
-  for (int v = 0; v < n_views; ++v) {
-    ls.push_back(choose_length(h.nx, views[v].out.nx));
-    ls.push_back(choose_length(h.ny, views[v].out.ny));
-  }
+  for (int v = 0; v < n_views; ++v)
+    for (int smooth = 0; smooth < 2; ++smooth) {
+      ls.push_back(choose_length(h.nx, views[v].out.nx, smooth != 0));
+      ls.push_back(choose_length(h.ny, views[v].out.ny, smooth != 0));
+    }
   std::sort(ls.begin(), ls.end());
   ls.erase(std::unique(ls.begin(), ls.end()), ls.end());
   P->lengths = ls;
@@ -1050,6 +1231,7 @@ sfd_status sfd_plan(sfd_plan_t* plan, double wavelength, const sfd_grid* holo_gr
     const sfd_grid& o = views[v].out;
     L.lx = choose_length(h.nx, o.nx);
     L.ly = choose_length(h.ny, o.ny);
+    const int lx2 = choose_length(h.nx, o.nx, false), ly2 = choose_length(h.ny, o.ny, false);
     auto take = [&](size_t bytes) {
       const size_t at = off;
       off += align_up(bytes);
@@ -1061,9 +1243,25 @@ sfd_status sfd_plan(sfd_plan_t* plan, double wavelength, const sfd_grid* holo_gr
       L.postx = take(sizeof(float2) * o.nx);
       L.posty = take(sizeof(float2) * o.ny);
     }
-    L.hx = take(sizeof(float2) * L.lx);
-    L.hy = take(sizeof(float2) * L.ly);
+    L.hx = take(sizeof(float2) * lx2);
+    L.hy = take(sizeof(float2) * ly2);
     L.inter = take(sizeof(float2) * (size_t)o.ny * inter_ld(h.nx));  // N1y x N0x after the y transforms
+  }
+  // Persistent launch: its counters, when either length policy allows it.
+  {
+    const bool ok_smooth = persist_eligible(P);
+    set_lengths(P, false);
+    const bool ok_pow2 = persist_eligible(P);
+    set_lengths(P, true);
+    P->persist_ok = ok_smooth;
+    P->persist = ok_smooth;
+    if (ok_smooth || ok_pow2) {
+      P->nstrips = (int)P->tiles.size() * ((h.nx + sfd::kStripW - 1) / sfd::kStripW);
+      P->col_tiles = (h.nx + sfd::kStripW - 1) / sfd::kStripW;
+      P->sync_words = sfd::persist_sync_words(n_views, P->nstrips);
+      P->sync_off = off;
+      off += align_up(sizeof(uint32_t) * P->sync_words);
+    }
   }
   if (flags & SFD_IN_C64) {
     // Backward: per view its own forward, moment and adjoint tables, the
@@ -1084,7 +1282,8 @@ sfd_status sfd_plan(sfd_plan_t* plan, double wavelength, const sfd_grid* holo_gr
     for (int v = 0; v < n_views; ++v) {
       sfd_plan_s::BwdLayout& B = P->blay[v];
       const sfd_grid& o = views[v].out;
-      const int lx = P->lay[v].lx, ly = P->lay[v].ly;
+      // Sized for the longer (power-of-two) length choice.
+      const int lx = choose_length(h.nx, o.nx, false), ly = choose_length(h.ny, o.ny, false);
       B.prexf = take(c8 * h.nx);
       B.preyf = take(c8 * h.ny);
       B.postxf = take(c8 * o.nx);
@@ -1105,7 +1304,7 @@ sfd_status sfd_plan(sfd_plan_t* plan, double wavelength, const sfd_grid* holo_gr
       B.wa = take(c8 * (size_t)h.ny * inter_ld(o.nx));
       B.vbuf = P->holo_views[views[v].holo] > 1 ? take(c8 * (size_t)h.nx * h.ny) : 0;
       // Partials: room for the most row-pass tiles any schedule launches.
-      const int gmin = min_tile_width(lx, false);
+      const int gmin = std::min(min_tile_width(lx, false), min_tile_width(choose_length(h.nx, o.nx), false));
       B.nt_r = (o.ny + gmin - 1) / gmin;
       B.nt_a = (h.ny + gmin - 1) / gmin;
       B.p12 = take(4 * sizeof(double) * B.nt_r);
@@ -1129,6 +1328,14 @@ sfd_status sfd_plan(sfd_plan_t* plan, double wavelength, const sfd_grid* holo_gr
         const auto it = g_tuned.find(std::make_tuple(col, L, sig));
         if (it != g_tuned.end()) (col ? P->gcol : P->grow)[L] = it->second;
       }
+    const auto il = g_tuned.find(std::make_tuple(3, 0, sig));
+    if (il != g_tuned.end() && (il->second != 0) != P->smooth) {
+      set_lengths(P, il->second != 0);
+      P->persist_ok = persist_eligible(P);
+      P->persist = P->persist_ok;
+    }
+    const auto it = g_tuned.find(std::make_tuple(2, 0, sig));
+    if (it != g_tuned.end()) P->persist = P->persist_ok && it->second != 0;
   }
   apply_schedule(P);
   *plan = P;
@@ -1169,23 +1376,44 @@ sfd_status sfd_reconstruct(sfd_plan_t plan, const void* holo, const double* z_or
   if ((st = check_z(plan, z_or_null)) != SFD_OK) return st;
 
   char* ws = static_cast<char*>(workspace);
+  // SFD_REUSE_TABLES: this call needs no tables or spectra when the
+  // workspace holds those of the same distances.
+  bool tables = true;
+  if ((plan->flags & SFD_REUSE_TABLES) && !(plan->flags & SFD_PER_VIEW_LAUNCH)) {
+    std::vector<double> zz(V);
+    for (int v = 0; v < V; ++v) zz[v] = z_or_null ? z_or_null[v] : plan->views[v].z;
+    tables = !(plan->tables_ws == ws && plan->tables_z == zz);
+    plan->tables_ws = nullptr;  // set again once this call's launches are enqueued
+    plan->tables_z = std::move(zz);
+  }
   CallDescs D;
   if ((st = build_descs(plan, holo, z_or_null, out, ws, &D)) != SFD_OK) return st;
   std::vector<unsigned char> img;
-  size_t off_axis, off_tw, off_rows;
-  pack_descs(plan, D, &img, &off_axis, &off_tw, &off_rows);
+  size_t off_axis, off_tw, off_rows, off_tiles;
+  pack_descs(plan, D, &img, &off_axis, &off_tw, &off_rows, &off_tiles);
+  if (plan->persist) {
+    if (plan->persist_grid <= 0) {
+      plan->persist_grid = sfd::persist_resident_blocks();
+      if (plan->persist_grid <= 0) return fail(SFD_ERR_HIP, "occupancy query of the persistent kernel failed");
+    }
+    pack_persist(plan, &D, ws, tables, &img, off_axis, off_tiles, off_rows);
+  }
   if ((st = upload(plan, 0, img, ws, plan->desc_off, stream)) != SFD_OK) return st;
   const auto* d_axis = reinterpret_cast<const sfd::AxisJob*>(ws + plan->desc_off + off_axis);
   const auto* d_tw = reinterpret_cast<const sfd::TwiddleJob*>(ws + plan->desc_off + off_tw);
   const auto* d_rows = reinterpret_cast<const sfd::RowJob*>(ws + plan->desc_off + off_rows);
-  const auto* d_tiles = reinterpret_cast<const sfd::TileJob*>(
-      ws + plan->desc_off + off_tw + align_up(sizeof(sfd::TwiddleJob) * 2 * plan->lengths.size()));
+  const auto* d_tiles = reinterpret_cast<const sfd::TileJob*>(ws + plan->desc_off + off_tiles);
 
   // The twiddle tables depend only on the transform shapes: built once per
-  // workspace (which stays dedicated to the plan).
+  // workspace (which stays dedicated to the plan).  The persistent launch's
+  // counters are zeroed once per workspace; every launch leaves them zero.
   if (plan->tw_ready_ws != ws) {
     if ((st = launch_setup_for(plan, D, ws, d_axis, d_tw, d_tiles, 0, 0, true, 0, 0, stream)) != SFD_OK) return st;
     plan->tw_ready_ws = ws;
+  }
+  if (plan->persist_ok && plan->sync_ready_ws != ws) {
+    SFD_HIP_TRY(sfd::launch_zero(reinterpret_cast<uint32_t*>(ws + plan->sync_off), plan->sync_words, stream));
+    plan->sync_ready_ws = ws;
   }
   if (plan->flags & SFD_PER_VIEW_LAUNCH) {
     // Baseline: every stage launched for one view at a time (axis jobs stay
@@ -1200,16 +1428,6 @@ sfd_status sfd_reconstruct(sfd_plan_t plan, const void* holo, const double* z_or
         return st;
     }
     return SFD_OK;
-  }
-  // SFD_REUSE_TABLES: this call needs no tables or spectra when the
-  // workspace holds those of the same distances.
-  bool tables = true;
-  if (plan->flags & SFD_REUSE_TABLES) {
-    std::vector<double> zz(V);
-    for (int v = 0; v < V; ++v) zz[v] = z_or_null ? z_or_null[v] : plan->views[v].z;
-    tables = !(plan->tables_ws == ws && plan->tables_z == zz);
-    plan->tables_ws = nullptr;  // set again once this call's launches are enqueued
-    plan->tables_z = std::move(zz);
   }
   const bool use_graph = !(plan->flags & SFD_EAGER) && !plan->profiling;
   if (use_graph) {
@@ -1304,6 +1522,9 @@ sfd_status sfd_autotune(sfd_plan_t plan, const void* holo, void* const* out, voi
     SFD_HIP_TRY(hipEventElapsedTime(ms, e0, e1));
     return SFD_OK;
   };
+  // Tile widths are tuned on the passes' schedule.
+  const bool was_persist = plan->persist;
+  if (was_persist && (st = sfd_set_launch(plan, SFD_LAUNCH_PASSES)) != SFD_OK) return st;
   std::vector<std::pair<int, int>> passes;  // (col, L)
   for (const ViewLayout& v : plan->lay) {
     passes.push_back({1, v.ly});
@@ -1340,6 +1561,43 @@ sfd_status sfd_autotune(sfd_plan_t plan, const void* holo, void* const* out, voi
     apply_schedule(plan);
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tuned[std::make_tuple(col, L, plan->shape_sig)] = best;
+  }
+  if (was_persist || plan->persist_ok) {
+    // The passes' schedule is tuned; keep the faster of it and the
+    // persistent launch.
+    float t_pass = 0.f, t_persist = 0.f;
+    if ((st = timed(&t_pass)) != SFD_OK) return st;
+    if ((st = sfd_set_launch(plan, SFD_LAUNCH_PERSISTENT)) != SFD_OK) return st;
+    if ((st = timed(&t_persist)) != SFD_OK) return st;
+    const bool keep = t_persist <= t_pass;
+    if (!keep && (st = sfd_set_launch(plan, SFD_LAUNCH_PASSES)) != SFD_OK) return st;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[std::make_tuple(2, 0, plan->shape_sig)] = keep ? 1 : 0;
+  }
+  // Radix choice: the other length policy (powers of two only, or the
+  // smooth lengths with their radix-3, -5 and -7 closing stages) where it
+  // gives other lengths, on its default tile widths and, where available,
+  // the persistent launch; the faster policy is kept.
+  bool differ = false;
+  for (size_t v = 0; v < plan->views.size(); ++v) {
+    const sfd_grid& o = plan->views[v].out;
+    differ = differ || choose_length(plan->holo.nx, o.nx, true) != choose_length(plan->holo.nx, o.nx, false) ||
+             choose_length(plan->holo.ny, o.ny, true) != choose_length(plan->holo.ny, o.ny, false);
+  }
+  if (differ) {
+    float t_cur = 0.f, t_other = 0.f;
+    if ((st = timed(&t_cur)) != SFD_OK) return st;
+    const bool cur_smooth = plan->smooth, cur_persist = plan->persist;
+    if ((st = sfd_set_length_policy(plan, cur_smooth ? 0 : 1)) != SFD_OK) return st;
+    if (plan->persist_ok && (st = sfd_set_launch(plan, SFD_LAUNCH_PERSISTENT)) != SFD_OK) return st;
+    if ((st = timed(&t_other)) != SFD_OK) return st;
+    if (t_cur <= t_other) {
+      if ((st = sfd_set_length_policy(plan, cur_smooth ? 1 : 0)) != SFD_OK) return st;
+      if ((st = sfd_set_launch(plan, cur_persist ? SFD_LAUNCH_PERSISTENT : SFD_LAUNCH_PASSES)) != SFD_OK) return st;
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[std::make_tuple(3, 0, plan->shape_sig)] = plan->smooth ? 1 : 0;
+    g_tuned[std::make_tuple(2, 0, plan->shape_sig)] = plan->persist ? 1 : 0;
   }
   return SFD_OK;
 }
@@ -1380,6 +1638,68 @@ sfd_status sfd_set_schedule(sfd_plan_t plan, int32_t L, int32_t col, int32_t til
                                          std::to_string(tile_width) + " at length " + std::to_string(L));
   (col ? plan->gcol : plan->grow)[L] = tile_width;
   apply_schedule(plan);
+  return SFD_OK;
+}
+
+sfd_status sfd_set_launch(sfd_plan_t plan, int32_t mode) {
+  g_err.clear();
+  if (!plan) return fail(SFD_ERR_INVALID_ARG, "plan is NULL");
+  if (mode != SFD_LAUNCH_PASSES && mode != SFD_LAUNCH_PERSISTENT)
+    return fail(SFD_ERR_INVALID_ARG, "unknown launch mode " + std::to_string(mode));
+  if (mode == SFD_LAUNCH_PERSISTENT && !plan->persist_ok)
+    return fail(SFD_ERR_UNSUPPORTED, "the persistent launch is not available for this plan's shapes");
+  const bool want = mode == SFD_LAUNCH_PERSISTENT;
+  if (want != plan->persist) {
+    plan->persist = want;
+    plan->drop_graph();
+    plan->last_desc[0].clear();  // the descriptor layout differs: upload on the next call
+  }
+  return SFD_OK;
+}
+
+sfd_status sfd_set_length_policy(sfd_plan_t plan, int32_t smooth) {
+  g_err.clear();
+  if (!plan) return fail(SFD_ERR_INVALID_ARG, "plan is NULL");
+  const bool want = smooth != 0;
+  if (want == plan->smooth) return SFD_OK;
+  const bool was_persist = plan->persist;
+  set_lengths(plan, want);
+  plan->persist_ok = persist_eligible(plan);
+  plan->persist = was_persist && plan->persist_ok;
+  plan->tables_ws = nullptr;     // spectra of other lengths
+  plan->last_desc[0].clear();
+  apply_schedule(plan);          // also drops the recorded graphs
+  return SFD_OK;
+}
+
+sfd_status sfd_length_policy(sfd_plan_t plan, int32_t* smooth) {
+  g_err.clear();
+  if (!plan || !smooth) return fail(SFD_ERR_INVALID_ARG, "NULL argument");
+  *smooth = plan->smooth ? 1 : 0;
+  return SFD_OK;
+}
+
+sfd_status sfd_launch_mode(sfd_plan_t plan, int32_t* mode, int32_t* persistent_available) {
+  g_err.clear();
+  if (!plan || !mode) return fail(SFD_ERR_INVALID_ARG, "NULL argument");
+  *mode = plan->persist ? SFD_LAUNCH_PERSISTENT : SFD_LAUNCH_PASSES;
+  if (persistent_available) *persistent_available = plan->persist_ok ? 1 : 0;
+  return SFD_OK;
+}
+
+sfd_status sfd_sync_faults(sfd_plan_t plan, void* workspace, size_t ws_bytes, int32_t clear, uint32_t* faults,
+                           hipStream_t stream) {
+  g_err.clear();
+  sfd_status st = check_common(plan, workspace, ws_bytes);
+  if (st != SFD_OK) return st;
+  if (!faults) return fail(SFD_ERR_INVALID_ARG, "faults is NULL");
+  *faults = 0;
+  if (!plan->persist_ok || plan->sync_ready_ws != workspace) return SFD_OK;
+  uint32_t* w = reinterpret_cast<uint32_t*>(static_cast<char*>(workspace) + plan->sync_off) +
+                sfd::kSyncErr * sfd::kSyncStride;
+  SFD_HIP_TRY(hipMemcpyAsync(faults, w, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
+  SFD_HIP_TRY(hipStreamSynchronize(stream));
+  if (clear && *faults) SFD_HIP_TRY(sfd::launch_zero(w, 1, stream));
   return SFD_OK;
 }
 

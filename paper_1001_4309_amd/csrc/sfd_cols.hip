@@ -1,0 +1,29 @@
+// Column pass kernels (the y transforms, see col_body) and their launcher.
+#include "sfd_device.h"
+
+namespace sfd {
+
+template <int L, int GC, int VAR, int P>
+__global__ void __launch_bounds__((PassShape<L, GC, P>::THREADS)) __attribute__((amdgpu_waves_per_eu(SFD_COL_WPE))) col_kernel(const PassArgs args, const float2* __restrict__ tw) {
+  __shared__ __align__(16) unsigned char lds[ColLds<L, GC, VAR, P>::bytes];
+  col_body<L, GC, VAR, P>(args, tw, xcd_tile(blockIdx.x, args.total_tiles), lds, (int)threadIdx.x);
+}
+
+hipError_t launch_col_pass(int L, int G, int var, const PassArgs& a, const float2* tw, hipStream_t s) {
+#define SFD_LAUNCH_V(l, g, p, v) \
+  hipLaunchKernelGGL((col_kernel<l, g, v, p>), dim3(a.total_tiles), dim3(PassShape<l, g, p>::THREADS), 0, s, a, tw)
+#define SFD_LAUNCH_COL(l, g, p)                   \
+  if (L == l && G == g) {                         \
+    if (var == 3) SFD_LAUNCH_V(l, g, p, 3);       \
+    else if (var == 2) SFD_LAUNCH_V(l, g, p, 2);  \
+    else if (var == 1) SFD_LAUNCH_V(l, g, p, 1);  \
+    else SFD_LAUNCH_V(l, g, p, 0);                \
+    return hipGetLastError();                     \
+  }
+  SFD_COL_SHAPES(SFD_LAUNCH_COL)
+#undef SFD_LAUNCH_COL
+#undef SFD_LAUNCH_V
+  return hipErrorInvalidValue;
+}
+
+}  // namespace sfd

@@ -59,6 +59,8 @@ struct RowJob {
   int32_t n_rows, n_in, n_out;
   int64_t in_ld, out_ld;
   int32_t mode;        // kInReal | kOutIntensity | kOutField | kUsePost | kReduce ...
+  int32_t view;        // the view the job belongs to (persistent launches)
+  int32_t copy;        // column pass: the hologram copy it reads (persistent launches)
   int32_t pad_;
 
   // Epilogue reductions (row kernel, kReduce): over the row's outputs V(m),
@@ -171,6 +173,62 @@ struct SetupArgs {
 };
 constexpr int kSetupThreads = 256;
 
+// Persistent launch: every stage of a batch in one launch.  Workgroups take
+// items from a ticket counter in the order of the segments below (each item
+// depends only on items with smaller tickets, so the launch cannot deadlock
+// whatever number of its workgroups are resident):
+//   kItemSetup  one per view: its kernel spectra Hx, Hy (half of the
+//               workgroup each) and its pre/post chirp tables;
+//   kItemStrip  kStripW columns of a hologram rewritten column-major (the
+//               copy the column pass reads, see TileJob);
+//   kItemCol    a column-pass tile; waits for its view's setup item and the
+//               strip holding its columns;
+//   kItemRow    a row-pass tile; waits for every column tile of its view.
+// Completion counters live in the workspace (PersistSync).  The last
+// workgroup to leave resets them to zero, so every launch, and every replay
+// of a graph holding it, starts from zero without a memset.
+enum : int32_t { kItemSetup = 0, kItemStrip = 1, kItemCol = 2, kItemRow = 3 };
+constexpr int kMaxSegments = 16;
+constexpr int kStripW = 16;           // columns per strip item: one column tile of the persistent shapes
+constexpr int kPersistThreads = 512;  // workgroup size of the persistent launch
+struct Segment {
+  int32_t kind;
+  int32_t first;         // first ticket of the segment
+  int32_t count;         // items
+  int32_t L;             // col/row: transform length
+  int32_t var;           // col/row: kernel specialisation (as launch_pass)
+  int32_t pad_;
+  const PassArgs* args;  // col/row: the pass arguments of the segment's jobs
+  const float2* tw;      // col/row: twiddle table of the passes' shape of L
+};
+struct PersistArgs {
+  Segment seg[kMaxSegments];
+  int32_t nseg;
+  int32_t total;          // items over all segments
+  int32_t grid;           // workgroups of the launch
+  int32_t nview;
+  int32_t wait_setup;     // column tiles wait for their view's setup item (0 when tables are kept)
+  int32_t ncopy;
+  int32_t nstrips;        // strip items (all copies)
+  int32_t pad_;
+  const AxisJob* axis;    // 2 per view: x, then y
+  const TileJob* tiles;   // per hologram copy
+  const int32_t* col_tiles;    // per view: column tiles (the row tiles' target)
+  const float2* const* tw_view;  // per view: twiddle tables of the kernel-spectrum shape of Lx, Ly
+  uint32_t* sync;         // counters, see persist_sync_words
+};
+// Counter layout, one counter per kSyncStride words (its own 256-byte line:
+// a counter that workgroups poll shares no line with one they advance):
+// [0] ticket, [1] workgroups that left, [2] error word (set when a
+// dependency wait gave up; never reset by the kernel), then per view its
+// setup and column-tile counters, then one counter per strip item.
+constexpr int kSyncStride = 64;
+constexpr int kSyncTicket = 0, kSyncExit = 1, kSyncErr = 2, kSyncHead = 3;
+__host__ __device__ inline int persist_sync_counters(int nview, int nstrips) { return kSyncHead + 2 * nview + nstrips; }
+__host__ __device__ inline int persist_sync_words(int nview, int nstrips) {
+  return kSyncStride * persist_sync_counters(nview, nstrips);
+}
+
 // Host-side launchers (defined in sfd_kernels.hip).
 hipError_t launch_setup(const SetupArgs& args, hipStream_t s);
 // Axis jobs one spectrum workgroup handles at a transform length.
@@ -178,14 +236,24 @@ int spectra_per_block(int L);
 
 // col = true: the y transforms (column kernel); false: the x transforms.
 // G is the tile width (transforms per workgroup): one of
-// pass_tile_widths(L, col).  var selects a
-// specialised kernel.  Row pass: 1 when every job has n_in == L/2,
-// n_out <= L/2, a complex input and no kReduce; 2 when, in addition, no job
-// applies a post-chirp and every job writes intensities only.  Column pass:
-// 1 when every job has n_in == L/2, n_out <= L/2 and a complex input; 2 when
-// every job has n_in == L/2, n_out <= L/2, a real input and no post-chirp;
-// 3 as 2 with post-chirps allowed.  0 otherwise.
+// pass_tile_widths(L, col).  var selects a specialised kernel; with
+// F = fast_input(L):  row pass: 1 when every job has n_in == F, n_out <= F,
+// a complex input and no kReduce; 2 when, in addition, no job applies a
+// post-chirp and every job writes intensities only.  Column pass: 1 when
+// every job has n_in == F, n_out <= F and a complex input; 2 when every job
+// has n_in == F, n_out <= F, a real input and no post-chirp; 3 as 2 with
+// post-chirps allowed.  0 otherwise.
 hipError_t launch_pass(int L, bool col, int G, int var, const PassArgs& args, const float2* tw, hipStream_t s);
+
+// Persistent launch (see PersistArgs): pa is a device copy; grid workgroups.
+hipError_t launch_persist(const PersistArgs* pa, int grid, hipStream_t s);
+// Zero n counters (the first launch on a workspace).
+hipError_t launch_zero(uint32_t* p, int n, hipStream_t s);
+// Lengths the persistent launch supports (the passes' shape of a row in one
+// wavefront, with two transforms per slot).
+bool persist_length(int L);
+// Workgroups of the persistent launch resident at once on this device.
+int persist_resident_blocks();
 
 hipError_t launch_gradz(const GradZJob* d_jobs, int njobs, hipStream_t s);
 hipError_t launch_gather(const GatherJob* d_jobs, int njobs, int max_n, hipStream_t s);
@@ -197,6 +265,9 @@ int pass_tile_widths(int L, bool col, int* widths, int cap, int* per_slot = null
 // The default tile width of a pass at length L (0 if L is unsupported).
 int rows_per_tile(int L, bool col);
 bool supported_length(int L);
+// Input length of the specialised pass kernels at length L: L / 2 at powers
+// of two, 1024 at the smooth lengths 1280, 1536 and 1792 (see FastIn).
+int fast_input(int L);
 // Entries of the twiddle table of the passes' (spec = false) or the kernel
 // spectrum's (spec = true) transform shape of length L.
 int twiddle_len(int L, bool spec);

@@ -1,0 +1,139 @@
+"""Smooth padded lengths (Section 2.2, steps 2 and 9: any L >= N0 + N1 - 1 is
+exact) on the GPU against the FP64 oracle.
+
+A 1024-sample hologram axis meeting a view of 256, 512 or 768 samples needs
+L >= 1279, 1535 or 1791; the library then uses 1280 = 2^8 5, 1536 = 2^9 3 or
+1792 = 2^8 7 (radix-4/8 stages closed by a radix-20, -24 or -28 stage)
+instead of 2048.  Covered: the specialised kernels (1024-sample inputs) in
+the persistent launch and in the pass schedule (bit for bit equal), the
+general kernels (other input sizes), the adjoint and dL/dz at smooth
+lengths, and the power-of-two policy of the same plan.  Bar: relative L2
+<= 1e-4 and max |error| / max |oracle| <= 1e-5 per view (1e-4 for the
+gradient, as in the backward tests).
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from tests.helpers import TOL, check, ogrid, oracle_field
+
+pytestmark = pytest.mark.gpu
+
+sfd = pytest.importorskip("paper_1001_4309_amd")
+DEV = "cuda:0"
+LAM = workloads.WAVELENGTH
+
+
+def _holo(w):
+    return torch.from_numpy(np.ascontiguousarray(w.holograms)).to(DEV)
+
+
+def _smooth_workload():
+    """One 1024^2 Gabor-like hologram, views of 256, 512, 768 and 1024
+    samples (padded lengths 1280, 1536, 1792, 2048), shifted and rescaled."""
+    r = np.random.default_rng(31)
+    g0 = workloads.GridSpec(1024, 1024, 4.65e-6, 4.65e-6)
+    holo = r.uniform(0, 2, (1, 1024, 1024)).astype(np.float32)
+    views = []
+    for k, n1 in enumerate((256, 512, 768, 1024)):
+        p1 = float(np.exp(r.uniform(np.log(1e-6), np.log(10e-6))))
+        ox, oy = (float(v) for v in r.uniform(-1e-3, 1e-3, 2))
+        views.append(workloads.ViewSpec(workloads.GridSpec(n1, n1, p1, p1, ox, oy), 0.02 + 0.025 * k, 0))
+    return workloads.Workload("smooth", LAM, g0, holo, views)
+
+
+def test_smooth_lengths_specialised_kernels():
+    w = _smooth_workload()
+    p = sfd.Plan(w.wavelength, w.holo_grid, 1, w.views, outputs="both", device=DEV)
+    assert p.length_policy() == "smooth"
+    assert [p.lengths(v) for v in range(4)] == [(1280, 1280), (1536, 1536), (1792, 1792), (2048, 2048)]
+    holo = _holo(w)
+    p.set_launch(True)
+    a = [t.clone() for t in p.reconstruct(holo)]
+    torch.cuda.synchronize()
+    assert p.sync_faults() == 0
+    p.set_launch(False)
+    b = p.reconstruct(holo)
+    torch.cuda.synchronize()
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    nv = len(w.views)
+    for v in range(nv):
+        ref = oracle_field(w, v)
+        L = p.lengths(v)[0]
+        check(a[v].cpu().numpy(), oracle.intensity(ref), f"L={L} view {v} intensity")
+        check(a[nv + v].cpu().numpy(), ref, f"L={L} view {v} field")
+    # The same plan on powers of two only: every view at 2048, same workspace.
+    p.set_lengths(False)
+    assert p.length_policy() == "pow2"
+    assert all(p.lengths(v) == (2048, 2048) for v in range(nv))
+    c = p.reconstruct(holo)
+    torch.cuda.synchronize()
+    for v in range(nv):
+        check(c[nv + v].cpu().numpy(), oracle_field(w, v), f"pow2 policy view {v} field")
+
+
+@pytest.mark.parametrize("shape", [(1000, 900, 260, 380), (1000, 900, 300, 500), (1000, 900, 700, 880),
+                                   (1024, 1000, 500, 256)])
+def test_smooth_lengths_general_kernels(shape):
+    """Inputs other than 1024 samples: the general kernels at smooth lengths
+    (ragged tiles, rectangular grids, shifts on both planes)."""
+    n0x, n0y, n1x, n1y = shape
+    r = np.random.default_rng(n0x + 7 * n1x + 13 * n1y)
+    g0 = workloads.GridSpec(n0x, n0y, 4.65e-6, 3.9e-6, 25e-6, -15e-6)
+    g1 = workloads.GridSpec(n1x, n1y, 3.5e-6, 5.5e-6, -140e-6, 90e-6)
+    holo = r.uniform(0, 2, (1, n0y, n0x)).astype(np.float32)
+    w = workloads.Workload("general", LAM, g0, holo, [workloads.ViewSpec(g1, 0.03, 0),
+                                                      workloads.ViewSpec(g1, -0.045, 0)])
+    p = sfd.Plan(w.wavelength, g0, 1, w.views, outputs="both", device=DEV)
+    lx, ly = p.lengths(0)
+    assert lx in (1280, 1536, 1792) or ly in (1280, 1536, 1792), (lx, ly)
+    res = p.reconstruct(_holo(w))
+    torch.cuda.synchronize()
+    for v in range(2):
+        ref = oracle_field(w, v)
+        check(res[v].cpu().numpy(), oracle.intensity(ref), f"{shape} L=({lx},{ly}) view {v} intensity")
+        check(res[2 + v].cpu().numpy(), ref, f"{shape} L=({lx},{ly}) view {v} field")
+
+
+def test_smooth_lengths_backward():
+    """Adjoint and dL/dz of an intensity loss with padded lengths 1280 and
+    1536 (a 600 x 700 complex field onto a 500 x 600 view)."""
+    r = np.random.default_rng(8)
+    g0 = workloads.GridSpec(600, 700, 4.65e-6, 4.65e-6, 10e-6, 20e-6)
+    g1 = workloads.GridSpec(500, 600, 3.0e-6, 3.5e-6, -60e-6, 40e-6)
+    u0 = np.exp(1j * r.uniform(0, 2 * np.pi, (1, 700, 600))).astype(np.complex64)
+    z = 0.025
+    w = workloads.Workload("bwd-smooth", LAM, g0, u0, [workloads.ViewSpec(g1, z, 0)])
+    p = sfd.Plan(LAM, g0, 1, w.views, outputs="both", complex_input=True, device=DEV)
+    assert p.lengths(0) == (1280, 1536)
+    holo = _holo(w)
+    res = p.reconstruct(holo)
+    src, dst = ogrid(g0), ogrid(g1)
+    u1 = oracle.direct(u0[0], src, dst, LAM, z)
+    target = (np.abs(u1) ** 2 * 0.9).astype(np.float32)
+    gi = 2.0 * (res[0] - torch.from_numpy(target).to(DEV))
+    grad_in, gz = p.backward([gi], holo, field_out=[res[1]])
+    torch.cuda.synchronize()
+    ref_gu, ref_gz = oracle.grads(u0[0], src, dst, LAM, z, 2.0 * (np.abs(u1) ** 2 - target))
+    check(grad_in[0].cpu().numpy(), ref_gu, "smooth-length field gradient", elem_tol=TOL)
+    ez = abs(float(gz[0]) - ref_gz) / abs(ref_gz)
+    print(f"smooth-length dL/dz {float(gz[0]):.6e} oracle {ref_gz:.6e} rel {ez:.2e}", flush=True)
+    assert ez <= TOL
+
+
+def test_autotune_picks_a_length_policy():
+    w = _smooth_workload()
+    holo = _holo(w)
+    p = sfd.Plan(w.wavelength, w.holo_grid, 1, w.views, device=DEV)
+    p.autotune(holo, reps=3)
+    print("tuned:", p.length_policy(), p.launch_mode(), flush=True)
+    got = p.reconstruct(holo)
+    torch.cuda.synchronize()
+    for v in range(len(w.views)):
+        check(got[v].cpu().numpy(), oracle.intensity(oracle_field(w, v)), f"tuned view {v} intensity")
+    q = sfd.Plan(w.wavelength, w.holo_grid, 1, w.views, device=DEV)
+    assert q.length_policy() == p.length_policy() and q.launch_mode() == p.launch_mode()

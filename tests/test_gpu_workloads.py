@@ -59,11 +59,14 @@ def test_config3_batched_uneven_views():
     w = workloads.config3()
     assert len(w.views) == 64 and len(w.holograms) == 8
     holo = _holo(w)
-    a = sfd.Plan(w.wavelength, w.holo_grid, 8, w.views, device=DEV).reconstruct(holo)
+    pa = sfd.Plan(w.wavelength, w.holo_grid, 8, w.views, device=DEV)
+    pa.set_launch(True)
+    a = pa.reconstruct(holo)
     b = sfd.Plan(w.wavelength, w.holo_grid, 8, w.views, device=DEV, per_view_launch=True).reconstruct(holo)
     torch.cuda.synchronize()
     for x, y in zip(a, b):
         assert torch.equal(x, y)
+    assert pa.sync_faults() == 0
     worst = (0.0, 0.0)
     for v, view in enumerate(w.views):
         e = check(a[v].cpu().numpy(), oracle.intensity(oracle_field(w, v)),
