@@ -94,13 +94,17 @@ def pass_variant(w, plan, kind: str) -> int:
     complex input), 2 (the same with a real input and no post-chirp), 3 (real
     input with post-chirp) or 0."""
     g = w.holo_grid
+
+    def fast_input(L):  # the library's fast_input: half the row at powers of two, else 1024
+        return L // 2 if (L & (L - 1)) == 0 else 1024
+
     fast = True
     for v, view in enumerate(w.views):
         lx, ly = plan.lengths(v)
         if kind == "pass_x":
-            fast = fast and 2 * g.nx == lx and 2 * view.grid.nx <= lx
+            fast = fast and g.nx == fast_input(lx) and view.grid.nx <= fast_input(lx)
         else:
-            fast = fast and 2 * g.ny == ly and 2 * view.grid.ny <= ly
+            fast = fast and g.ny == fast_input(ly) and view.grid.ny <= fast_input(ly)
     if not fast:
         return 0
     if kind == "pass_x":
@@ -183,36 +187,58 @@ def summarize_pmc(fetch_dir: str, write_dir: str, config: int, copy_mib: int, co
     print("\n".join(lines))
 
 
+def cpu_info():
+    """Host cores this process may use and the CPU model."""
+    cores = len(os.sched_getaffinity(0))
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return cores, model
+
+
 def cpu_baseline(w, seconds: float):
+    """The FP64 oracle as it stands, timed on the host cores (BLAS threads set
+    to the cores this process may use): the separable direct sum over all
+    views until ``seconds`` have passed, then the paper-literal FFT path
+    (steps 2-10 on the padded 2D grid) over all views once."""
     import numpy as np
     import threadpoolctl
 
     import oracle
     from tests.helpers import ogrid
 
-    info = threadpoolctl.threadpool_info()
-    cores = max([i.get("num_threads", 1) for i in info if i.get("user_api") == "blas"] or [1])
-    src = ogrid(w.holo_grid)
-    n = 0
-    t0 = time.perf_counter()
-    while True:
+    cores, model = cpu_info()
+    with threadpoolctl.threadpool_limits(limits=cores):
+        info = threadpoolctl.threadpool_info()
+        blas = max([i.get("num_threads", 1) for i in info if i.get("user_api") == "blas"] or [1])
+        src = ogrid(w.holo_grid)
+        n = 0
+        t0 = time.perf_counter()
+        while True:
+            for view in w.views:
+                u = oracle.direct(w.holograms[view.holo], src, ogrid(view.grid), w.wavelength, view.z)
+                _ = np.abs(u) ** 2
+                n += 1
+            if time.perf_counter() - t0 >= seconds:
+                break
+        dt = time.perf_counter() - t0
+        t1 = time.perf_counter()
         for view in w.views:
-            u = oracle.direct(w.holograms[view.holo], src, ogrid(view.grid), w.wavelength, view.z)
-            _ = np.abs(u) ** 2
-            n += 1
-        if time.perf_counter() - t0 >= seconds:
-            break
-    dt = time.perf_counter() - t0
-    # The paper-literal FFT path (steps 2-10 on the padded 2D grid), one view.
-    view = w.views[0]
-    t1 = time.perf_counter()
-    oracle.fft_path(w.holograms[view.holo], src, ogrid(view.grid), w.wavelength, view.z)
-    dt_fft = time.perf_counter() - t1
+            oracle.fft_path(w.holograms[view.holo], src, ogrid(view.grid), w.wavelength, view.z)
+        dt_fft = time.perf_counter() - t1
+    nv = len(w.views)
     return {"value": n / dt, "unit": "views/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"{n} views ({n // len(w.views)} passes over the {len(w.views)} views of the workload), "
+            "cpu_model": model, "blas_threads": int(blas),
+            "sample": f"{n} views ({n // nv} passes over the {nv} views of the workload), "
                       f"FP64 separable direct sum (zgemm) plus |u|^2, {dt:.1f} s",
-            "fft_path_views_per_s": 1.0 / dt_fft,
-            "fft_path_sample": f"1 view through the FP64 steps 2-10 on the padded 2D grid, {dt_fft:.2f} s"}
+            "fft_path_views_per_s": nv / dt_fft,
+            "fft_path_sample": f"all {nv} views through the FP64 steps 2-10 on the padded 2D grid "
+                               f"(numpy FFT, one thread), {dt_fft:.2f} s"}
 
 
 def bench_backward(dev, steps: int, warmup: int):
@@ -259,6 +285,8 @@ def bench_backward(dev, steps: int, warmup: int):
 
 
 def time_steps(plan, holo, outs, steps: int) -> float:
+    """Seconds per step over exactly ``steps`` calls, bracketed by device
+    synchronisations (the contract's timed region)."""
     import torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -266,6 +294,151 @@ def time_steps(plan, holo, outs, steps: int) -> float:
         plan.reconstruct(holo, outs=outs)
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / steps
+
+
+def event_stats(plan, holo, outs, n: int):
+    """Per-call durations from HIP events recorded around each call on the
+    stream the library launches on (torch's current stream): median, p10 and
+    p90 over n calls."""
+    import torch
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record()
+        plan.reconstruct(holo, outs=outs)
+        b.record()
+    torch.cuda.synchronize()
+    t = sorted(a.elapsed_time(b) * 1e3 for a, b in ev)
+    return {"calls": n, "median_us": t[n // 2], "p10_us": t[n // 10], "p90_us": t[(9 * n) // 10],
+            "how": "hipEvent pair around each call (graph replay) on the launch stream"}
+
+
+def counters_file(config: int) -> str:
+    return os.path.join(ROOT, "profiles", f"valu_counters_config{config}.txt")
+
+
+def read_counters(config: int, name: str):
+    """VALU and LDS counter figures of kernel ``name`` from the committed
+    summary (see profiles/), or None when absent or stale."""
+    path = counters_file(config)
+    if not os.path.exists(path):
+        return None
+    fields, kernels = {}, {}
+    for line in open(path):
+        line = line.strip()
+        if line.startswith("kernel:"):
+            k, _, rest = line[len("kernel:"):].partition("|")
+            kernels[k.strip()] = {a: float(b) for a, b in (kv.split("=") for kv in rest.split())}
+        elif ":" in line and not line.startswith("#"):
+            a, _, b = line.partition(":")
+            fields[a.strip()] = b.strip()
+    if fields.get("source-sha256") != kernel_source_hash() or name not in kernels:
+        return None
+    return kernels[name]
+
+
+def measure(w, dev, args, steps: int, warmup: int, config: int, tune: bool = True, schedule: str = ""):
+    """One workload: plan, schedule (autotuned unless told otherwise), the
+    contract's timed steps, per-call event statistics, and the kernels'
+    event-measured durations with the dominant kernel's roofline."""
+    import numpy as np
+    import torch
+
+    import paper_1001_4309_amd as sfd
+
+    holo = torch.from_numpy(np.ascontiguousarray(w.holograms)).to(dev)
+    plan = sfd.Plan(w.wavelength, w.holo_grid, len(w.holograms), w.views, device=dev)
+    outs = plan.new_outputs()
+    nv = len(w.views)
+    if schedule:
+        for item in schedule.split(","):
+            key, g = item.split("=")
+            if key == "launch":
+                plan.set_launch(g == "persistent")
+            elif key == "lengths":
+                plan.set_lengths(g == "smooth")
+            else:
+                plan.set_schedule(int(key[3:]), key.startswith("col"), int(g))
+    elif tune:
+        plan.autotune(holo, reps=10, outs=outs)
+    sched = {f"{k[0]}{k[1]}": g for k, g in sorted(plan.schedule().items())}
+    mode = plan.launch_mode()[0]
+    log(f"{w.name}: launch {mode}, lengths {plan.length_policy()}, tile widths {sched}")
+    for _ in range(warmup):
+        plan.reconstruct(holo, outs=outs)
+    sec = time_steps(plan, holo, outs, steps)
+    stats = event_stats(plan, holo, outs, max(100, steps))
+    log(f"{w.name}: {sec * 1e6:.1f} us/step over {steps} steps, {nv / sec:.0f} views/s; per call median "
+        f"{stats['median_us']:.1f} us (p10 {stats['p10_us']:.1f}, p90 {stats['p90_us']:.1f})")
+
+    prof_steps = max(1, min(steps, 100))
+    plan.profile(True)
+    for _ in range(prof_steps):
+        plan.reconstruct(holo, outs=outs)
+    torch.cuda.synchronize()
+    rep = plan.profile_report()
+    plan.profile(False)
+    costs = pass_costs(w, plan)
+    costs["persist"] = [costs["pass_x"][0] + costs["pass_y"][0], costs["pass_x"][1] + costs["pass_y"][1]]
+    kern = {k: {"launches": n, "avg_us": (ms / n * 1e3) if n else 0.0} for k, (n, ms) in rep.items() if n}
+    if rep.get("persist", (0, 0.0))[0] > 0:
+        dom = "persist"  # one launch per step holds every pass
+    else:
+        dom = max(("pass_x", "pass_y"), key=lambda k: rep[k][1])
+    n_launch, tot_ms = rep[dom]
+    avg_s = tot_ms / n_launch / 1e3
+    per_step = n_launch / prof_steps
+    flops, nbytes = costs[dom][1] / per_step, costs[dom][0] / per_step
+    if dom == "persist":
+        dom_name = "persist_kernel"
+    else:
+        lx0, ly0 = plan.lengths(0)
+        dom_L = lx0 if dom == "pass_x" else ly0
+        dom_name = kernel_name(dom, dom_L, plan.schedule()[("row" if dom == "pass_x" else "col", dom_L)],
+                               pass_variant(w, plan, dom))
+    alu = flops / avg_s / 1e12
+    hbm = nbytes / avg_s / 1e9
+    frac_alu, frac_hbm = alu / FP32_VECTOR_PEAK_TFLOPS, hbm / HBM_PEAK_GBPS
+    # The bound: the roofline the kernel's algorithmic work sits closer to
+    # (its flop/byte ratio against the ridge of the two peaks).
+    bound = "alu" if flops / nbytes > FP32_VECTOR_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBPS * 1e9) else "hbm"
+    roofline = {"bound": bound,
+                "achieved": alu if bound == "alu" else hbm,
+                "peak": FP32_VECTOR_PEAK_TFLOPS if bound == "alu" else HBM_PEAK_GBPS,
+                "unit": "TFLOP/s" if bound == "alu" else "GB/s",
+                "frac": frac_alu if bound == "alu" else frac_hbm,
+                "traffic": read_traffic(config, dom_name),
+                "kernel": dom_name, "avg_launch_us": avg_s * 1e6,
+                "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": nbytes,
+                "frac_of_fp32_vector_peak": frac_alu, "frac_of_hbm_peak": frac_hbm,
+                "hbm_GBps": hbm, "fp32_TFLOPs": alu,
+                "counters": read_counters(config, dom_name)}
+    step_bytes = costs["pass_x"][0] + costs["pass_y"][0]
+    res = {"workload": w.name, "views_per_step": nv, "views_per_s": nv / sec, "ms_per_step": sec * 1e3,
+           "per_call": stats, "launch_mode": mode, "length_policy": plan.length_policy(), "schedule": sched,
+           "lengths": sorted({plan.lengths(v) for v in range(nv)}),
+           "kernels": kern, "roofline": roofline,
+           "hbm": {"algorithmic_bytes_per_step": step_bytes, "achieved_GBps": step_bytes / sec / 1e9,
+                   "frac_of_8TBps": step_bytes / sec / 1e9 / HBM_PEAK_GBPS}}
+    return plan, holo, outs, res
+
+
+def per_view_baseline(w, dev, holo, steps: int, warmup: int, tune: bool, batched_sec: float):
+    """The same views with one launch sequence per view (setup, column pass,
+    row pass for each view in turn), with its own tuned tile widths."""
+    import paper_1001_4309_amd as sfd
+
+    nv = len(w.views)
+    pv = sfd.Plan(w.wavelength, w.holo_grid, len(w.holograms), w.views, device=dev, per_view_launch=True)
+    pouts = pv.new_outputs()
+    if tune:
+        pv.autotune(holo, reps=10, outs=pouts)
+    for _ in range(warmup):
+        pv.reconstruct(holo, outs=pouts)
+    psec = time_steps(pv, holo, pouts, steps)
+    log(f"{w.name} per-view launch: {psec * 1e6:.1f} us/step, {nv / psec:.0f} views/s")
+    return {"views_per_s": nv / psec, "ms_per_step": psec * 1e3, "batched_speedup": psec / batched_sec,
+            "schedule": {f"{k[0]}{k[1]}": g for k, g in pv.schedule().items()}}
 
 
 def bench_streaming(w, plan, steps: int, warmup: int):
@@ -355,6 +528,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 5])
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--legs", default="3,5",
+                    help="other workloads to measure beside the main one (comma-separated config numbers; "
+                         "'' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tile widths")
@@ -397,66 +573,12 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy: {args.calib_copy_mib} MiB read + {args.calib_copy_mib} MiB written")
         del a, b
+    tune = not args.no_autotune
     w = workloads.CONFIGS[args.config]()
-    holo = torch.from_numpy(np.ascontiguousarray(w.holograms)).to(dev)
-    plan = sfd.Plan(w.wavelength, w.holo_grid, len(w.holograms), w.views, device=dev)
-    outs = plan.new_outputs()
     nv = len(w.views)
-    if args.schedule:
-        for item in args.schedule.split(","):
-            key, g = item.split("=")
-            col = key.startswith("col")
-            plan.set_schedule(int(key[3:]), col, int(g))
-    elif not args.no_autotune:
-        plan.autotune(holo, reps=10, outs=outs)
-    schedule = {f"{k[0]}{k[1]}": g for k, g in sorted(plan.schedule().items())}
-    log("schedule (tile widths):", schedule)
-
-    for _ in range(args.warmup):
-        plan.reconstruct(holo, outs=outs)
-    sec = time_steps(plan, holo, outs, args.steps)
-    ms_per_step = sec * 1e3
-    value = nv / sec
-    log(f"batched: {ms_per_step * 1e3:.1f} us/step, {value:.0f} views/s")
-
-    # Kernel durations from HIP events on the launch stream, over a second
-    # timed region of the same steps.
-    prof_steps = max(1, min(args.steps, 100))
-    plan.profile(True)
-    for _ in range(prof_steps):
-        plan.reconstruct(holo, outs=outs)
-    torch.cuda.synchronize()
-    rep = plan.profile_report()
-    plan.profile(False)
-    costs = pass_costs(w, plan)
-    kern = {k: {"launches": n, "avg_us": (ms / n * 1e3) if n else 0.0} for k, (n, ms) in rep.items() if n}
-    log("kernels:", json.dumps(kern))
-    if rep.get("persist", (0, 0.0))[0] > 0:
-        # One persistent launch per step holds every pass.
-        dom = "persist"
-        costs["persist"] = [costs["pass_x"][0] + costs["pass_y"][0], costs["pass_x"][1] + costs["pass_y"][1]]
-    else:
-        dom = max(("pass_x", "pass_y"), key=lambda k: rep[k][1])
-    n_launch, tot_ms = rep[dom]
-    avg_s = tot_ms / n_launch / 1e3
-    launches_per_step = n_launch / prof_steps
-    flops = costs[dom][1] / launches_per_step
-    lx0, ly0 = plan.lengths(0)
-    if dom == "persist":
-        dom_name = "persist_kernel"
-    else:
-        dom_L = lx0 if dom == "pass_x" else ly0
-        dom_name = kernel_name(dom, dom_L, plan.schedule()[("row" if dom == "pass_x" else "col", dom_L)],
-                               pass_variant(w, plan, dom))
-    traffic = read_traffic(args.config, dom_name)  # HBM bytes per launch, from the committed counters
-    roofline = {"bound": "alu", "achieved": flops / avg_s / 1e12, "peak": FP32_VECTOR_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": flops / avg_s / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
-                "traffic": traffic, "kernel": dom_name, "avg_launch_us": avg_s * 1e6,
-                "algorithmic_flops_per_launch": flops,
-                "algorithmic_bytes_per_launch": costs[dom][0] / launches_per_step}
-    step_bytes = costs["pass_x"][0] + costs["pass_y"][0]
-    hbm = {"algorithmic_bytes_per_step": step_bytes, "achieved_GBps": step_bytes / sec / 1e9,
-           "frac_of_8TBps": step_bytes / sec / 1e9 / HBM_PEAK_GBPS}
+    plan, holo, outs, main_res = measure(w, dev, args, args.steps, args.warmup, args.config, tune, args.schedule)
+    sec = main_res["ms_per_step"] / 1e3
+    value = main_res["views_per_s"]
     if args.calib_copy_mib <= 0:  # a counter run keeps its only copy the calibration one
         # Reference: a plain 1 GiB device-to-device copy on the same GPU.
         ca = torch.empty(1 << 28, dtype=torch.float32, device=dev)
@@ -470,22 +592,27 @@ def main():
         torch.cuda.synchronize()
         copy_gbps = 5 * 2 * ca.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
         del ca, cb
-        hbm["device_copy_GBps"] = copy_gbps
-        hbm["frac_of_device_copy"] = step_bytes / sec / 1e9 / copy_gbps
+        main_res["hbm"]["device_copy_GBps"] = copy_gbps
+        main_res["hbm"]["frac_of_device_copy"] = main_res["hbm"]["achieved_GBps"] / copy_gbps
 
     per_view = None
     if not args.no_per_view:
-        pv = sfd.Plan(w.wavelength, w.holo_grid, len(w.holograms), w.views, device=dev, per_view_launch=True)
-        pouts = pv.new_outputs()
-        if not args.no_autotune:
-            # Its own best tile widths: one view per launch favours narrower tiles.
-            pv.autotune(holo, reps=10, outs=pouts)
-        for _ in range(args.warmup):
-            pv.reconstruct(holo, outs=pouts)
-        psec = time_steps(pv, holo, pouts, args.steps)
-        per_view = {"views_per_s": nv / psec, "ms_per_step": psec * 1e3, "batched_speedup": psec / sec,
-                    "schedule": {f"{k[0]}{k[1]}": g for k, g in pv.schedule().items()}}
-        log(f"per-view launch: {psec * 1e6:.1f} us/step, {nv / psec:.0f} views/s")
+        per_view = per_view_baseline(w, dev, holo, args.steps, args.warmup, tune, sec)
+
+    # Other workloads of the method: the batched uneven views (64 views of 8
+    # holograms) and the large one (L = 8192), each with its own roofline.
+    legs = {}
+    for c in [int(x) for x in args.legs.split(",") if x.strip()]:
+        if c == args.config:
+            continue
+        wl = workloads.CONFIGS[c]()
+        lsteps = max(5, min(args.steps, 20 if c == 5 else 50))
+        _, lholo, _, lres = measure(wl, dev, args, lsteps, max(2, min(args.warmup, 5)), c, tune)
+        if c == 3 and not args.no_per_view:
+            lres["per_view_launch"] = per_view_baseline(wl, dev, lholo, lsteps, 2, tune, lres["ms_per_step"] / 1e3)
+        legs[f"config{c}"] = lres
+        del lholo
+        torch.cuda.empty_cache()
 
     streaming = None
     if not args.no_streaming:
@@ -507,10 +634,9 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, args.cpu_seconds)
-        log(f"cpu oracle: {cpu['value']:.3f} views/s on {cpu['cores']} threads")
+        log(f"cpu oracle: {cpu['value']:.3f} views/s on {cpu['cores']} cores ({cpu['cpu_model']})")
 
     g = w.holo_grid
-    lx, ly = plan.lengths(0)
     line = {
         "metric": METRIC,
         "value": value,
@@ -518,7 +644,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": sec * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -526,19 +652,20 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "holograms": len(w.holograms), "views_per_step": nv,
                    "hologram": [g.ny, g.nx], "views": [[v.grid.ny, v.grid.nx] for v in w.views],
-                   "padded_length": [lx, ly], "phase": "fp64-reduced", "output": "intensity",
-                   "schedule": schedule, "launch": "hip-graph replay",
-                   "launch_mode": plan.launch_mode()[0]},
-        "roofline": roofline,
-        "hbm": hbm,
+                   "padded_lengths": main_res["lengths"], "phase": "fp64-reduced", "output": "intensity",
+                   "schedule": main_res["schedule"], "launch": "hip-graph replay",
+                   "launch_mode": main_res["launch_mode"], "length_policy": main_res["length_policy"]},
+        "roofline": main_res["roofline"],
+        "per_call": main_res["per_call"],
+        "hbm": main_res["hbm"],
         "per_view_launch": per_view,
+        "legs": legs,
         "backward": backward,
         "streaming": streaming,
-        "kernels": kern,
+        "kernels": main_res["kernels"],
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
-
 
 if __name__ == "__main__":
     main()

@@ -177,8 +177,8 @@ constexpr int kSetupThreads = 256;
 // items from a ticket counter in the order of the segments below (each item
 // depends only on items with smaller tickets, so the launch cannot deadlock
 // whatever number of its workgroups are resident):
-//   kItemSetup  one per view: its kernel spectra Hx, Hy (half of the
-//               workgroup each) and its pre/post chirp tables;
+//   kItemSetup  two per view: its kernel spectra Hx, Hy (half of the
+//               workgroup each), and its pre/post chirp tables;
 //   kItemStrip  kStripW columns of a hologram rewritten column-major (the
 //               copy the column pass reads, see TileJob);
 //   kItemCol    a column-pass tile; waits for its view's setup item and the

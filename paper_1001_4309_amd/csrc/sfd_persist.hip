@@ -117,41 +117,45 @@ __device__ __forceinline__ void spectra_pass(int L, const AxisJob* jx, const Axi
   }
 }
 
-__device__ __forceinline__ void persist_setup(const PersistArgs& A, int v, unsigned char* lds, int tid) {
+// Setup items of view v, two per view so that they run side by side: part 0
+// builds the kernel spectra, part 1 the chirp tables of both axes (each
+// axis's fields read once).
+__device__ __forceinline__ void persist_setup(const PersistArgs& A, int v, int part, unsigned char* lds, int tid) {
   const AxisJob* X = &A.axis[2 * v];
   const AxisJob* Y = &A.axis[2 * v + 1];
-  const int lx = X->L, ly = Y->L;
-  if (lx == ly) {
-    spectra_pass(lx, X, Y, A.tw_view[2 * v], lds, tid);
-  } else {
-    spectra_pass(lx, X, nullptr, A.tw_view[2 * v], lds, tid);
-    __syncthreads();
-    spectra_pass(ly, nullptr, Y, A.tw_view[2 * v + 1], lds, tid);
+  if (part == 0) {
+    const int lx = X->L, ly = Y->L;
+    const float2* twx = A.tw_view[2 * v];
+    const float2* twy = A.tw_view[2 * v + 1];
+    if (lx == ly) {
+      spectra_pass(lx, X, Y, twx, lds, tid);
+    } else {
+      spectra_pass(lx, X, nullptr, twx, lds, tid);
+      __syncthreads();
+      spectra_pass(ly, nullptr, Y, twy, lds, tid);
+    }
+    return;
   }
-  const int nx = X->n0 + (X->post ? X->n1 : 0);
-  const int total = nx + Y->n0 + (Y->post ? Y->n1 : 0);
+  const AxisJob jx = *X, jy = *Y;
+  const int nx = jx.n0 + (jx.post ? jx.n1 : 0);
+  const int total = nx + jy.n0 + (jy.post ? jy.n1 : 0);
   for (int i = tid; i < total; i += kPersistThreads) {
-    const bool xa = i < nx;
-    const AxisJob& J = xa ? *X : *Y;
-    const int k = xa ? i : i - nx;
-    if (k < J.n0) gst_c<true>(J.pre, (unsigned)k, pre_value(J, k));
-    else gst_c<true>(J.post, (unsigned)(k - J.n0), post_value(J, k - J.n0));
+    if (i < jx.n0) gst_c<true>(jx.pre, (unsigned)i, pre_value(jx, i));
+    else if (i < nx) gst_c<true>(jx.post, (unsigned)(i - jx.n0), post_value(jx, i - jx.n0));
+    else if (i - nx < jy.n0) gst_c<true>(jy.pre, (unsigned)(i - nx), pre_value(jy, i - nx));
+    else gst_c<true>(jy.post, (unsigned)(i - nx - jy.n0), post_value(jy, i - nx - jy.n0));
   }
 }
 
-// One hologram sample for the column-major copy (see TileJob): float32,
-// complex64, or a camera sample resized along x.
-template <typename T>
-__device__ __forceinline__ T holo_sample(const TileJob& J, int n, int c);
-template <>
-__device__ __forceinline__ float2 holo_sample<float2>(const TileJob& J, int n, int c) {
-  return gld(static_cast<const float2*>(J.in), (unsigned)(n * J.nx + c));
-}
+// Strip item: columns [c0, c0 + kStripW) of a hologram, every row, into its
+// column-major copy (see TileJob).  Rows go in chunks of CH: every load of a
+// chunk is issued before the first is used (rows of kStripW consecutive
+// samples; the sample format is decided once, outside the loads), the chunk
+// is turned around in LDS, and each column leaves as a contiguous run of CH
+// samples, written through (later items read it on other XCDs).
 template <typename S>
-__device__ __forceinline__ float resampled(const TileJob& J, int n, int c) {
-  const S* in = static_cast<const S*>(J.in);
-  const int ns = J.nx_src;
-  double sx = ((double)c + 0.5) * (double)ns / (double)J.nx - 0.5;
+__device__ __forceinline__ float resample_at(const S* in, int ns, int nx, int n, int c) {
+  double sx = ((double)c + 0.5) * (double)ns / (double)nx - 0.5;
   sx = fmin(fmax(sx, 0.0), (double)(ns - 1));
   const int i0 = (int)sx;
   const int i1 = i0 + 1 < ns ? i0 + 1 : ns - 1;
@@ -159,32 +163,25 @@ __device__ __forceinline__ float resampled(const TileJob& J, int n, int c) {
   const float a = (float)gld(in, (unsigned)(n * ns + i0)), b = (float)gld(in, (unsigned)(n * ns + i1));
   return fmaf(wt, b - a, a);
 }
-template <>
-__device__ __forceinline__ float holo_sample<float>(const TileJob& J, int n, int c) {
-  if (J.nx_src > 0) {
-    if (J.src_bits == 8) return resampled<unsigned char>(J, n, c);
-    if (J.src_bits == 16) return resampled<unsigned short>(J, n, c);
-    return resampled<float>(J, n, c);
-  }
-  return gld(static_cast<const float*>(J.in), (unsigned)(n * J.nx + c));
-}
 
-// Strip item: columns [c0, c0 + kStripW) of a hologram, every row, into its
-// column-major copy.  Rows go in chunks of CH: all loads of a chunk are
-// issued first (rows of kStripW consecutive samples), the chunk is turned
-// around in LDS, and each column leaves as a contiguous run of CH samples.
-template <typename T, int CH>
-__device__ __forceinline__ void persist_strip_t(const TileJob& J, int c0, unsigned char* lds, int tid) {
+// FMT: 0 float32 (or complex64 for T = float2), 8 / 16 / 32 camera samples
+// resized along x (real input only).
+template <typename T, int CH, int FMT>
+__device__ __forceinline__ void strip_chunks(const TileJob J, int c0, T* buf, int tid) {
   constexpr int W = kStripW, K = CH * W / kPersistThreads, ST = CH + 4;
-  T* buf = reinterpret_cast<T*>(lds);
-  const auto rs = store_rsrc(J.out, (uint32_t)J.nx * (uint32_t)J.ld * (uint32_t)sizeof(T));
-  for (int r0 = 0; r0 < J.ny; r0 += CH) {
+  const int nx = J.nx, ny = J.ny, ld = J.ld, ns = J.nx_src;
+  const auto rs = store_rsrc(J.out, (uint32_t)nx * (uint32_t)ld * (uint32_t)sizeof(T));
+  for (int r0 = 0; r0 < ny; r0 += CH) {
     T v[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int f = tid + kPersistThreads * k;
-      const int n = r0 + f / W, c = c0 + f % W;
-      v[k] = holo_sample<T>(J, n < J.ny ? n : J.ny - 1, c < J.nx ? c : J.nx - 1);
+      const int n0 = r0 + f / W, cc = c0 + f % W;
+      const int n = n0 < ny ? n0 : ny - 1, c = cc < nx ? cc : nx - 1;
+      if constexpr (FMT == 0) v[k] = gld(static_cast<const T*>(J.in), (unsigned)(n * nx + c));
+      else if constexpr (FMT == 8) v[k] = resample_at(static_cast<const unsigned char*>(J.in), ns, nx, n, c);
+      else if constexpr (FMT == 16) v[k] = resample_at(static_cast<const unsigned short*>(J.in), ns, nx, n, c);
+      else v[k] = resample_at(static_cast<const float*>(J.in), ns, nx, n, c);
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -196,12 +193,21 @@ __device__ __forceinline__ void persist_strip_t(const TileJob& J, int c0, unsign
     for (int k = 0; k < K; ++k) {
       const int f = tid + kPersistThreads * k;
       const int c = f / CH, n = f % CH;
-      const bool ok = r0 + n < J.ny && c0 + c < J.nx;
-      bst<kWriteThrough>(rs, ok ? (uint32_t)((c0 + c) * J.ld + r0 + n) * (uint32_t)sizeof(T) : kDrop,
+      const bool ok = r0 + n < ny && c0 + c < nx;
+      bst<kWriteThrough>(rs, ok ? (uint32_t)((c0 + c) * ld + r0 + n) * (uint32_t)sizeof(T) : kDrop,
                          buf[c * ST + n]);
     }
     __syncthreads();
   }
+}
+
+__device__ __forceinline__ void persist_strip(const TileJob* Jp, int c0, unsigned char* lds, int tid) {
+  const TileJob J = *Jp;  // fields read once
+  if (J.complex_in) strip_chunks<float2, 512, 0>(J, c0, reinterpret_cast<float2*>(lds), tid);
+  else if (J.nx_src <= 0) strip_chunks<float, 1024, 0>(J, c0, reinterpret_cast<float*>(lds), tid);
+  else if (J.src_bits == 8) strip_chunks<float, 1024, 8>(J, c0, reinterpret_cast<float*>(lds), tid);
+  else if (J.src_bits == 16) strip_chunks<float, 1024, 16>(J, c0, reinterpret_cast<float*>(lds), tid);
+  else strip_chunks<float, 1024, 32>(J, c0, reinterpret_cast<float*>(lds), tid);
 }
 
 template <int L>
@@ -234,9 +240,6 @@ __global__ void __launch_bounds__(kPersistThreads) persist_kernel(const PersistA
     __syncthreads();
     const int t = s_ticket;
     if (t >= total) break;
-    // The next ticket is taken now; its value is needed only after this item.
-    uint32_t next = 0;
-    if (threadIdx.x == 0) next = sync_add(&sync[kSyncTicket * kSyncStride], 1u);
     // The thread index enters each item through an opaque move: nothing
     // derived from it is hoisted out of the item loop (and held in registers
     // across every item).
@@ -246,16 +249,16 @@ __global__ void __launch_bounds__(kPersistThreads) persist_kernel(const PersistA
     const Segment& sg = A.seg[k];
     const int local = t - sg.first;
     switch (sg.kind) {
-      case kItemSetup:
-        persist_setup(A, local, lds, tid);
-        signal_count(&setup_done[local * kSyncStride]);
+      case kItemSetup: {
+        // Items 0 .. nview-1: spectra of view i; nview .. 2 nview - 1: tables.
+        const int v = local < nview ? local : local - nview;
+        persist_setup(A, v, local < nview ? 0 : 1, lds, tid);
+        signal_count(&setup_done[v * kSyncStride]);
         break;
+      }
       case kItemStrip: {
         const int nsp = (A.tiles[0].nx + kStripW - 1) / kStripW;
-        const TileJob& J = A.tiles[local / nsp];
-        const int c0 = (local % nsp) * kStripW;
-        if (J.complex_in) persist_strip_t<float2, 512>(J, c0, lds, tid);
-        else persist_strip_t<float, 1024>(J, c0, lds, tid);
+        persist_strip(&A.tiles[local / nsp], (local % nsp) * kStripW, lds, tid);
         signal_count(&strip_done[local * kSyncStride]);
         break;
       }
@@ -267,7 +270,7 @@ __global__ void __launch_bounds__(kPersistThreads) persist_kernel(const PersistA
         const int nsp = (A.tiles[0].nx + kStripW - 1) / kStripW;
         const int strip = J.copy * nsp + (local - PA.tile_prefix[jid]);
         wait_counts(sync, &strip_done[strip * kSyncStride], 1u,
-                    A.wait_setup ? &setup_done[view * kSyncStride] : nullptr, 1u);
+                    A.wait_setup ? &setup_done[view * kSyncStride] : nullptr, 2u);
         switch (sg.L) {
           case 2048: persist_col<2048>(sg, local, lds, tid); break;
           case 1792: persist_col<1792>(sg, local, lds, tid); break;
@@ -293,7 +296,9 @@ __global__ void __launch_bounds__(kPersistThreads) persist_kernel(const PersistA
         break;
       }
     }
-    if (threadIdx.x == 0) s_ticket = (int)next;
+    // The next ticket is taken once this item is done: a ticket taken earlier
+    // would hold its item back behind this one while other workgroups idle.
+    if (threadIdx.x == 0) s_ticket = (int)sync_add(&sync[kSyncTicket * kSyncStride], 1u);
   }
   // Leaving: the last workgroup out resets the counters for the next launch
   // (every item is done once every workgroup has taken a ticket past the end).
