@@ -253,6 +253,29 @@ sfd_status sfd_set_raw_input(sfd_plan_t plan, int32_t nx_raw, int32_t sample_bit
  * length), or -1 if cap < 0 or cap > 0 with widths NULL. */
 int32_t sfd_tile_widths(int32_t L, int32_t col, int32_t* widths, int32_t* per_slot, int32_t cap);
 
+/*
+ * sfd_reconstruct without a caller workspace and without any allocation,
+ * for callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  The workspace is a
+ * static device array of the library, sfd_noalloc_capacity() bytes (64 MiB:
+ * enough for a 1024^2 hologram with four 1024^2 views at padded length 2048),
+ * held on every GPU the library runs on until the process ends.  The call
+ * allocates nothing: descriptors reach the device through kernel
+ * arguments, the kernels are launched directly on ``stream`` (no graph is
+ * recorded), and no host staging buffer is used.
+ *   plan, holo, z_or_null, out, stream: as in sfd_reconstruct.
+ * Every call on a GPU shares that GPU's array, and the array keeps the last
+ * call's contents: a call of another plan than the previous one rebuilds the
+ * plan's tables and zeroes its counters first.  Calls that overlap in time on
+ * one GPU (several streams or threads) race on the array and must not be
+ * made.  Errors: SFD_ERR_WORKSPACE when sfd_workspace_size of the plan
+ * exceeds the array (checked before any HIP call), and the sfd_reconstruct
+ * errors.
+ */
+sfd_status sfd_reconstruct_noalloc(sfd_plan_t plan, const void* holo, const double* z_or_null,
+                                   void* const* out, hipStream_t stream);
+size_t sfd_noalloc_capacity(void);
+
 /* Kernel kinds reported by sfd_profile_report. */
 enum {
   SFD_KERNEL_TABLES = 0,   /* chirp and twiddle tables (Eqs. 2-4) */

@@ -28,7 +28,7 @@ __all__ = ["Plan", "SFDFunction", "sfd_plan", "sfd_workspace_size", "sfd_view_le
            "sfd_backward", "sfd_autotune", "sfd_schedule", "sfd_set_schedule", "sfd_tile_widths",
            "sfd_stream_frame", "sfd_set_raw_input", "sfd_profile_enable", "sfd_profile_report", "sfd_destroy",
            "sfd_set_launch", "sfd_launch_mode", "sfd_sync_faults", "sfd_set_length_policy", "sfd_length_policy",
-           "SfdError", "FrameStream"]
+           "sfd_reconstruct_noalloc", "SfdError", "FrameStream"]
 
 
 def _grid(g) -> SfdGrid:
@@ -94,6 +94,14 @@ def sfd_reconstruct(plan, holo: torch.Tensor, z, outs: Sequence[torch.Tensor], w
     _lib.check(_lib.load().sfd_reconstruct(plan, _ptr(holo), za, _ptr_array(outs), _ptr(workspace),
                                            workspace.numel() * workspace.element_size(),
                                            _stream_handle(holo.device)))
+
+
+def sfd_reconstruct_noalloc(plan, holo: torch.Tensor, z, outs: Sequence[torch.Tensor]) -> None:
+    """sfd_reconstruct on the library's static scratch array (no workspace,
+    no allocation)."""
+    za = _z_array(z)
+    _lib.check(_lib.load().sfd_reconstruct_noalloc(plan, _ptr(holo), za, _ptr_array(outs),
+                                                   _stream_handle(holo.device)))
 
 
 def sfd_stream_frame(plan, host_frame: torch.Tensor, dev_holo: Sequence[torch.Tensor], outs: Sequence[torch.Tensor],
@@ -317,6 +325,17 @@ class Plan:
         if outs is None:
             outs = self.new_outputs()
         sfd_reconstruct(self.handle, holo, z, outs, self.workspace)
+        return outs
+
+    def reconstruct_noalloc(self, holo: torch.Tensor, z=None, outs=None):
+        """As reconstruct, on the library's static scratch array instead of
+        the plan's workspace (sfd_reconstruct_noalloc); ``outs`` must be
+        given by callers that cannot allocate."""
+        holo = self._check_holo(holo)
+        self._check_z(z)
+        if outs is None:
+            outs = self.new_outputs()
+        sfd_reconstruct_noalloc(self.handle, holo, z, outs)
         return outs
 
     def stream_frame(self, host_frame: torch.Tensor, dev_holo: Sequence[torch.Tensor], outs) -> None:

@@ -30,7 +30,7 @@ EXPORTED = ["sfd_plan", "sfd_workspace_size", "sfd_view_lengths", "sfd_reconstru
             "sfd_backward", "sfd_autotune", "sfd_schedule", "sfd_set_schedule", "sfd_tile_widths",
             "sfd_stream_frame", "sfd_set_raw_input", "sfd_profile_enable", "sfd_profile_report", "sfd_destroy",
             "sfd_last_error", "sfd_set_launch", "sfd_launch_mode", "sfd_sync_faults", "sfd_set_length_policy",
-            "sfd_length_policy"]
+            "sfd_length_policy", "sfd_reconstruct_noalloc", "sfd_noalloc_capacity"]
 
 SFD_KERNEL_TABLES = 0
 SFD_KERNEL_SPECTRA = 1
@@ -101,13 +101,16 @@ def load() -> ctypes.CDLL:
     lib.sfd_sync_faults.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint32), vp]
     lib.sfd_set_length_policy.argtypes = [vp, ctypes.c_int32]
     lib.sfd_length_policy.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    lib.sfd_reconstruct_noalloc.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(vp), vp]
+    lib.sfd_noalloc_capacity.argtypes = []
+    lib.sfd_noalloc_capacity.restype = ctypes.c_size_t
     lib.sfd_destroy.argtypes = [vp]
     lib.sfd_last_error.argtypes = []
     lib.sfd_last_error.restype = ctypes.c_char_p
     for name in ("sfd_plan", "sfd_workspace_size", "sfd_view_lengths", "sfd_reconstruct", "sfd_backward",
                  "sfd_autotune", "sfd_schedule", "sfd_set_schedule", "sfd_stream_frame", "sfd_set_raw_input",
                  "sfd_profile_enable", "sfd_profile_report", "sfd_destroy", "sfd_set_launch", "sfd_launch_mode",
-                 "sfd_sync_faults", "sfd_set_length_policy", "sfd_length_policy"):
+                 "sfd_sync_faults", "sfd_set_length_policy", "sfd_length_policy", "sfd_reconstruct_noalloc"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib

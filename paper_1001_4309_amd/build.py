@@ -15,7 +15,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsfd.so")
 
-SOURCES = ["sfd_api.cpp", "sfd_kernels.hip", "sfd_rows.hip", "sfd_cols.hip", "sfd_persist.hip"]
+SOURCES = ["sfd_api.cpp", "sfd_kernels.hip", "sfd_rows.hip", "sfd_cols.hip", "sfd_persist.hip", "sfd_noalloc.hip"]
 
 # Packed FP32 instructions are disabled for every device compile: some of their
 # forms have produced silently wrong results on this hardware.

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -135,7 +136,15 @@ std::mutex g_tune_mu;
 std::map<std::tuple<int, int, std::string>, int> g_tuned;
 }  // namespace
 
+namespace {
+std::atomic<uint64_t> g_plan_serial{0};
+// Which plan used a no-allocation scratch array (per device address) last.
+std::mutex g_scratch_mu;
+std::map<void*, uint64_t> g_scratch_owner;
+}  // namespace
+
 struct sfd_plan_s {
+  const uint64_t serial = ++g_plan_serial;
   double lam = 0;
   sfd_grid holo{};
   int n_holo = 0;
@@ -1358,9 +1367,12 @@ sfd_status sfd_view_lengths(sfd_plan_t plan, int32_t v, int32_t* lx, int32_t* ly
   return SFD_OK;
 }
 
-sfd_status sfd_reconstruct(sfd_plan_t plan, const void* holo, const double* z_or_null, void* const* out,
-                           void* workspace, size_t ws_bytes, hipStream_t stream) {
-  g_err.clear();
+}  // extern "C"
+
+sfd_status sfd::set_error(sfd_status s, const char* msg) { return fail(s, msg); }
+
+sfd_status sfd::reconstruct_impl(sfd_plan_s* plan, const void* holo, const double* z_or_null, void* const* out,
+                                 void* workspace, size_t ws_bytes, hipStream_t stream, bool no_alloc) {
   sfd_status st = check_common(plan, workspace, ws_bytes);
   if (st != SFD_OK) return st;
   if (!holo) return fail(SFD_ERR_INVALID_ARG, "holo is NULL");
@@ -1376,6 +1388,21 @@ sfd_status sfd_reconstruct(sfd_plan_t plan, const void* holo, const double* z_or
   if ((st = check_z(plan, z_or_null)) != SFD_OK) return st;
 
   char* ws = static_cast<char*>(workspace);
+  if (no_alloc) {
+    // The scratch array is shared by every plan: state cached for it (twiddle
+    // tables, zeroed counters, descriptors, kept tables) is valid only if this
+    // plan used it last.
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    uint64_t& owner = g_scratch_owner[workspace];
+    if (owner != plan->serial) {
+      if (plan->tw_ready_ws == ws) plan->tw_ready_ws = nullptr;
+      if (plan->sync_ready_ws == ws) plan->sync_ready_ws = nullptr;
+      if (plan->tables_ws == ws) plan->tables_ws = nullptr;
+      if (plan->last_ws[0] == ws) plan->last_ws[0] = nullptr;
+      if (plan->last_ws[1] == ws) plan->last_ws[1] = nullptr;
+      owner = plan->serial;
+    }
+  }
   // SFD_REUSE_TABLES: this call needs no tables or spectra when the
   // workspace holds those of the same distances.
   bool tables = true;
@@ -1398,7 +1425,18 @@ sfd_status sfd_reconstruct(sfd_plan_t plan, const void* holo, const double* z_or
     }
     pack_persist(plan, &D, ws, tables, &img, off_axis, off_tiles, off_rows);
   }
-  if ((st = upload(plan, 0, img, ws, plan->desc_off, stream)) != SFD_OK) return st;
+  if (no_alloc) {
+    // Kernel-argument copies instead of the pinned staging buffer (which the
+    // first upload would allocate).
+    if (!(plan->last_ws[0] == ws && plan->last_desc[0] == img)) {
+      img.resize((img.size() + 3) / 4 * 4, 0);
+      SFD_HIP_TRY(sfd::launch_blit(ws + plan->desc_off, img.data(), img.size(), stream));
+      plan->last_desc[0] = img;
+      plan->last_ws[0] = ws;
+    }
+  } else if ((st = upload(plan, 0, img, ws, plan->desc_off, stream)) != SFD_OK) {
+    return st;
+  }
   const auto* d_axis = reinterpret_cast<const sfd::AxisJob*>(ws + plan->desc_off + off_axis);
   const auto* d_tw = reinterpret_cast<const sfd::TwiddleJob*>(ws + plan->desc_off + off_tw);
   const auto* d_rows = reinterpret_cast<const sfd::RowJob*>(ws + plan->desc_off + off_rows);
@@ -1429,7 +1467,7 @@ sfd_status sfd_reconstruct(sfd_plan_t plan, const void* holo, const double* z_or
     }
     return SFD_OK;
   }
-  const bool use_graph = !(plan->flags & SFD_EAGER) && !plan->profiling;
+  const bool use_graph = !(plan->flags & SFD_EAGER) && !plan->profiling && !no_alloc;
   if (use_graph) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     SFD_HIP_TRY(hipStreamIsCapturing(stream, &cs));
@@ -1461,6 +1499,14 @@ sfd_status sfd_reconstruct(sfd_plan_t plan, const void* holo, const double* z_or
   st = launch_forward(plan, D, ws, d_axis, d_tw, d_tiles, d_rows, stream, tables);
   if (st == SFD_OK && (plan->flags & SFD_REUSE_TABLES)) plan->tables_ws = ws;
   return st;
+}
+
+extern "C" {
+
+sfd_status sfd_reconstruct(sfd_plan_t plan, const void* holo, const double* z_or_null, void* const* out,
+                           void* workspace, size_t ws_bytes, hipStream_t stream) {
+  g_err.clear();
+  return sfd::reconstruct_impl(plan, holo, z_or_null, out, workspace, ws_bytes, stream, false);
 }
 
 sfd_status sfd_backward(sfd_plan_t plan, void* const* grad_out, void* const* field_out, const void* holo,

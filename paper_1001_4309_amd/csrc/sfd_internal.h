@@ -20,6 +20,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "sfd.h"
+
 namespace sfd {
 
 // Table-building job for one axis of one view (Eqs. 2-4).
@@ -255,6 +257,10 @@ bool persist_length(int L);
 // Workgroups of the persistent launch resident at once on this device.
 int persist_resident_blocks();
 
+// Copy ``bytes`` (a multiple of 4) from host memory to device memory on
+// stream s through kernel arguments (no staging buffer, no allocation).
+hipError_t launch_blit(void* dst, const void* src, size_t bytes, hipStream_t s);
+
 hipError_t launch_gradz(const GradZJob* d_jobs, int njobs, hipStream_t s);
 hipError_t launch_gather(const GatherJob* d_jobs, int njobs, int max_n, hipStream_t s);
 
@@ -271,5 +277,15 @@ int fast_input(int L);
 // Entries of the twiddle table of the passes' (spec = false) or the kernel
 // spectrum's (spec = true) transform shape of length L.
 int twiddle_len(int L, bool spec);
+
+// The reconstruction behind sfd_reconstruct (no_alloc = false) and
+// sfd_reconstruct_noalloc (no_alloc = true: the workspace is the library's
+// static scratch array; descriptors go up through kernel arguments, kernels
+// are launched directly, and the plan's cached workspace state is rebuilt
+// whenever another plan used the scratch last).
+sfd_status reconstruct_impl(sfd_plan_s* plan, const void* holo, const double* z_or_null, void* const* out,
+                            void* workspace, size_t ws_bytes, hipStream_t stream, bool no_alloc);
+// Set the calling thread's error message (see sfd_last_error) and return s.
+sfd_status set_error(sfd_status s, const char* msg);
 
 }  // namespace sfd

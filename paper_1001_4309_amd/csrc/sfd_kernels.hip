@@ -238,6 +238,34 @@ int spectra_per_block(int L) {
 }
 
 
+// Host-to-device copy through kernel arguments: each launch carries
+// kBlitWords words of the image in its argument block and stores them.  No
+// host staging buffer and no allocation are involved (the runtime's own
+// argument buffers carry the data).
+constexpr int kBlitWords = 512;
+struct BlitArgs {
+  uint32_t w[kBlitWords];
+};
+__global__ void __launch_bounds__(256) blit_kernel(uint32_t* dst, int n, const BlitArgs a) {
+  for (int i = threadIdx.x; i < n; i += 256) dst[i] = a.w[i];
+}
+
+hipError_t launch_blit(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  if (bytes % 4) return hipErrorInvalidValue;
+  const size_t words = bytes / 4;
+  const uint32_t* sw = static_cast<const uint32_t*>(src);
+  uint32_t* dw = static_cast<uint32_t*>(dst);
+  for (size_t off = 0; off < words; off += kBlitWords) {
+    const int n = (int)(words - off < (size_t)kBlitWords ? words - off : (size_t)kBlitWords);
+    BlitArgs a;
+    for (int i = 0; i < n; ++i) a.w[i] = sw[off + i];
+    hipLaunchKernelGGL(blit_kernel, dim3(1), dim3(256), 0, s, dw + off, n, a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_pass(int L, bool col, int G, int var, const PassArgs& a, const float2* tw, hipStream_t s) {
   if (a.total_tiles <= 0) return hipSuccess;
   return col ? launch_col_pass(L, G, var, a, tw, s) : launch_row_pass(L, G, var, a, tw, s);

@@ -22,7 +22,7 @@ def lib():
 
 def declared_functions():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:sfd_status|const char\*|int32_t)\s+(sfd_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:sfd_status|const char\*|int32_t|size_t)\s+(sfd_\w+)\s*\(", text, re.M)))
 
 
 def test_header_declares_the_boundary():
@@ -54,7 +54,7 @@ def test_tile_width_query(lib):
     """Every supported length has kernels for both passes, the default first;
     widths are distinct; transforms per slot divide the width; the argument
     checks and the unsupported-length answer."""
-    for L in (64, 128, 256, 512, 1024, 2048, 4096, 8192):
+    for L in (64, 128, 256, 512, 1024, 1280, 1536, 1792, 2048, 4096, 8192):
         for col in (0, 1):
             w = (ctypes.c_int32 * 64)()
             p = (ctypes.c_int32 * 64)()
@@ -274,3 +274,25 @@ def test_raw_input_validation(lib):
     assert lib.sfd_set_raw_input(h, 85, 32) == lib_mod.SFD_ERR_INVALID_ARG
     assert b"real-input" in lib.sfd_last_error()
     assert lib.sfd_destroy(h) == 0
+
+
+def test_noalloc_rejects_plans_larger_than_its_scratch(lib):
+    """The no-allocation entry point checks the plan's workspace against its
+    static array before any HIP call: the 64-view batch (370 MiB) does not
+    fit the 64 MiB array."""
+    import workloads
+    import paper_1001_4309_amd as sfd
+
+    assert lib.sfd_noalloc_capacity() == 64 << 20
+    w = workloads.config3()
+    h = sfd.sfd_plan(w.wavelength, w.holo_grid, len(w.holograms), w.views,
+                     lib_mod.SFD_IN_REAL_F32 | lib_mod.SFD_OUT_INTENSITY)
+    try:
+        assert sfd.sfd_workspace_size(h) > lib.sfd_noalloc_capacity()
+        outs = (ctypes.c_void_p * len(w.views))(*([16] * len(w.views)))
+        st = lib.sfd_reconstruct_noalloc(h, ctypes.c_void_p(16), None, outs, None)
+        assert st == lib_mod.SFD_ERR_WORKSPACE
+        assert b"scratch" in lib.sfd_last_error()
+        assert lib.sfd_reconstruct_noalloc(None, ctypes.c_void_p(16), None, outs, None) == lib_mod.SFD_ERR_INVALID_ARG
+    finally:
+        sfd.sfd_destroy(h)
