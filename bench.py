@@ -356,7 +356,8 @@ def measure(w, dev, args, steps: int, warmup: int, config: int, tune: bool = Tru
             if key == "launch":
                 plan.set_launch(g == "persistent")
             elif key == "lengths":
-                plan.set_lengths(g == "smooth")
+                plan.set_lengths(0 if g == "pow2" else
+                                 sum({"1280": 1, "1536": 2, "1792": 4}[x] for x in g.split(":")[1].split("+")))
             else:
                 plan.set_schedule(int(key[3:]), key.startswith("col"), int(g))
     elif tune:

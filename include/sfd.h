@@ -85,10 +85,12 @@ enum {
   SFD_PER_VIEW_LAUNCH = 1u << 5, /* launch the kernels one view at a time (baseline for batching) */
   SFD_EAGER = 1u << 6,           /* batched calls launch their kernels directly instead of replaying
                                     the plan's HIP graph */
-  SFD_REUSE_TABLES = 1u << 7     /* streaming (the repeated steps 1-11 of Section 2.2): the chirp
+  SFD_REUSE_TABLES = 1u << 7,    /* streaming (the repeated steps 1-11 of Section 2.2): the chirp
                                     tables and kernel spectra of a call are kept for the next call on
                                     the same workspace when its distances are the same, so that call
                                     runs only the hologram copy and the two passes */
+  SFD_WITH_BACKWARD = 1u << 8    /* real-hologram plans: lay out the workspace for sfd_backward too
+                                    (complex-input plans always have it) */
 };
 
 /*
@@ -135,9 +137,10 @@ sfd_status sfd_view_lengths(sfd_plan_t plan, int32_t v, int32_t* lx, int32_t* ly
  *   workspace   device, >= sfd_workspace_size bytes, 256-byte aligned
  *   ws_bytes    size of workspace in bytes
  *   stream      HIP stream the work is enqueued on (0 = null stream)
- * Batched plans (no SFD_PER_VIEW_LAUNCH, no SFD_EAGER) record their kernel
- * sequence once per workspace into a HIP graph owned by the plan and replay
- * it on every later call; the kernels read the call's pointers and distances
+ * The persistent schedule (see sfd_set_launch) is one kernel launched
+ * directly.  The pass schedule of batched plans (no SFD_PER_VIEW_LAUNCH, no
+ * SFD_EAGER) records its kernel sequence once per workspace into a HIP graph
+ * owned by the plan and replays it on every later call; the kernels read the call's pointers and distances
  * from descriptors that each call copies into the workspace first (on
  * ``stream``, only when they changed), so one graph serves every call.  When
  * ``stream`` is being captured by the caller, or kernel timing is on, the
@@ -157,17 +160,21 @@ sfd_status sfd_reconstruct(sfd_plan_t plan, const void* holo, const double* z_or
  * Gradients of a real loss through reconstruct: the adjoint (conjugate chirps
  * and the transposed scaled convolution, A(z)^H = (px0 py0)/(px1 py1) A(-z)
  * with the two planes swapped) and the derivative with respect to each
- * view's z.  Requires a plan made with SFD_IN_C64.
+ * view's z.  Requires a plan made with SFD_IN_C64, or with SFD_IN_REAL_F32
+ * and SFD_WITH_BACKWARD (not with sfd_set_raw_input frames).
  *   grad_out    host array of n_views device pointers.  If field_out is NULL
  *               each is complex64 [ny][nx]: g = dL/dRe(u1) + i dL/dIm(u1).
  *               Otherwise each is float32 dL/dI and g = 2 (dL/dI) u1 is formed
  *               on the device.
  *   field_out   NULL, or host array of n_views device pointers to the complex64
  *               fields u1 of the forward call (SFD_OUT_FIELD plan or saved)
- *   holo        device, the forward's complex64 inputs (needed for dL/dz)
+ *   holo        device, the forward's inputs (complex64, or float32 for a real
+ *               plan; needed for dL/dz)
  *   z_or_null   as in sfd_reconstruct
- *   grad_in     device, n_holo x [ny][nx] complex64: sum over the views of each
- *               hologram of A^H g (PyTorch's convention for complex inputs)
+ *   grad_in     device, n_holo x [ny][nx]: sum over the views of each hologram
+ *               of A^H g, complex64 (PyTorch's convention for complex inputs);
+ *               for a real plan float32, its real part (the gradient with
+ *               respect to a real input)
  *   grad_z      device, n_views doubles receiving dL/dz, or NULL to skip the
  *               z-derivative work
  */
@@ -185,7 +192,12 @@ sfd_status sfd_backward(sfd_plan_t plan, void* const* grad_out, void* const* fie
  * that later plans with the same hologram grid, view sizes and flags start
  * from.  Arguments as in sfd_reconstruct; outputs are overwritten.
  * Synchronises ``stream``.  The workspace layout does not change, so the same
- * workspace stays valid.
+ * workspace stays valid.  When the environment variable SFD_TUNE_CACHE names
+ * a file, the result is also written there (JSON, keyed by the target
+ * architecture, the schedule version, the hologram grid and count, the flags
+ * and the view sizes: the things the padded lengths follow from), and
+ * sfd_plan starts new plans of the same key from it in later processes; a
+ * file that does not parse is ignored (and replaced by the next autotune).
  *   reps   timed forwards per candidate, 1..1000
  */
 sfd_status sfd_autotune(sfd_plan_t plan, const void* holo, void* const* out, void* workspace,
@@ -325,13 +337,18 @@ sfd_status sfd_launch_mode(sfd_plan_t plan, int32_t* mode, int32_t* persistent_a
 /*
  * Length policy (the radix choice of the schedule).  Any padded length
  * L >= N0 + N1 - 1 evaluates the same linear convolution (Section 2.2,
- * steps 2 and 9).  smooth != 0 (the default): the smallest supported length,
- * which between 1024 and 2048 may be 1280 = 2^8 5, 1536 = 2^9 3 or
- * 1792 = 2^8 7 (transforms closing with a radix-20, -24 or -28 stage);
- * smooth == 0: powers of two only (the paper's doubled grid).  The
- * workspace is sized for both, so the same workspace stays valid.
- * sfd_autotune keeps the faster policy.
+ * steps 2 and 9).  Each axis takes the smallest supported length that the
+ * policy allows: powers of two always, and the smooth lengths named by the
+ * mask smooth: SFD_SMOOTH_1280 = 2^8 5, SFD_SMOOTH_1536 = 2^9 3,
+ * SFD_SMOOTH_1792 = 2^8 7 (transforms closing with a radix-20, -24 or -28
+ * stage).  0 is the paper's doubled grid (powers of two only).  Default:
+ * SFD_SMOOTH_1280 (the one smooth length measured faster than 2048 on
+ * gfx950).  The workspace is sized for every policy, so the same workspace
+ * stays valid.  sfd_autotune switches each smooth length that changes some
+ * view's length on or off and keeps the faster setting.  Errors:
+ * SFD_ERR_INVALID_ARG (bits other than the three).
  */
+enum { SFD_SMOOTH_1280 = 1, SFD_SMOOTH_1536 = 2, SFD_SMOOTH_1792 = 4, SFD_SMOOTH_ALL = 7 };
 sfd_status sfd_set_length_policy(sfd_plan_t plan, int32_t smooth);
 sfd_status sfd_length_policy(sfd_plan_t plan, int32_t* smooth);
 

@@ -22,7 +22,8 @@ import torch
 
 from . import _lib
 from ._lib import (SFD_EAGER, SFD_IN_C64, SFD_IN_REAL_F32, SFD_OUT_FIELD, SFD_OUT_INTENSITY,  # noqa: F401
-                   SFD_PER_VIEW_LAUNCH, SFD_PHASE_FP32, SFD_REUSE_TABLES, SfdError, SfdGrid, SfdView)
+                   SFD_PER_VIEW_LAUNCH, SFD_PHASE_FP32, SFD_REUSE_TABLES, SFD_SMOOTH_1280, SFD_SMOOTH_1536,
+                   SFD_SMOOTH_1792, SFD_SMOOTH_ALL, SFD_WITH_BACKWARD, SfdError, SfdGrid, SfdView)
 
 __all__ = ["Plan", "SFDFunction", "sfd_plan", "sfd_workspace_size", "sfd_view_lengths", "sfd_reconstruct",
            "sfd_backward", "sfd_autotune", "sfd_schedule", "sfd_set_schedule", "sfd_tile_widths",
@@ -176,16 +177,18 @@ def sfd_launch_mode(plan):
     return int(m.value), bool(a.value)
 
 
-def sfd_set_length_policy(plan, smooth: bool) -> None:
-    _lib.check(_lib.load().sfd_set_length_policy(plan, 1 if smooth else 0))
+def sfd_set_length_policy(plan, smooth: int) -> None:
+    """smooth: mask of SFD_SMOOTH_1280 | SFD_SMOOTH_1536 | SFD_SMOOTH_1792
+    (0: powers of two only)."""
+    _lib.check(_lib.load().sfd_set_length_policy(plan, int(smooth)))
 
 
-def sfd_length_policy(plan) -> bool:
-    """True when the plan uses the smooth lengths (1280, 1536, 1792) where
+def sfd_length_policy(plan) -> int:
+    """Mask of the smooth lengths (1280, 1536, 1792) the plan may use where
     they are shorter than the next power of two."""
     v = ctypes.c_int32()
     _lib.check(_lib.load().sfd_length_policy(plan, ctypes.byref(v)))
-    return bool(v.value)
+    return int(v.value)
 
 
 def sfd_sync_faults(plan, workspace: torch.Tensor, clear: bool = False) -> int:
@@ -212,7 +215,7 @@ class Plan:
     def __init__(self, wavelength: float, holo_grid, n_holo: int, views: Sequence, *,
                  outputs: str = "intensity", complex_input: bool = False, phase_fp32: bool = False,
                  per_view_launch: bool = False, eager: bool = False, reuse_tables: bool = False,
-                 raw_width: Optional[int] = None, raw_bits: int = 32, device=None):
+                 raw_width: Optional[int] = None, raw_bits: int = 32, backward: bool = False, device=None):
         if outputs not in ("intensity", "field", "both"):
             raise ValueError("outputs must be 'intensity', 'field' or 'both'")
         self.device = torch.device(device if device is not None else "cuda")
@@ -233,6 +236,8 @@ class Plan:
             flags |= SFD_EAGER
         if reuse_tables:
             flags |= SFD_REUSE_TABLES
+        if backward and not complex_input:
+            flags |= SFD_WITH_BACKWARD
         self.flags = flags
         self.handle = None
         self.handle = sfd_plan(wavelength, holo_grid, n_holo, self.views, flags)
@@ -271,13 +276,18 @@ class Plan:
         m, avail = sfd_launch_mode(self.handle)
         return ("persistent" if m == _lib.SFD_LAUNCH_PERSISTENT else "passes"), avail
 
-    def set_lengths(self, smooth: bool) -> None:
-        """Length policy: smooth lengths (1280, 1536, 1792) where shorter, or
-        powers of two only; the workspace stays valid."""
+    def set_lengths(self, smooth) -> None:
+        """Length policy: a mask of SFD_SMOOTH_* (True: all three smooth
+        lengths, False: powers of two only); the workspace stays valid."""
+        if isinstance(smooth, bool):
+            smooth = _lib.SFD_SMOOTH_ALL if smooth else 0
         sfd_set_length_policy(self.handle, smooth)
 
     def length_policy(self) -> str:
-        return "smooth" if sfd_length_policy(self.handle) else "pow2"
+        """"pow2", or "smooth:" and the smooth lengths allowed."""
+        m = sfd_length_policy(self.handle)
+        on = [str(L) for b, L in ((1, 1280), (2, 1536), (4, 1792)) if m & b]
+        return "smooth:" + ",".join(on) if on else "pow2"
 
     def sync_faults(self, clear: bool = False) -> int:
         """Dependency waits of persistent launches that gave up on this
@@ -359,7 +369,8 @@ class Plan:
         holo = self._check_holo(holo)
         self._check_z(z)
         g = self.holo_grid
-        grad_in = torch.empty((self.n_holo, g.ny, g.nx), dtype=torch.complex64, device=self.device)
+        # Complex holograms get the complex gradient; real ones its real part.
+        grad_in = torch.empty((self.n_holo, g.ny, g.nx), dtype=self.input_dtype, device=self.device)
         gz = torch.empty(len(self.views), dtype=torch.float64, device=self.device) if grad_z else None
         sfd_backward(self.handle, [t.contiguous() for t in grad_out],
                      None if field_out is None else [t.contiguous() for t in field_out],
@@ -386,14 +397,15 @@ class Plan:
 
 class SFDFunction(torch.autograd.Function):
     """I_v = |A_v(z_v) u_{holo(v)}|^2 for every view, differentiable in the
-    complex input fields and in z.  ``plan`` must have complex input and
-    ``outputs="both"``: the library writes each intensity and keeps the field
-    for the backward pass.  Returns one intensity tensor per view."""
+    input fields (complex, or real holograms) and in z.  ``plan`` must have
+    ``outputs="both"`` (the library writes each intensity and keeps the field
+    for the backward pass) and, for real input, ``backward=True``.  Returns
+    one intensity tensor per view."""
 
     @staticmethod
     def forward(ctx, fields: torch.Tensor, z: torch.Tensor, plan: "Plan"):
-        if not plan.complex_input or plan.outputs != "both":
-            raise ValueError("SFDFunction needs a plan with complex_input=True and outputs='both'")
+        if plan.outputs != "both" or not (plan.complex_input or plan.flags & SFD_WITH_BACKWARD):
+            raise ValueError("SFDFunction needs a plan with outputs='both' and complex_input=True or backward=True")
         zl = z.detach().to("cpu", torch.float64).tolist()
         res = plan.reconstruct(fields, zl)
         nv = len(plan.views)

@@ -25,6 +25,9 @@ SFD_PHASE_FP32 = 1 << 4
 SFD_PER_VIEW_LAUNCH = 1 << 5
 SFD_EAGER = 1 << 6
 SFD_REUSE_TABLES = 1 << 7
+SFD_WITH_BACKWARD = 1 << 8
+
+SFD_SMOOTH_1280, SFD_SMOOTH_1536, SFD_SMOOTH_1792, SFD_SMOOTH_ALL = 1, 2, 4, 7
 
 EXPORTED = ["sfd_plan", "sfd_workspace_size", "sfd_view_lengths", "sfd_reconstruct",
             "sfd_backward", "sfd_autotune", "sfd_schedule", "sfd_set_schedule", "sfd_tile_widths",

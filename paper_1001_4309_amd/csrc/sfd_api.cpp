@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <atomic>
 #include <map>
@@ -61,13 +62,23 @@ bool grid_ok(const sfd_grid& g, std::string* why, const char* what) {
 // smooth lengths 1280 = 2^8 5, 1536 = 2^9 3, 1792 = 2^8 7.
 constexpr int kLengths[] = {64, 128, 256, 512, 1024, 1280, 1536, 1792, 2048, 4096, 8192};
 
+// Length policy: a mask of the smooth lengths a plan may use (bit 0: 1280,
+// bit 1: 1536, bit 2: 1792); 0 keeps to powers of two (the paper's
+// doubling).  The default allows 1280 only: measured per view at the paper's
+// 1024-sample holograms, 1280 (radices 4, 4, 4, 20) beats 2048 while 1536
+// (8, 8, 24) only matches it and 1792 (4, 4, 4, 28) loses to it.
+constexpr int kSmoothAll = 7, kSmoothDefault = 1;
+bool smooth_allowed(int L, int mask) {
+  return (L & (L - 1)) == 0 || (L == 1280 && (mask & 1)) || (L == 1536 && (mask & 2)) || (L == 1792 && (mask & 4));
+}
+
 // Smallest supported padded length for a linear convolution of n0 inputs
-// onto n1 outputs (reading of steps 2 and 9: any L >= n0 + n1 - 1 is exact).
-// smooth = false: powers of two only (the paper's doubling).
-int choose_length(int n0, int n1, bool smooth = true) {
+// onto n1 outputs (reading of steps 2 and 9: any L >= n0 + n1 - 1 is exact)
+// among those the mask allows.
+int choose_length(int n0, int n1, int mask = kSmoothDefault) {
   const long need = (long)n0 + (long)n1 - 1;
   for (int L : kLengths)
-    if (L >= need && (smooth || (L & (L - 1)) == 0)) return L;
+    if (L >= need && smooth_allowed(L, mask)) return L;
   return -1;
 }
 
@@ -131,9 +142,177 @@ int inter_ld(int n0x) { return (n0x + 15) / 16 * 16 + 16; }
 }  // namespace
 
 namespace {
-// Tuned tile widths, keyed by the plan's shapes: (col, L, shape signature).
+// Tuned schedules, keyed by the plan's shapes: (col, L, shape signature) ->
+// tile width; (2, 0, signature) -> persistent launch; (3, 0, signature) ->
+// smooth lengths.
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, std::string>, int> g_tuned;
+
+// ---- Persisted schedule cache (environment variable SFD_TUNE_CACHE) ------
+// A JSON file {"format": "sfd-schedule-cache", "entries": {KEY: {"col":
+// {"L": width, ...}, "row": {...}, "persist": 0|1, "smooth": mask}, ...}}
+// with KEY = "<arch>|v<schedule version>|<hologram grid, hologram count,
+// flags, view sizes>".  sfd_autotune writes it, sfd_plan reads it; a file
+// that does not parse (or another format) is ignored, and rewritten by the
+// next autotune.
+constexpr int kScheduleVersion = 2;
+constexpr const char* kArch = "gfx950";
+
+// Minimal JSON reader for that file: objects, strings without escapes,
+// integers.  Returns false on anything else.
+struct JVal {
+  enum Kind { kObj, kStr, kInt } kind = kInt;
+  long long i = 0;
+  std::string s;
+  std::map<std::string, JVal> o;
+};
+struct JReader {
+  const std::string& t;
+  size_t p = 0;
+  void ws() {
+    while (p < t.size() && (t[p] == ' ' || t[p] == '\n' || t[p] == '\t' || t[p] == '\r')) ++p;
+  }
+  bool str(std::string* out) {
+    ws();
+    if (p >= t.size() || t[p] != '"') return false;
+    const size_t e = t.find('"', p + 1);
+    if (e == std::string::npos) return false;
+    *out = t.substr(p + 1, e - p - 1);
+    if (out->find('\\') != std::string::npos) return false;
+    p = e + 1;
+    return true;
+  }
+  bool val(JVal* v, int depth) {
+    ws();
+    if (p >= t.size() || depth > 8) return false;
+    if (t[p] == '{') {
+      v->kind = JVal::kObj;
+      ++p;
+      ws();
+      if (p < t.size() && t[p] == '}') return ++p, true;
+      for (;;) {
+        std::string k;
+        if (!str(&k)) return false;
+        ws();
+        if (p >= t.size() || t[p] != ':') return false;
+        ++p;
+        if (!val(&v->o[k], depth + 1)) return false;
+        ws();
+        if (p < t.size() && t[p] == ',') { ++p; continue; }
+        if (p < t.size() && t[p] == '}') return ++p, true;
+        return false;
+      }
+    }
+    if (t[p] == '"') {
+      v->kind = JVal::kStr;
+      return str(&v->s);
+    }
+    size_t e = p;
+    if (e < t.size() && t[e] == '-') ++e;
+    while (e < t.size() && t[e] >= '0' && t[e] <= '9') ++e;
+    if (e == p) return false;
+    v->kind = JVal::kInt;
+    v->i = std::stoll(t.substr(p, e - p));
+    p = e;
+    return true;
+  }
+};
+
+bool read_cache(const std::string& path, JVal* root) {
+  FILE* f = std::fopen(path.c_str(), "rb");
+  if (!f) return false;
+  std::string text;
+  char buf[4096];
+  size_t n;
+  while ((n = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, n);
+  std::fclose(f);
+  JReader r{text};
+  if (!r.val(root, 0)) return false;
+  r.ws();
+  if (r.p != text.size() || root->kind != JVal::kObj) return false;
+  const auto fm = root->o.find("format");
+  if (fm == root->o.end() || fm->second.kind != JVal::kStr || fm->second.s != "sfd-schedule-cache") return false;
+  const auto en = root->o.find("entries");
+  return en != root->o.end() && en->second.kind == JVal::kObj;
+}
+
+std::string cache_key(const std::string& sig) {
+  return std::string(kArch) + "|v" + std::to_string(kScheduleVersion) + "|" + sig;
+}
+
+// Entries of the cache file for ``sig`` into the in-process table (caller
+// holds g_tune_mu).
+void load_cached(const std::string& sig) {
+  const char* path = std::getenv("SFD_TUNE_CACHE");
+  if (!path || !*path) return;
+  JVal root;
+  if (!read_cache(path, &root)) return;
+  const auto& entries = root.o["entries"].o;
+  const auto it = entries.find(cache_key(sig));
+  if (it == entries.end() || it->second.kind != JVal::kObj) return;
+  const JVal& e = it->second;
+  for (int col = 0; col < 2; ++col) {
+    const auto pc = e.o.find(col ? "col" : "row");
+    if (pc == e.o.end() || pc->second.kind != JVal::kObj) continue;
+    for (const auto& kv : pc->second.o)
+      if (kv.second.kind == JVal::kInt && kv.second.i > 0)
+        g_tuned[std::make_tuple(col, std::atoi(kv.first.c_str()), sig)] = (int)kv.second.i;
+  }
+  for (const char* k : {"persist", "smooth"}) {
+    const auto pk = e.o.find(k);
+    if (pk != e.o.end() && pk->second.kind == JVal::kInt && pk->second.i >= 0 && pk->second.i <= kSmoothAll)
+      g_tuned[std::make_tuple(k[0] == 'p' ? 2 : 3, 0, sig)] = k[0] == 'p' ? pk->second.i != 0 : (int)pk->second.i;
+  }
+}
+
+// Write the plan's schedule into the cache file (other entries kept when
+// the file parses; an unparsable file is replaced).
+void store_cached(const std::string& sig, const std::map<int, int>& gcol, const std::map<int, int>& grow,
+                  bool persist, int smooth) {
+  const char* path = std::getenv("SFD_TUNE_CACHE");
+  if (!path || !*path) return;
+  JVal root;
+  std::map<std::string, std::string> kept;  // key -> serialised entry
+  auto ser = [](const JVal& v, auto& self) -> std::string {
+    if (v.kind == JVal::kInt) return std::to_string(v.i);
+    if (v.kind == JVal::kStr) return "\"" + v.s + "\"";
+    std::string out = "{";
+    bool first = true;
+    for (const auto& kv : v.o) {
+      out += (first ? "" : ", ") + std::string("\"") + kv.first + "\": " + self(kv.second, self);
+      first = false;
+    }
+    return out + "}";
+  };
+  if (read_cache(path, &root))
+    for (const auto& kv : root.o["entries"].o) kept[kv.first] = ser(kv.second, ser);
+  auto widths = [](const std::map<int, int>& m) {
+    std::string out = "{";
+    bool first = true;
+    for (const auto& kv : m) {
+      out += (first ? "" : ", ") + std::string("\"") + std::to_string(kv.first) + "\": " + std::to_string(kv.second);
+      first = false;
+    }
+    return out + "}";
+  };
+  kept[cache_key(sig)] = "{\"col\": " + widths(gcol) + ", \"row\": " + widths(grow) +
+                         ", \"persist\": " + (persist ? "1" : "0") + ", \"smooth\": " + std::to_string(smooth) + "}";
+  std::string text = "{\"format\": \"sfd-schedule-cache\", \"version\": " + std::to_string(kScheduleVersion) +
+                     ", \"entries\": {\n";
+  bool first = true;
+  for (const auto& kv : kept) {
+    text += (first ? "  \"" : ",\n  \"") + kv.first + "\": " + kv.second;
+    first = false;
+  }
+  text += "\n}}\n";
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "wb");
+  if (!f) return;
+  const bool ok = std::fwrite(text.data(), 1, text.size(), f) == text.size();
+  std::fclose(f);
+  if (ok) std::rename(tmp.c_str(), path);
+  else std::remove(tmp.c_str());
+}
 }  // namespace
 
 namespace {
@@ -193,7 +372,7 @@ struct sfd_plan_s {
 
   // Persistent launch (batched plans whose passes all have persistent
   // shapes): counters in the workspace, zeroed once per workspace.
-  bool smooth = true;        // length policy (see set_lengths)
+  int smooth = kSmoothDefault;  // length policy: smooth lengths allowed (see choose_length)
   bool persist_ok = false;   // the plan's shapes allow it
   bool persist = false;      // the schedule uses it
   size_t sync_off = 0;
@@ -461,6 +640,12 @@ sfd_status build_descs(sfd_plan_s* P, const void* holo, const double* z, void* c
     jc.colscale = reinterpret_cast<const float2*>(ws + L.prex);
     jc.view = v;
     jc.copy = L.tile;
+    if (P->persist && in_real) {
+      // The persistent launch reads real holograms in place, row-major.
+      jc.in = static_cast<const char*>(holo) + (size_t)w.holo * holo_stride;
+      jc.in_ld = P->raw_nx > 0 ? P->raw_nx : h.nx;
+      jc.in_fmt = P->raw_nx > 0 ? (P->raw_bits == 32 ? 33 : P->raw_bits) : 32;
+    }
     py.push_back({L.ly, jc});
 
     sfd::RowJob jr{};
@@ -588,7 +773,7 @@ void pack_persist(const sfd_plan_s* P, CallDescs* D, char* ws, bool tables, std:
     t += count;
   };
   if (tables) add(sfd::kItemSetup, 2 * V, 0, 0, nullptr, nullptr);  // spectra, then tables, per view
-  add(sfd::kItemStrip, P->nstrips, 0, 0, nullptr, nullptr);
+  if (P->nstrips > 0) add(sfd::kItemStrip, P->nstrips, 0, 0, nullptr, nullptr);
   const auto* d_rows = reinterpret_cast<const sfd::RowJob*>(dbase + off_rows);
   const auto* d_pass = reinterpret_cast<const sfd::PassArgs*>(dbase + off_pass);
   for (int col = 1; col >= 0; --col) {
@@ -784,9 +969,9 @@ bool persist_eligible(const sfd_plan_s* P) {
   return segs <= sfd::kMaxSegments;
 }
 
-// Length policy: smooth lengths where they are shorter (default), or the
-// paper's powers of two.  Per-view arrays are sized for the longer choice.
-void set_lengths(sfd_plan_s* P, bool smooth) {
+// Length policy (see choose_length).  Per-view arrays are sized for the
+// longest choice (powers of two).
+void set_lengths(sfd_plan_s* P, int smooth) {
   P->smooth = smooth;
   for (size_t v = 0; v < P->views.size(); ++v) {
     P->lay[v].lx = choose_length(P->holo.nx, P->views[v].out.nx, smooth);
@@ -803,7 +988,8 @@ sfd_status launch_forward(sfd_plan_s* P, const CallDescs& D, char* ws, const sfd
   sfd_status st;
   if (P->persist) {
     SFD_TIMED(P, SFD_KERNEL_PERSIST, stream,
-              sfd::launch_persist(D.d_pa, std::max(1, std::min(D.persist_total, P->persist_grid)), stream));
+              sfd::launch_persist(D.d_pa, std::max(1, std::min(D.persist_total, P->persist_grid)),
+                                  (P->flags & SFD_IN_C64) != 0, stream));
     return SFD_OK;
   }
   if ((st = launch_setup_for(P, D, ws, d_axis, d_tw, d_tiles, 0, tables ? (int)D.axis.size() : 0, false, 0,
@@ -850,7 +1036,8 @@ sfd_status run_backward(sfd_plan_s* P, void* const* grad_out, void* const* field
   const sfd_grid& h = P->holo;
   const bool want_z = grad_z != nullptr;
   const bool from_i = field_out != nullptr;  // grad_out holds dL/dI
-  const size_t holo_stride = (size_t)h.nx * h.ny * sizeof(float2);
+  const bool real_in = (P->flags & SFD_IN_C64) == 0;  // a real hologram: its gradient is Re(A^H g)
+  const size_t holo_stride = (size_t)h.nx * h.ny * (real_in ? sizeof(float) : sizeof(float2));
   const double k = 2.0 * M_PI / P->lam;
   CallDescs D;
 
@@ -930,7 +1117,7 @@ sfd_status run_backward(sfd_plan_s* P, void* const* grad_out, void* const* field
       j.nx = h.nx;
       j.ny = h.ny;
       j.ld = col_ld(h.ny);
-      j.complex_in = 1;
+      j.complex_in = real_in ? 0 : 1;
       D.tiles.push_back(j);
     }
   const int gtile0 = (int)D.tiles.size();
@@ -986,6 +1173,10 @@ sfd_status run_backward(sfd_plan_s* P, void* const* grad_out, void* const* field
                                 w.out.ny)});
       cols.push_back({L.ly, col(ws + T.off, col_ld(h.ny), B.wm, ldh, B.preym, B.hyf, B.postyf, h.nx, h.ny,
                                 w.out.ny)});
+      if (real_in) {
+        cols[cols.size() - 1].second.mode |= sfd::kInReal;
+        cols[cols.size() - 2].second.mode |= sfd::kInReal;
+      }
     }
     auto row = [&](size_t in, int in_ld, size_t pre, size_t H, size_t post, int n_rows, int n_in, int n_out,
                    int32_t mode, size_t partial) {
@@ -1009,7 +1200,7 @@ sfd_status run_backward(sfd_plan_s* P, void* const* grad_out, void* const* field
                     : static_cast<void*>(static_cast<char*>(grad_in) + (size_t)w.holo * holo_stride);
     r4.out_ld = h.nx;
     if (want_z) {
-      r4.mode |= sfd::kReduce | sfd::kRedSwap;
+      r4.mode |= sfd::kReduce | sfd::kRedSwap | (real_in ? sfd::kRedRealRef : 0);
       r4.uref = reinterpret_cast<const float2*>(u0);
       r4.red_ld = h.nx;
       r4.xp = fx.p0;
@@ -1100,8 +1291,9 @@ sfd_status run_backward(sfd_plan_s* P, void* const* grad_out, void* const* field
   std::vector<sfd::GatherJob> ga;
   std::vector<const float2*> srcs;
   for (int hh = 0; hh < P->n_holo; ++hh) {
-    if (P->holo_views[hh] == 1) continue;  // written directly by its view's adjoint pass
+    if (P->holo_views[hh] == 1 && !real_in) continue;  // written directly by its view's adjoint pass
     sfd::GatherJob j{};
+    j.real_out = real_in ? 1 : 0;
     j.src = reinterpret_cast<const float2* const*>(dbase + o_src) + srcs.size();
     j.dst = reinterpret_cast<float2*>(static_cast<char*>(grad_in) + (size_t)hh * holo_stride);
     j.n = h.nx * h.ny;
@@ -1167,7 +1359,7 @@ sfd_status sfd_plan(sfd_plan_t* plan, double wavelength, const sfd_grid* holo_gr
   if (n_views < 1) return fail(SFD_ERR_INVALID_ARG, "n_views must be >= 1");
   if (n_views > 65536) return fail(SFD_ERR_UNSUPPORTED, "at most 65536 views per plan");
   const uint32_t known = SFD_IN_REAL_F32 | SFD_IN_C64 | SFD_OUT_INTENSITY | SFD_OUT_FIELD | SFD_PHASE_FP32 |
-                         SFD_PER_VIEW_LAUNCH | SFD_EAGER | SFD_REUSE_TABLES;
+                         SFD_PER_VIEW_LAUNCH | SFD_EAGER | SFD_REUSE_TABLES | SFD_WITH_BACKWARD;
   if (flags & ~known) return fail(SFD_ERR_INVALID_ARG, "unknown flag bits");
   if (((flags & SFD_IN_REAL_F32) != 0) == ((flags & SFD_IN_C64) != 0))
     return fail(SFD_ERR_INVALID_ARG, "exactly one of SFD_IN_REAL_F32 and SFD_IN_C64 must be set");
@@ -1200,9 +1392,9 @@ sfd_status sfd_plan(sfd_plan_t* plan, double wavelength, const sfd_grid* holo_gr
   // schedule can switch policies on the same workspace.
   std::vector<int> ls;
   for (int v = 0; v < n_views; ++v)
-    for (int smooth = 0; smooth < 2; ++smooth) {
-      ls.push_back(choose_length(h.nx, views[v].out.nx, smooth != 0));
-      ls.push_back(choose_length(h.ny, views[v].out.ny, smooth != 0));
+    for (int smooth : {0, kSmoothAll}) {
+      ls.push_back(choose_length(h.nx, views[v].out.nx, smooth));
+      ls.push_back(choose_length(h.ny, views[v].out.ny, smooth));
     }
   std::sort(ls.begin(), ls.end());
   ls.erase(std::unique(ls.begin(), ls.end()), ls.end());
@@ -1256,23 +1448,27 @@ sfd_status sfd_plan(sfd_plan_t* plan, double wavelength, const sfd_grid* holo_gr
     L.hy = take(sizeof(float2) * ly2);
     L.inter = take(sizeof(float2) * (size_t)o.ny * inter_ld(h.nx));  // N1y x N0x after the y transforms
   }
-  // Persistent launch: its counters, when either length policy allows it.
+  // Persistent launch: its counters, when any length policy allows it.
   {
-    const bool ok_smooth = persist_eligible(P);
-    set_lengths(P, false);
-    const bool ok_pow2 = persist_eligible(P);
-    set_lengths(P, true);
-    P->persist_ok = ok_smooth;
-    P->persist = ok_smooth;
-    if (ok_smooth || ok_pow2) {
-      P->nstrips = (int)P->tiles.size() * ((h.nx + sfd::kStripW - 1) / sfd::kStripW);
+    bool ok_any = false;
+    for (int mask = 0; mask <= kSmoothAll; ++mask) {
+      set_lengths(P, mask);
+      ok_any = ok_any || persist_eligible(P);
+    }
+    set_lengths(P, kSmoothDefault);
+    P->persist_ok = persist_eligible(P);
+    P->persist = P->persist_ok;
+    if (ok_any) {
+      // Strips of the column-major copy for complex holograms only: the
+      // column tiles read real holograms in place.
+      P->nstrips = (flags & SFD_IN_C64) ? (int)P->tiles.size() * ((h.nx + sfd::kStripW - 1) / sfd::kStripW) : 0;
       P->col_tiles = (h.nx + sfd::kStripW - 1) / sfd::kStripW;
       P->sync_words = sfd::persist_sync_words(n_views, P->nstrips);
       P->sync_off = off;
       off += align_up(sizeof(uint32_t) * P->sync_words);
     }
   }
-  if (flags & SFD_IN_C64) {
+  if (flags & (SFD_IN_C64 | SFD_WITH_BACKWARD)) {
     // Backward: per view its own forward, moment and adjoint tables, the
     // gradient's column tiles, three intermediates, an adjoint buffer when
     // the hologram has several views, and the reduction partials.
@@ -1311,7 +1507,9 @@ sfd_status sfd_plan(sfd_plan_t* plan, double wavelength, const sfd_grid* holo_gr
       B.wf = take(c8 * (size_t)o.ny * inter_ld(h.nx));
       B.wm = take(c8 * (size_t)o.ny * inter_ld(h.nx));
       B.wa = take(c8 * (size_t)h.ny * inter_ld(o.nx));
-      B.vbuf = P->holo_views[views[v].holo] > 1 ? take(c8 * (size_t)h.nx * h.ny) : 0;
+      // Adjoint buffer: several views sum into a hologram's gradient, and a
+      // real hologram's gradient is the real part of the complex adjoint.
+      B.vbuf = (P->holo_views[views[v].holo] > 1 || !(flags & SFD_IN_C64)) ? take(c8 * (size_t)h.nx * h.ny) : 0;
       // Partials: room for the most row-pass tiles any schedule launches.
       const int gmin = std::min(min_tile_width(lx, false), min_tile_width(choose_length(h.nx, o.nx), false));
       B.nt_r = (o.ny + gmin - 1) / gmin;
@@ -1332,14 +1530,15 @@ sfd_status sfd_plan(sfd_plan_t* plan, double wavelength, const sfd_grid* holo_gr
              std::to_string(views[v].holo);
     P->shape_sig = sig;
     std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (g_tuned.find(std::make_tuple(2, 0, sig)) == g_tuned.end()) load_cached(sig);
     for (int L : ls)
       for (int col = 0; col < 2; ++col) {
         const auto it = g_tuned.find(std::make_tuple(col, L, sig));
         if (it != g_tuned.end()) (col ? P->gcol : P->grow)[L] = it->second;
       }
     const auto il = g_tuned.find(std::make_tuple(3, 0, sig));
-    if (il != g_tuned.end() && (il->second != 0) != P->smooth) {
-      set_lengths(P, il->second != 0);
+    if (il != g_tuned.end() && il->second != P->smooth) {
+      set_lengths(P, il->second);
       P->persist_ok = persist_eligible(P);
       P->persist = P->persist_ok;
     }
@@ -1467,7 +1666,10 @@ sfd_status sfd::reconstruct_impl(sfd_plan_s* plan, const void* holo, const doubl
     }
     return SFD_OK;
   }
-  const bool use_graph = !(plan->flags & SFD_EAGER) && !plan->profiling && !no_alloc;
+  // The persistent schedule is one kernel: it is launched directly (a graph
+  // replay of that one node measured about 10 us slower per call than the
+  // launch itself).  The pass schedule replays its recorded launches.
+  const bool use_graph = !(plan->flags & SFD_EAGER) && !plan->profiling && !no_alloc && !plan->persist;
   if (use_graph) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     SFD_HIP_TRY(hipStreamIsCapturing(stream, &cs));
@@ -1515,7 +1717,9 @@ sfd_status sfd_backward(sfd_plan_t plan, void* const* grad_out, void* const* fie
   g_err.clear();
   sfd_status st = check_common(plan, workspace, ws_bytes);
   if (st != SFD_OK) return st;
-  if (!(plan->flags & SFD_IN_C64)) return fail(SFD_ERR_INVALID_ARG, "sfd_backward needs a plan made with SFD_IN_C64");
+  if (!(plan->flags & (SFD_IN_C64 | SFD_WITH_BACKWARD)))
+    return fail(SFD_ERR_INVALID_ARG, "sfd_backward needs a plan made with SFD_IN_C64 or SFD_WITH_BACKWARD");
+  if (plan->raw_nx > 0) return fail(SFD_ERR_INVALID_ARG, "sfd_backward does not take raw camera frames");
   if (!grad_out) return fail(SFD_ERR_INVALID_ARG, "grad_out is NULL");
   if (!holo || reinterpret_cast<uintptr_t>(holo) % 16)
     return fail(SFD_ERR_INVALID_ARG, "holo must be a non-NULL 16-byte aligned device pointer");
@@ -1620,30 +1824,42 @@ sfd_status sfd_autotune(sfd_plan_t plan, const void* holo, void* const* out, voi
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tuned[std::make_tuple(2, 0, plan->shape_sig)] = keep ? 1 : 0;
   }
-  // Radix choice: the other length policy (powers of two only, or the
-  // smooth lengths with their radix-3, -5 and -7 closing stages) where it
-  // gives other lengths, on its default tile widths and, where available,
-  // the persistent launch; the faster policy is kept.
-  bool differ = false;
-  for (size_t v = 0; v < plan->views.size(); ++v) {
-    const sfd_grid& o = plan->views[v].out;
-    differ = differ || choose_length(plan->holo.nx, o.nx, true) != choose_length(plan->holo.nx, o.nx, false) ||
-             choose_length(plan->holo.ny, o.ny, true) != choose_length(plan->holo.ny, o.ny, false);
-  }
-  if (differ) {
+  // Radix choice: each smooth length (1280, 1536, 1792 with their radix-5,
+  // -3 and -7 closing stages) is switched on or off in turn where that
+  // changes some view's padded length, timed on its default tile widths and,
+  // where available, the persistent launch; the faster setting is kept.
+  bool tried = false;
+  for (int bit = 1; bit <= 4; bit <<= 1) {
+    const int other = plan->smooth ^ bit;
+    bool differ = false;
+    for (size_t v = 0; v < plan->views.size(); ++v) {
+      const sfd_grid& o = plan->views[v].out;
+      differ = differ || choose_length(plan->holo.nx, o.nx, plan->smooth) != choose_length(plan->holo.nx, o.nx, other) ||
+               choose_length(plan->holo.ny, o.ny, plan->smooth) != choose_length(plan->holo.ny, o.ny, other);
+    }
+    if (!differ) continue;
+    tried = true;
     float t_cur = 0.f, t_other = 0.f;
     if ((st = timed(&t_cur)) != SFD_OK) return st;
-    const bool cur_smooth = plan->smooth, cur_persist = plan->persist;
-    if ((st = sfd_set_length_policy(plan, cur_smooth ? 0 : 1)) != SFD_OK) return st;
+    const int cur_mask = plan->smooth;
+    const bool cur_persist = plan->persist;
+    if ((st = sfd_set_length_policy(plan, other)) != SFD_OK) return st;
     if (plan->persist_ok && (st = sfd_set_launch(plan, SFD_LAUNCH_PERSISTENT)) != SFD_OK) return st;
     if ((st = timed(&t_other)) != SFD_OK) return st;
     if (t_cur <= t_other) {
-      if ((st = sfd_set_length_policy(plan, cur_smooth ? 1 : 0)) != SFD_OK) return st;
+      if ((st = sfd_set_length_policy(plan, cur_mask)) != SFD_OK) return st;
       if ((st = sfd_set_launch(plan, cur_persist ? SFD_LAUNCH_PERSISTENT : SFD_LAUNCH_PASSES)) != SFD_OK) return st;
     }
+  }
+  if (tried) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tuned[std::make_tuple(3, 0, plan->shape_sig)] = plan->smooth ? 1 : 0;
+    g_tuned[std::make_tuple(3, 0, plan->shape_sig)] = plan->smooth;
     g_tuned[std::make_tuple(2, 0, plan->shape_sig)] = plan->persist ? 1 : 0;
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[std::make_tuple(2, 0, plan->shape_sig)] = plan->persist ? 1 : 0;
+    store_cached(plan->shape_sig, plan->gcol, plan->grow, plan->persist, plan->smooth);
   }
   return SFD_OK;
 }
@@ -1706,10 +1922,10 @@ sfd_status sfd_set_launch(sfd_plan_t plan, int32_t mode) {
 sfd_status sfd_set_length_policy(sfd_plan_t plan, int32_t smooth) {
   g_err.clear();
   if (!plan) return fail(SFD_ERR_INVALID_ARG, "plan is NULL");
-  const bool want = smooth != 0;
-  if (want == plan->smooth) return SFD_OK;
+  if (smooth < 0 || smooth > kSmoothAll) return fail(SFD_ERR_INVALID_ARG, "length policy must be a mask of bits 0..2");
+  if (smooth == plan->smooth) return SFD_OK;
   const bool was_persist = plan->persist;
-  set_lengths(plan, want);
+  set_lengths(plan, smooth);
   plan->persist_ok = persist_eligible(plan);
   plan->persist = was_persist && plan->persist_ok;
   plan->tables_ws = nullptr;     // spectra of other lengths
@@ -1721,7 +1937,7 @@ sfd_status sfd_set_length_policy(sfd_plan_t plan, int32_t smooth) {
 sfd_status sfd_length_policy(sfd_plan_t plan, int32_t* smooth) {
   g_err.clear();
   if (!plan || !smooth) return fail(SFD_ERR_INVALID_ARG, "NULL argument");
-  *smooth = plan->smooth ? 1 : 0;
+  *smooth = plan->smooth;
   return SFD_OK;
 }
 

@@ -494,7 +494,9 @@ __device__ __forceinline__ void row_accumulate(const RowJob& J, const float2 (&v
         float2 G, V;
         if (mode & kRedSwap) {
           G = v[i];
-          V = gld(J.uref + base, (unsigned)m);
+          V = (mode & kRedRealRef)
+                  ? make_float2(gld(reinterpret_cast<const float*>(J.uref) + base, (unsigned)m), 0.f)
+                  : gld(J.uref + base, (unsigned)m);
         } else if (mode & kRedIntensity) {
           const float gi = 2.0f * gld(J.giref + base, (unsigned)m);
           G = make_float2(gi * v[i].x, gi * v[i].y);
@@ -614,6 +616,43 @@ __device__ __forceinline__ void stage_tables(float2* tws, float2* hs, float2* ps
   }
 }
 
+// A camera sample resized along x (see TileJob): row n of a frame of ns
+// samples per row, read at column c of a grid nx wide.
+template <typename S>
+__device__ __forceinline__ float resample_at(const S* in, int ns, int nx, int n, int c) {
+  double sx = ((double)c + 0.5) * (double)ns / (double)nx - 0.5;
+  sx = fmin(fmax(sx, 0.0), (double)(ns - 1));
+  const int i0 = (int)sx;
+  const int i1 = i0 + 1 < ns ? i0 + 1 : ns - 1;
+  const float wt = (float)(sx - (double)i0);
+  const float a = (float)gld(in, (unsigned)(n * ns + i0)), b = (float)gld(in, (unsigned)(n * ns + i1));
+  return fmaf(wt, b - a, a);
+}
+
+// Row-major real input of a column tile's round (RowJob::in_fmt != 0): the
+// round's NS columns from cb on, every one of the K x THREADS / NS rows, by
+// the whole workgroup (element f = tid + THREADS k is row f / NS, column
+// cb + f % NS; columns past the grid repeat its last).  Rows of NS
+// consecutive samples; the format is decided once, outside the loads.
+template <int K, int THREADS, int NS>
+__device__ __forceinline__ void fetch_rowmajor(float2 (&x)[K], const void* in, int fmt, int ld, int ncols, int cb,
+                                               int tid) {
+  auto run = [&](auto sample) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int f = tid + THREADS * k;
+      const int c = cb + f % NS;
+      x[k].x = sample(f / NS, c < ncols ? c : ncols - 1);
+    }
+  };
+  if (fmt == 32) run([&](int n, int c) { return gld(static_cast<const float*>(in), (unsigned)(n * ld + c)); });
+  else if (fmt == 8)
+    run([&](int n, int c) { return resample_at(static_cast<const unsigned char*>(in), ld, ncols, n, c); });
+  else if (fmt == 16)
+    run([&](int n, int c) { return resample_at(static_cast<const unsigned short*>(in), ld, ncols, n, c); });
+  else run([&](int n, int c) { return resample_at(static_cast<const float*>(in), ld, ncols, n, c); });
+}
+
 // The common case (input of L/2 samples) in two steps, so that the loads of
 // the next transform can be issued before the current one is computed:
 // fetch_half loads the raw first half (a real input only into .x),
@@ -672,14 +711,21 @@ struct RowLds {
       SharedTables<L>::bytes + PRE_BYTES + S::NS * row_lds_bytes<L, kSplit>() + S::NW * 32 + (PF ? 16 : 0);
 };
 
+// A call made once the body's last transform is computed, before its last
+// stores leave (the persistent launch takes its next ticket there, so that
+// the ticket's latency overlaps the stores).  NoTail does nothing.
+struct NoTail {
+  __device__ __forceinline__ void operator()() const {}
+};
+
 // tid: the thread's index in the workgroup (threadIdx.x; the persistent
 // launch passes it through an opaque move, so that nothing derived from it
 // is hoisted out of its item loop).  The same holds for col_body.
 // COH: read what other items of a persistent launch wrote (the input, H,
 // the pre- and post-chirps) with loads coherent across XCDs (gld_c).
-template <int L, int GR, int VAR, int P, bool COH = false>
+template <int L, int GR, int VAR, int P, bool COH = false, typename TAIL = NoTail>
 __device__ __forceinline__ void row_body(const PassArgs& args, const float2* __restrict__ tw, const int tile,
-                                         unsigned char* __restrict__ lds, const int tid) {
+                                         unsigned char* __restrict__ lds, const int tid, const TAIL& tail = TAIL{}) {
   using S = PassShape<L, GR, P>;
   constexpr int TPR = S::TPR;
   constexpr int R = L / TPR;
@@ -873,6 +919,7 @@ __device__ __forceinline__ void row_body(const PassArgs& args, const float2* __r
       }
     }
     if constexpr (PF) {
+      tail();
       if (prev >= 0) flush(prev, t);
     }
     if constexpr (!HALF) {
@@ -905,9 +952,16 @@ struct ColLds {
   static constexpr int bytes = SharedTables<L>::bytes + PRE_BYTES + XCH_BYTES;
 };
 
-template <int L, int GC, int VAR, int P, bool COH = false>
+// RM: a persistent launch's real-hologram column tiles read the hologram
+// itself, row-major (RowJob::in_fmt), and turn each round's columns around
+// in an LDS area after the tile's own (kColRmBytes); no column-major copy.
+template <int L>
+constexpr int col_rm_bytes() {
+  return 8 * (FastIn<L>::RIN * FastIn<L>::TPR + 4) * 4;
+}
+template <int L, int GC, int VAR, int P, bool COH = false, bool RM = false, typename TAIL = NoTail>
 __device__ __forceinline__ void col_body(const PassArgs& args, const float2* __restrict__ tw, const int tile,
-                                         unsigned char* __restrict__ lds, const int tid0) {
+                                         unsigned char* __restrict__ lds, const int tid0, const TAIL& tail = TAIL{}) {
   using S = PassShape<L, GC, P>;
   constexpr int TPR = S::TPR;
   constexpr int R = L / TPR;
@@ -964,11 +1018,17 @@ __device__ __forceinline__ void col_body(const PassArgs& args, const float2* __r
   float2 v[R];
   float2 x[PF ? RIN : 1];
   float2 csn = make_float2(1.f, 0.f);
-  auto load = [&](int p, int t) {
+  static_assert(!RM || (PF && REAL && NS == 8), "row-major input: real, several columns per slot, 8 slots");
+  constexpr int RS = RIN * TPR + 4;  // LDS stride of a column of the round (RM)
+  float* const rmb = reinterpret_cast<float*>(lds + ColLds<L, GC, VAR, P>::bytes);
+  const int in_fmt = RM ? J.in_fmt : 0;
+  auto load = [&](int p, int t, int tw_) {
     const int c = c0 + p * NS + g;
     const int cl = c < ncols ? c : ncols - 1;
     const int64_t off = (int64_t)cl * in_ld;
-    if constexpr (PF) {
+    if constexpr (RM) {
+      fetch_rowmajor<RIN, THREADS, NS>(x, in, in_fmt, in_ld, ncols, c0 + p * NS, tw_);
+    } else if constexpr (PF) {
       fetch_half<TPR, REAL, RIN, COH>(x, in, off, t);
     } else if constexpr (FAST) {
       if constexpr (REAL) load_half<TPR, R, RIN, true>(v, static_cast<const float*>(in) + off, pre, t);
@@ -979,7 +1039,7 @@ __device__ __forceinline__ void col_body(const PassArgs& args, const float2* __r
     }
     if (colscale) csn = gld_c<COH>(colscale, (unsigned)cl);
   };
-  load(0, t);
+  load(0, t, tid0);
 
   if constexpr (T::on) {
     stage_tables<L, THREADS, PF, RIN * TPR, COH>(tws, hs, ps, tw, H, pre, tid0);
@@ -1025,6 +1085,17 @@ __device__ __forceinline__ void col_body(const PassArgs& args, const float2* __r
       float2 cs;
       if constexpr (PF) {
         cs = csn;
+        if constexpr (RM) {
+          // The round's columns turned around: slot g takes column g.
+#pragma unroll
+          for (int k = 0; k < RIN; ++k) {
+            const int f = tid + THREADS * k;
+            rmb[(f % NS) * RS + f / NS] = x[k].x;
+          }
+          __syncthreads();
+#pragma unroll
+          for (int i = 0; i < RIN; ++i) x[i].x = rmb[g * RS + tl + TPR * i];
+        }
         apply_half<TPR, R, RIN, REAL>(v, x, pre ? ps : nullptr, tl);
         sched_fence();
         if (p > 0) {
@@ -1032,9 +1103,9 @@ __device__ __forceinline__ void col_body(const PassArgs& args, const float2* __r
           // The exchanges below reuse the staging memory.
           __syncthreads();
         }
-        if (p + 1 < P) load(p + 1, tl);
+        if (p + 1 < P) load(p + 1, tl, tid);
       } else {
-        if (p > 0) load(p, tl);
+        if (p > 0) load(p, tl, tid);
         cs = csn;
       }
       fft_row<PassPlan<L>, false, kSplit, T::src, HALF && PRUNE>(v, buf, tl, twx);
@@ -1081,7 +1152,10 @@ __device__ __forceinline__ void col_body(const PassArgs& args, const float2* __r
       // The next round's exchanges reuse the staging memory (PF: after its flush).
       if (!PF && p + 1 < P) __syncthreads();
     }
-    if constexpr (PF) flush(c0 + (P - 1) * NS, tid0);
+    if constexpr (PF) {
+      tail();
+      flush(c0 + (P - 1) * NS, tid0);
+    }
   };
   if constexpr (FAST) body(std::true_type{});
   else body(std::false_type{});

@@ -63,6 +63,12 @@ struct RowJob {
   int32_t mode;        // kInReal | kOutIntensity | kOutField | kUsePost | kReduce ...
   int32_t view;        // the view the job belongs to (persistent launches)
   int32_t copy;        // column pass: the hologram copy it reads (persistent launches)
+  // Column pass of a persistent launch over real holograms: 0 when ``in`` is
+  // the column-major copy; otherwise ``in`` is the hologram itself, row-major
+  // with in_ld samples per row, and in_fmt gives their format (32: float32
+  // at the grid's width; 8, 16: camera samples, 33: float32 camera samples,
+  // resized from in_ld samples per row as in TileJob).
+  int32_t in_fmt;
   int32_t pad_;
 
   // Epilogue reductions (row kernel, kReduce): over the row's outputs V(m),
@@ -89,6 +95,7 @@ enum : int32_t {
   kReduce = 32,
   kRedSwap = 64,
   kRedIntensity = 128,
+  kRedRealRef = 256,  // kRedSwap with a real reference: uref points to float32 values
 };
 
 constexpr int kMaxJobsPerLaunch = 256;
@@ -143,12 +150,15 @@ struct GradZJob {
   double* out;
 };
 
-// Sum of per-view adjoint results into a hologram's gradient.
+// Sum of per-view adjoint results into a hologram's gradient (its real part
+// only when real_out: dst is then float32).
 struct GatherJob {
   const float2* const* src;  // device array of nsrc pointers
   float2* dst;
   int32_t nsrc;
   int32_t n;
+  int32_t real_out;
+  int32_t pad_;
 };
 
 // One launch builds everything a batch needs before the passes.  Workgroups
@@ -247,8 +257,9 @@ int spectra_per_block(int L);
 // post-chirps allowed.  0 otherwise.
 hipError_t launch_pass(int L, bool col, int G, int var, const PassArgs& args, const float2* tw, hipStream_t s);
 
-// Persistent launch (see PersistArgs): pa is a device copy; grid workgroups.
-hipError_t launch_persist(const PersistArgs* pa, int grid, hipStream_t s);
+// Persistent launch (see PersistArgs): pa is a device copy; grid workgroups;
+// complex_in selects the instance for complex holograms.
+hipError_t launch_persist(const PersistArgs* pa, int grid, bool complex_in, hipStream_t s);
 // Zero n counters (the first launch on a workspace).
 hipError_t launch_zero(uint32_t* p, int n, hipStream_t s);
 // Lengths the persistent launch supports (the passes' shape of a row in one

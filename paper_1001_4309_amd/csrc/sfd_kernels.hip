@@ -195,7 +195,8 @@ __global__ void __launch_bounds__(256) gather_kernel(const GatherJob* __restrict
     const float2 x = gld(J.src[k], (unsigned)i);
     acc = cadd(acc, x);
   }
-  gst(J.dst, (unsigned)i, acc);
+  if (J.real_out) gst(reinterpret_cast<float*>(J.dst), (unsigned)i, acc.x);
+  else gst(J.dst, (unsigned)i, acc);
 }
 
 hipError_t launch_gradz(const GradZJob* d_jobs, int njobs, hipStream_t s) {

@@ -39,6 +39,15 @@ constexpr int kPersistPassLds =
               cmax(PersistPassLds<1536>::bytes, PersistPassLds<1792>::bytes)),
          PersistPassLds<2048>::bytes);
 constexpr int kPersistLds = cmax(kPersistPassLds, cmax(kStripLdsBytes, kSetupItemLdsBytes));
+// The real-hologram instance's column tiles turn their rows around in LDS
+// after the tile's own area (col_rm_bytes; 1024-sample columns at every
+// persistent length).
+constexpr int kRmLdsBytes = cmax(cmax(ColLds<2048, kPG, 2, kPP>::bytes, ColLds<1792, kPG, 2, kPP>::bytes),
+                                 cmax(cmax(ColLds<1536, kPG, 2, kPP>::bytes, ColLds<1280, kPG, 2, kPP>::bytes),
+                                      ColLds<1024, kPG, 2, kPP>::bytes)) +
+                            col_rm_bytes<2048>();
+static_assert(col_rm_bytes<2048>() == col_rm_bytes<1280>() && col_rm_bytes<1024>() <= col_rm_bytes<2048>(),
+              "one row-major staging size");
 
 // Counters are read and advanced at device scope: the workgroups of a launch
 // run on every XCD, and each XCD has its own L2.
@@ -153,17 +162,6 @@ __device__ __forceinline__ void persist_setup(const PersistArgs& A, int v, int p
 // samples; the sample format is decided once, outside the loads), the chunk
 // is turned around in LDS, and each column leaves as a contiguous run of CH
 // samples, written through (later items read it on other XCDs).
-template <typename S>
-__device__ __forceinline__ float resample_at(const S* in, int ns, int nx, int n, int c) {
-  double sx = ((double)c + 0.5) * (double)ns / (double)nx - 0.5;
-  sx = fmin(fmax(sx, 0.0), (double)(ns - 1));
-  const int i0 = (int)sx;
-  const int i1 = i0 + 1 < ns ? i0 + 1 : ns - 1;
-  const float wt = (float)(sx - (double)i0);
-  const float a = (float)gld(in, (unsigned)(n * ns + i0)), b = (float)gld(in, (unsigned)(n * ns + i1));
-  return fmaf(wt, b - a, a);
-}
-
 // FMT: 0 float32 (or complex64 for T = float2), 8 / 16 / 32 camera samples
 // resized along x (real input only).
 template <typename T, int CH, int FMT>
@@ -210,22 +208,27 @@ __device__ __forceinline__ void persist_strip(const TileJob* Jp, int c0, unsigne
   else strip_chunks<float, 1024, 32>(J, c0, reinterpret_cast<float*>(lds), tid);
 }
 
-template <int L>
-__device__ __forceinline__ void persist_col(const Segment& sg, int tile, unsigned char* lds, int tid) {
-  switch (sg.var) {
-    case 1: col_body<L, kPG, 1, kPP, true>(*sg.args, sg.tw, tile, lds, tid); break;
-    case 2: col_body<L, kPG, 2, kPP, true>(*sg.args, sg.tw, tile, lds, tid); break;
-    default: col_body<L, kPG, 3, kPP, true>(*sg.args, sg.tw, tile, lds, tid); break;
+// CPLX: the kernel instance for complex holograms (column specialisation 1);
+// the real-hologram instance holds specialisations 2 and 3.  Keeping them
+// apart keeps each instance's register need that of its largest body.
+template <int L, bool CPLX, typename TAIL>
+__device__ __forceinline__ void persist_col(const Segment& sg, int tile, unsigned char* lds, int tid, const TAIL& tail) {
+  if constexpr (CPLX) {
+    col_body<L, kPG, 1, kPP, true, false>(*sg.args, sg.tw, tile, lds, tid, tail);
+  } else {
+    if (sg.var == 2) col_body<L, kPG, 2, kPP, true, true>(*sg.args, sg.tw, tile, lds, tid, tail);
+    else col_body<L, kPG, 3, kPP, true, true>(*sg.args, sg.tw, tile, lds, tid, tail);
   }
 }
-template <int L>
-__device__ __forceinline__ void persist_row(const Segment& sg, int tile, unsigned char* lds, int tid) {
-  if (sg.var == 2) row_body<L, kPG, 2, kPP, true>(*sg.args, sg.tw, tile, lds, tid);
-  else row_body<L, kPG, 1, kPP, true>(*sg.args, sg.tw, tile, lds, tid);
+template <int L, typename TAIL>
+__device__ __forceinline__ void persist_row(const Segment& sg, int tile, unsigned char* lds, int tid, const TAIL& tail) {
+  if (sg.var == 2) row_body<L, kPG, 2, kPP, true>(*sg.args, sg.tw, tile, lds, tid, tail);
+  else row_body<L, kPG, 1, kPP, true>(*sg.args, sg.tw, tile, lds, tid, tail);
 }
 
+template <bool CPLX>
 __global__ void __launch_bounds__(kPersistThreads) persist_kernel(const PersistArgs* __restrict__ pa) {
-  __shared__ __align__(16) unsigned char lds[kPersistLds];
+  __shared__ __align__(16) unsigned char lds[CPLX ? kPersistLds : cmax(kPersistLds, kRmLdsBytes)];
   __shared__ int s_ticket;
   const PersistArgs& A = *pa;
   uint32_t* const sync = A.sync;
@@ -248,6 +251,15 @@ __global__ void __launch_bounds__(kPersistThreads) persist_kernel(const PersistA
     while (k + 1 < A.nseg && t >= A.seg[k + 1].first) ++k;
     const Segment& sg = A.seg[k];
     const int local = t - sg.first;
+    // Column and row tiles take the next ticket once their last transform is
+    // computed (its latency then overlaps their last stores); the short setup
+    // and strip items take it when they are done.
+    uint32_t next = 0;
+    bool took = false;
+    const auto tail = [&]() {
+      if (threadIdx.x == 0) next = sync_add(&sync[kSyncTicket * kSyncStride], 1u);
+      took = true;
+    };
     switch (sg.kind) {
       case kItemSetup: {
         // Items 0 .. nview-1: spectra of view i; nview .. 2 nview - 1: tables.
@@ -257,8 +269,11 @@ __global__ void __launch_bounds__(kPersistThreads) persist_kernel(const PersistA
         break;
       }
       case kItemStrip: {
-        const int nsp = (A.tiles[0].nx + kStripW - 1) / kStripW;
-        persist_strip(&A.tiles[local / nsp], (local % nsp) * kStripW, lds, tid);
+        // Only complex holograms have strips (real ones are read in place).
+        if constexpr (CPLX) {
+          const int nsp = (A.tiles[0].nx + kStripW - 1) / kStripW;
+          persist_strip(&A.tiles[local / nsp], (local % nsp) * kStripW, lds, tid);
+        }
         signal_count(&strip_done[local * kSyncStride]);
         break;
       }
@@ -269,14 +284,18 @@ __global__ void __launch_bounds__(kPersistThreads) persist_kernel(const PersistA
         const int view = J.view;
         const int nsp = (A.tiles[0].nx + kStripW - 1) / kStripW;
         const int strip = J.copy * nsp + (local - PA.tile_prefix[jid]);
-        wait_counts(sync, &strip_done[strip * kSyncStride], 1u,
-                    A.wait_setup ? &setup_done[view * kSyncStride] : nullptr, 2u);
+        // Real holograms are read in place (no strips): only the setup.
+        if (A.nstrips > 0)
+          wait_counts(sync, &strip_done[strip * kSyncStride], 1u,
+                      A.wait_setup ? &setup_done[view * kSyncStride] : nullptr, 2u);
+        else if (A.wait_setup)
+          wait_counts(sync, &setup_done[view * kSyncStride], 2u, nullptr, 0u);
         switch (sg.L) {
-          case 2048: persist_col<2048>(sg, local, lds, tid); break;
-          case 1792: persist_col<1792>(sg, local, lds, tid); break;
-          case 1536: persist_col<1536>(sg, local, lds, tid); break;
-          case 1280: persist_col<1280>(sg, local, lds, tid); break;
-          default: persist_col<1024>(sg, local, lds, tid); break;
+          case 2048: persist_col<2048, CPLX>(sg, local, lds, tid, tail); break;
+          case 1792: persist_col<1792, CPLX>(sg, local, lds, tid, tail); break;
+          case 1536: persist_col<1536, CPLX>(sg, local, lds, tid, tail); break;
+          case 1280: persist_col<1280, CPLX>(sg, local, lds, tid, tail); break;
+          default: persist_col<1024, CPLX>(sg, local, lds, tid, tail); break;
         }
         signal_count(&col_done[view * kSyncStride]);
         break;
@@ -286,19 +305,19 @@ __global__ void __launch_bounds__(kPersistThreads) persist_kernel(const PersistA
         const int view = PA.jobs[find_job(PA, local)].view;
         wait_counts(sync, &col_done[view * kSyncStride], (uint32_t)A.col_tiles[view], nullptr, 0u);
         switch (sg.L) {
-          case 2048: persist_row<2048>(sg, local, lds, tid); break;
-          case 1792: persist_row<1792>(sg, local, lds, tid); break;
-          case 1536: persist_row<1536>(sg, local, lds, tid); break;
-          case 1280: persist_row<1280>(sg, local, lds, tid); break;
-          default: persist_row<1024>(sg, local, lds, tid); break;
+          case 2048: persist_row<2048>(sg, local, lds, tid, tail); break;
+          case 1792: persist_row<1792>(sg, local, lds, tid, tail); break;
+          case 1536: persist_row<1536>(sg, local, lds, tid, tail); break;
+          case 1280: persist_row<1280>(sg, local, lds, tid, tail); break;
+          default: persist_row<1024>(sg, local, lds, tid, tail); break;
         }
         __syncthreads();
         break;
       }
     }
-    // The next ticket is taken once this item is done: a ticket taken earlier
-    // would hold its item back behind this one while other workgroups idle.
-    if (threadIdx.x == 0) s_ticket = (int)sync_add(&sync[kSyncTicket * kSyncStride], 1u);
+    // (A ticket taken early in an item would hold its item back behind this
+    // one while other workgroups idle.)
+    if (threadIdx.x == 0) s_ticket = took ? (int)next : (int)sync_add(&sync[kSyncTicket * kSyncStride], 1u);
   }
   // Leaving: the last workgroup out resets the counters for the next launch
   // (every item is done once every workgroup has taken a ticket past the end).
@@ -317,9 +336,10 @@ __global__ void zero_kernel(uint32_t* p, int n) {
   if (i < n) p[i] = 0u;
 }
 
-hipError_t launch_persist(const PersistArgs* pa, int grid, hipStream_t s) {
+hipError_t launch_persist(const PersistArgs* pa, int grid, bool complex_in, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
-  hipLaunchKernelGGL(persist_kernel, dim3(grid), dim3(kPersistThreads), 0, s, pa);
+  if (complex_in) hipLaunchKernelGGL(persist_kernel<true>, dim3(grid), dim3(kPersistThreads), 0, s, pa);
+  else hipLaunchKernelGGL(persist_kernel<false>, dim3(grid), dim3(kPersistThreads), 0, s, pa);
   return hipGetLastError();
 }
 
@@ -332,8 +352,11 @@ hipError_t launch_zero(uint32_t* p, int n, hipStream_t s) {
 int persist_resident_blocks() {
   int dev = 0, per_cu = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persist_kernel, kPersistThreads, 0) != hipSuccess)
+  int per_cu2 = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persist_kernel<false>, kPersistThreads, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu2, persist_kernel<true>, kPersistThreads, 0) != hipSuccess)
     return 0;
+  per_cu = per_cu < per_cu2 ? per_cu : per_cu2;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
   return per_cu * cus;
 }

@@ -42,6 +42,10 @@ def test_binding_flag_values_match_the_header():
     kinds = dict(re.findall(r"^\s*(SFD_KERNEL_[A-Z_]+)\s*=\s*(\d+)", text, re.M))
     for name, value in kinds.items():
         assert getattr(lib_mod, name) == int(value), name
+    smooth = dict(re.findall(r"(SFD_SMOOTH_[A-Z0-9]+)\s*=\s*(\d+)", text))
+    assert len(smooth) == 4
+    for name, value in smooth.items():
+        assert getattr(lib_mod, name) == int(value), name
 
 
 def test_library_exports_every_declared_symbol(lib):
@@ -112,6 +116,25 @@ def test_paper_size_uses_doubled_grid(lib):
     lx, ly = ctypes.c_int32(), ctypes.c_int32()
     lib.sfd_view_lengths(h, 0, ctypes.byref(lx), ctypes.byref(ly))
     assert (lx.value, ly.value) == (2048, 2048)
+    lib.sfd_destroy(h)
+
+
+@pytest.mark.parametrize("mask,want", [(0, (2048, 2048)), (1, (1280, 2048)), (2, (1536, 1536)),
+                                       (3, (1280, 1536)), (4, (1792, 1792)), (7, (1280, 1536))])
+def test_length_policy_mask_picks_the_smallest_allowed_length(lib, mask, want):
+    """Each axis takes the smallest length >= N0 + N1 - 1 that the mask
+    allows (x: 1024 + 200 - 1 = 1223, y: 1024 + 500 - 1 = 1523)."""
+    views = [lib_mod.SfdView(_grid(200, 500, 8e-6, 8e-6), 0.03, 0)]
+    st, h = _plan(lib, holo=_grid(1024, 1024), views=views)
+    assert st == lib_mod.SFD_OK
+    lx, ly, m = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    assert lib.sfd_length_policy(h, ctypes.byref(m)) == lib_mod.SFD_OK
+    assert m.value == lib_mod.SFD_SMOOTH_1280
+    assert lib.sfd_set_length_policy(h, mask) == lib_mod.SFD_OK
+    lib.sfd_view_lengths(h, 0, ctypes.byref(lx), ctypes.byref(ly))
+    assert (lx.value, ly.value) == want
+    assert lib.sfd_set_length_policy(h, 8) == lib_mod.SFD_ERR_INVALID_ARG
+    assert lib.sfd_set_length_policy(h, -1) == lib_mod.SFD_ERR_INVALID_ARG
     lib.sfd_destroy(h)
 
 
@@ -254,7 +277,7 @@ def test_stream_frame_validates_before_any_hip_call(lib):
     assert lib.sfd_stream_frame(h, host, two, out, ws, n.value, None) == lib_mod.SFD_ERR_INVALID_ARG
     assert lib.sfd_destroy(h) == 0
     # Unknown flag bits are still refused.
-    st, _ = _plan(lib, flags=lib_mod.SFD_IN_REAL_F32 | lib_mod.SFD_OUT_INTENSITY | (1 << 8))
+    st, _ = _plan(lib, flags=lib_mod.SFD_IN_REAL_F32 | lib_mod.SFD_OUT_INTENSITY | (1 << 9))
     assert st == lib_mod.SFD_ERR_INVALID_ARG
 
 
@@ -294,5 +317,40 @@ def test_noalloc_rejects_plans_larger_than_its_scratch(lib):
         assert st == lib_mod.SFD_ERR_WORKSPACE
         assert b"scratch" in lib.sfd_last_error()
         assert lib.sfd_reconstruct_noalloc(None, ctypes.c_void_p(16), None, outs, None) == lib_mod.SFD_ERR_INVALID_ARG
+    finally:
+        sfd.sfd_destroy(h)
+
+
+def test_schedule_cache_file_seeds_plans_and_corrupt_files_are_ignored(lib, tmp_path, monkeypatch):
+    """SFD_TUNE_CACHE: a plan whose key (architecture, schedule version,
+    hologram grid and count, flags, view sizes) is in the file starts from
+    its schedule; an unreadable file is ignored (defaults)."""
+    import json
+
+    import workloads
+    import paper_1001_4309_amd as sfd
+
+    flags = lib_mod.SFD_IN_REAL_F32 | lib_mod.SFD_OUT_INTENSITY
+    w = workloads.config2()
+    g = w.holo_grid
+    sig = f"{g.nx}x{g.ny}/1/{flags}" + "".join(f";{v.grid.nx}x{v.grid.ny}@{v.holo}" for v in w.views)
+    path = tmp_path / "schedule.json"
+    path.write_text(json.dumps({"format": "sfd-schedule-cache", "version": 2, "entries": {
+        "gfx950|v2|" + sig: {"col": {"2048": 4}, "row": {"2048": 16}, "persist": 0, "smooth": 1}}}))
+    monkeypatch.setenv("SFD_TUNE_CACHE", str(path))
+    h = sfd.sfd_plan(w.wavelength, g, 1, w.views, flags)
+    try:
+        assert sfd.sfd_schedule(h, 2048, True) == 4
+        assert sfd.sfd_schedule(h, 2048, False) == 16
+        assert sfd.sfd_launch_mode(h) == (lib_mod.SFD_LAUNCH_PASSES, True)
+    finally:
+        sfd.sfd_destroy(h)
+    # Another shape, unreadable file: the defaults.
+    path.write_text("{\"format\": \"sfd-schedule-cache\", \"entries\": {oops")
+    w1 = workloads.config1()
+    h = sfd.sfd_plan(w1.wavelength, w1.holo_grid, 1, w1.views, flags)
+    try:
+        for col in (True, False):
+            assert sfd.sfd_schedule(h, 512, col) == sfd.sfd_tile_widths(512, col)[0][0]
     finally:
         sfd.sfd_destroy(h)

@@ -203,3 +203,33 @@ def test_backward_every_tile_width():
                   flush=True)
             assert float(rel.max()) <= 1e-12, (col, g, per_slot)
         p.set_schedule(L, col, default)
+
+
+@pytest.mark.parametrize("n_holo,views_per", [(1, 1), (2, 2)])
+def test_real_hologram_gradients(n_holo, views_per):
+    """Real holograms (SFD_WITH_BACKWARD): the gradient of an intensity loss
+    with respect to a real input is Re(A^H g), and dL/dz as for complex
+    input; both against the oracle, through the autograd function."""
+    r = np.random.default_rng(60 + n_holo)
+    w0 = _case(70 + n_holo, n_holo=n_holo, views_per=views_per)
+    holos = r.uniform(0.5, 1.5, w0.holograms.shape).astype(np.float32)
+    w = workloads.Workload("bwd-real", LAM, w0.holo_grid, holos, w0.views)
+    src = ogrid(w.holo_grid)
+    targets = [(np.abs(oracle.direct(holos[v.holo] * 1.05, src, ogrid(v.grid), LAM, v.z * 1.02)) ** 2)
+               .astype(np.float32) for v in w.views]
+    p = sfd.Plan(LAM, w.holo_grid, n_holo, w.views, outputs="both", backward=True, device=DEV)
+    fields = torch.from_numpy(holos).to(DEV).requires_grad_(True)
+    z = torch.tensor([v.z for v in w.views], dtype=torch.float64, requires_grad=True)
+    inten = sfd.SFDFunction.apply(fields, z, p)
+    loss = sum(((i.double() - torch.from_numpy(t).to(DEV).double()) ** 2).sum() for i, t in zip(inten, targets))
+    loss.backward()
+    torch.cuda.synchronize()
+    assert fields.grad.dtype == torch.float32
+    ref_gu, ref_gz = _intensity_loss_grads(w, targets)
+    assert not np.iscomplexobj(ref_gu) or np.allclose(ref_gu.imag, 0)
+    for h in range(n_holo):
+        check(fields.grad[h].cpu().numpy(), np.real(ref_gu[h]), f"real hologram {h}: field gradient", elem_tol=TOL)
+    for v in range(len(w.views)):
+        ez = abs(float(z.grad[v]) - ref_gz[v]) / abs(ref_gz[v])
+        print(f"real view {v}: dL/dz {float(z.grad[v]):.6e} oracle {ref_gz[v]:.6e} rel {ez:.2e}", flush=True)
+        assert ez <= TOL

@@ -48,7 +48,10 @@ def _smooth_workload():
 def test_smooth_lengths_specialised_kernels():
     w = _smooth_workload()
     p = sfd.Plan(w.wavelength, w.holo_grid, 1, w.views, outputs="both", device=DEV)
-    assert p.length_policy() == "smooth"
+    assert p.length_policy() == "smooth:1280"
+    assert [p.lengths(v) for v in range(4)] == [(1280, 1280), (2048, 2048), (2048, 2048), (2048, 2048)]
+    p.set_lengths(True)
+    assert p.length_policy() == "smooth:1280,1536,1792"
     assert [p.lengths(v) for v in range(4)] == [(1280, 1280), (1536, 1536), (1792, 1792), (2048, 2048)]
     holo = _holo(w)
     p.set_launch(True)
@@ -89,6 +92,7 @@ def test_smooth_lengths_general_kernels(shape):
     w = workloads.Workload("general", LAM, g0, holo, [workloads.ViewSpec(g1, 0.03, 0),
                                                       workloads.ViewSpec(g1, -0.045, 0)])
     p = sfd.Plan(w.wavelength, g0, 1, w.views, outputs="both", device=DEV)
+    p.set_lengths(True)
     lx, ly = p.lengths(0)
     assert lx in (1280, 1536, 1792) or ly in (1280, 1536, 1792), (lx, ly)
     res = p.reconstruct(_holo(w))
@@ -109,6 +113,7 @@ def test_smooth_lengths_backward():
     z = 0.025
     w = workloads.Workload("bwd-smooth", LAM, g0, u0, [workloads.ViewSpec(g1, z, 0)])
     p = sfd.Plan(LAM, g0, 1, w.views, outputs="both", complex_input=True, device=DEV)
+    p.set_lengths(sfd.SFD_SMOOTH_1280 | sfd.SFD_SMOOTH_1536)
     assert p.lengths(0) == (1280, 1536)
     holo = _holo(w)
     res = p.reconstruct(holo)
