@@ -549,6 +549,7 @@ sfd_status build_descs(sfd_plan_s* P, const void* holo, const double* z, void* c
   struct AxisTmp {
     sfd::AxisJob j;
     int L;
+    int key;  // 2 v + axis
   };
   std::vector<AxisTmp> ax;
   ax.reserve(2 * V);
@@ -580,7 +581,7 @@ sfd_status build_descs(sfd_plan_s* P, const void* holo, const double* z, void* c
       j.n1 = a == 0 ? w.out.nx : w.out.ny;
       j.L = a == 0 ? L.lx : L.ly;
       j.flags = pflags;
-      ax.push_back({j, j.L});
+      ax.push_back({j, j.L, 2 * v + a});
     }
   }
   // The setup launch groups the spectra by length; the persistent launch's
@@ -589,7 +590,9 @@ sfd_status build_descs(sfd_plan_s* P, const void* holo, const double* z, void* c
     std::stable_sort(ax.begin(), ax.end(), [](const AxisTmp& a, const AxisTmp& b) { return a.L < b.L; });
   D->axis.clear();
   D->axis_L.clear();
+  std::vector<int> axis_pos(2 * V);
   for (auto& a : ax) {
+    axis_pos[a.key] = (int)D->axis.size();
     D->axis.push_back(a.j);
     D->axis_L.push_back(a.L);
   }
@@ -640,6 +643,8 @@ sfd_status build_descs(sfd_plan_s* P, const void* holo, const double* z, void* c
     jc.colscale = reinterpret_cast<const float2*>(ws + L.prex);
     jc.view = v;
     jc.copy = L.tile;
+    jc.ax_pre = axis_pos[2 * v + 1];
+    jc.ax_scale = axis_pos[2 * v];
     if (P->persist && in_real) {
       // The persistent launch reads real holograms in place, row-major.
       jc.in = static_cast<const char*>(holo) + (size_t)w.holo * holo_stride;
@@ -781,6 +786,7 @@ void pack_persist(const sfd_plan_s* P, CallDescs* D, char* ws, bool tables, std:
     for_length_runs(*D, first, last, [&](int i, int j, int L) {
       sfd::PassArgs a{};
       a.jobs = d_rows + i;
+      a.axis = reinterpret_cast<const sfd::AxisJob*>(dbase + off_axis);
       a.njobs = j - i;
       int acc = 0;
       for (int k = i; k < j; ++k) {

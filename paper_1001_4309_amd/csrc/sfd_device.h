@@ -25,6 +25,86 @@ typedef const uint64_t g_u64;
 typedef uint64_t g_u64w;
 #endif
 
+// Global loads that are coherent across the XCDs (device-scope relaxed
+// atomic loads: they bypass the per-XCD caches' possibly stale lines).  The
+// persistent launch reads what other items of the same launch wrote, on any
+// XCD, through these; COH = false gives ordinary loads.
+template <bool COH>
+__device__ __forceinline__ float gld_c(const float* p, unsigned i) {
+  if constexpr (COH) {
+    return __builtin_bit_cast(float, __hip_atomic_load((g_u32*)p + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  } else {
+    return gld(p, i);
+  }
+}
+template <bool COH>
+__device__ __forceinline__ float2 gld_c(const float2* p, unsigned i) {
+  if constexpr (COH) {
+    return __builtin_bit_cast(float2, __hip_atomic_load((g_u64*)p + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  } else {
+    return gld(p, i);
+  }
+}
+template <bool COH>
+__device__ __forceinline__ float4 gld_c(const float4* p, unsigned i) {
+  if constexpr (COH) {
+    const float2 a = gld_c<true>(reinterpret_cast<const float2*>(p), 2 * i);
+    const float2 b = gld_c<true>(reinterpret_cast<const float2*>(p), 2 * i + 1);
+    return make_float4(a.x, a.y, b.x, b.y);
+  } else {
+    return gld(p, i);
+  }
+}
+
+// A descriptor that no kernel writes (the call's descriptor image), read
+// into scalar registers: the pointer (the same in every lane of the
+// wavefront) is made wave-uniform and read through the constant address
+// space, which the compiler serves with scalar loads.  For descriptors
+// reached through pointers that it cannot otherwise prove global, uniform
+// or unwritten.
+template <typename T>
+__device__ __forceinline__ T load_uniform(const T* p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  // (readfirstlane returns a signed int: each half goes through uint32_t so
+  // that the low half is not sign-extended into the high one.)
+  const uint64_t a = reinterpret_cast<uint64_t>(p);
+  const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(a >> 32));
+  const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)a);
+  const uint64_t u = (hi << 32) | lo;
+  return *reinterpret_cast<const __attribute__((address_space(4))) T*>(u);
+#else
+  return *p;
+#endif
+}
+
+// Cooperative copies of N float4 from global memory into LDS by THREADS
+// threads.  Every thread issues all of its loads before its first LDS
+// write, so that their latencies overlap; a thread past the end of a table
+// reloads its last entry instead of skipping the load, which keeps the loads
+// branch-free.
+template <int N, int THREADS>
+struct CopyShare {
+  static constexpr int K = N > 0 ? (N + THREADS - 1) / THREADS : 0;
+  static constexpr int KA = K > 0 ? K : 1;  // register array size
+};
+template <int N, int THREADS, int KA, bool COH = false>
+__device__ __forceinline__ void copy_load(float4 (&r)[KA], const float2* src, int tid) {
+  const float4* s4 = reinterpret_cast<const float4*>(src);
+#pragma unroll
+  for (int k = 0; k < CopyShare<N, THREADS>::K; ++k) {
+    const int e = tid + k * THREADS;
+    r[k] = gld_c<COH>(s4, (unsigned)(e < N ? e : N - 1));
+  }
+}
+template <int N, int THREADS, int KA>
+__device__ __forceinline__ void copy_store(float2* dst, const float4 (&r)[KA], int tid) {
+  float4* d4 = reinterpret_cast<float4*>(dst);
+#pragma unroll
+  for (int k = 0; k < CopyShare<N, THREADS>::K; ++k) {
+    const int e = tid + k * THREADS;
+    if (N % THREADS == 0 || e < N) d4[e] = r[k];
+  }
+}
 // exp(i pi v) for a large phase v (in half-turns).  The reduction to
 // [-1, 1] is done in FP64, exact enough for phases of 10^5 half-turns and
 // more.  The reduced argument r is split as r_hi + r_lo with r_hi its FP32
@@ -32,6 +112,7 @@ typedef uint64_t g_u64w;
 // pi r_lo (|pi r_lo| < 1e-7, so the dropped second-order term is ~1e-14)
 // give the FP32 result at FP32 sin/cos accuracy without FP64 trigonometry.
 __device__ __forceinline__ float2 cispi_f64(double v) {
+#pragma clang fp contract(off)
   const double r = v - 2.0 * rint(0.5 * v);
   const float rh = static_cast<float>(r);
   const float rl = static_cast<float>((r - static_cast<double>(rh)) * M_PI);
@@ -42,18 +123,24 @@ __device__ __forceinline__ float2 cispi_f64(double v) {
 
 // The same phase carried entirely in FP32 (comparison variant).
 __device__ __forceinline__ float2 cispi_f32(float v) {
+#pragma clang fp contract(off)
   const float r = v - 2.0f * rintf(0.5f * v);
   float s, c;
   sincospif(r, &s, &c);
   return make_float2(c, s);
 }
 
+// The chirp values below are written with explicit fused multiply-adds and
+// no contraction left to the compiler, so that every kernel that evaluates
+// one (the setup kernel, the persistent launch's setup items and its column
+// tiles) rounds it identically.
 __device__ __forceinline__ float2 pre_value(const AxisJob& J, int m) {
+#pragma clang fp contract(off)
   if (J.flags & kPhaseFp32) {
     const float p0 = (float)J.p0, a0 = (float)J.a0, il = (float)J.inv_lz, S = (float)J.S, c1 = (float)J.c1;
     const float fm = (float)m;
-    const float x0 = fm * p0 + a0;
-    float2 v = cispi_f32(x0 * x0 * il - 2.0f * fm * S * c1 - S * fm * fm);
+    const float x0 = fmaf(fm, p0, a0);
+    float2 v = cispi_f32(fmaf(-S * fm, fm, fmaf(x0 * x0, il, -(2.0f * fm * S * c1))));
     if (J.flags & kMomentX0) {
       const float w = x0 * (float)J.wscale;
       v = make_float2(v.x * w, v.y * w);
@@ -61,8 +148,8 @@ __device__ __forceinline__ float2 pre_value(const AxisJob& J, int m) {
     return v;
   }
   const double dm = (double)m;
-  const double x0 = dm * J.p0 + J.a0;
-  float2 v = cispi_f64(x0 * x0 * J.inv_lz - 2.0 * dm * J.S * J.c1 - J.S * (double)((int64_t)m * m));
+  const double x0 = fma(dm, J.p0, J.a0);
+  float2 v = cispi_f64(fma(-J.S, (double)((int64_t)m * m), fma(x0 * x0, J.inv_lz, -(2.0 * dm * J.S * J.c1))));
   if (J.flags & kMomentX0) {
     const float w = (float)(x0 * J.wscale);
     v = make_float2(v.x * w, v.y * w);
@@ -71,30 +158,36 @@ __device__ __forceinline__ float2 pre_value(const AxisJob& J, int m) {
 }
 
 __device__ __forceinline__ float2 post_value(const AxisJob& J, int m) {
+#pragma clang fp contract(off)
   float2 v;
   if (J.flags & kPhaseFp32) {
     const float p1 = (float)J.p1, a1 = (float)J.a1, a0 = (float)J.a0, il = (float)J.inv_lz, S = (float)J.S;
     const float fm = (float)m;
-    const float x1 = fm * p1 + a1;
-    v = cispi_f32(x1 * x1 * il - 2.0f * a0 * x1 * il - S * fm * fm);
+    const float x1 = fmaf(fm, p1, a1);
+    v = cispi_f32(fmaf(-S * fm, fm, fmaf(x1 * x1, il, -(2.0f * a0 * x1 * il))));
   } else {
     const double dm = (double)m;
-    const double x1 = dm * J.p1 + J.a1;
-    v = cispi_f64(x1 * x1 * J.inv_lz - 2.0 * J.a0 * x1 * J.inv_lz - J.S * (double)((int64_t)m * m));
+    const double x1 = fma(dm, J.p1, J.a1);
+    v = cispi_f64(fma(-J.S, (double)((int64_t)m * m), fma(x1 * x1, J.inv_lz, -(2.0 * J.a0 * x1 * J.inv_lz))));
   }
   return cmul(v, J.post_scale);
 }
 
 // h of Eq. (4) at storage index i in [0, L): lag k = i for i < n1, k = i - L
 // otherwise; zero outside k in [-(n0-1), n1-1].
-__device__ __forceinline__ float2 kernel_value(const AxisJob& J, int i) {
-  const int k = i < J.n1 ? i : i - J.L;
-  if (k < -(J.n0 - 1)) return make_float2(0.f, 0.f);
+// h at lag k (without the window), which depends on k^2 only.
+__device__ __forceinline__ float2 kernel_lag(const AxisJob& J, int k) {
+#pragma clang fp contract(off)
   if (J.flags & kPhaseFp32) {
     const float fk = (float)k;
     return cispi_f32((float)J.S * fk * fk);
   }
   return cispi_f64(J.S * (double)((int64_t)k * k));
+}
+__device__ __forceinline__ float2 kernel_value(const AxisJob& J, int i) {
+  const int k = i < J.n1 ? i : i - J.L;
+  if (k < -(J.n0 - 1)) return make_float2(0.f, 0.f);
+  return kernel_lag(J, k);
 }
 
 template <int L>
@@ -121,6 +214,10 @@ __device__ __forceinline__ bool twiddle_any(int L, bool spec, int e, float2* out
 
 // Split (real/imaginary in turn) LDS exchanges halve the LDS a row needs.
 constexpr bool kSplit = true;
+// The lone kernel-spectrum transforms exchange complex values (one LDS round
+// trip and two barriers per exchange instead of two and four): their
+// latency, not their LDS footprint, is what matters.
+constexpr bool kSpecSplit = false;
 
 // Setup roles ---------------------------------------------------------------
 
@@ -134,15 +231,23 @@ template <int L>
 struct SpecShape {
   using P = SpecPlan<L>;
   static constexpr int GS = kSetupThreads / P::TPR;  // spectra per workgroup
-  static constexpr int BYTES = GS * row_lds_bytes<L, kSplit>();  // exchange rows
+  // Up to L = 2048 the shape's twiddle table is staged in LDS (its loads are
+  // issued first and overlap the evaluation of h; the stages then read LDS);
+  // longer spectra read theirs from global memory, a stage ahead.
+  static constexpr bool TW_LDS = L <= 2048;
+  static constexpr int TW_N = twiddle_entries<P>();
+  static constexpr int TW_BYTES = TW_LDS ? TW_N * 8 : 0;
+  static constexpr int BYTES = GS * row_lds_bytes<L, kSpecSplit>() + TW_BYTES;  // exchange rows, table
 };
 
 // One kernel spectrum H = FFT_L(h) / L by the TPR threads of row g of a
-// spectrum workgroup (t = thread in the row); J null: the row computes on
-// zeros and stores nothing (it still takes part in the exchanges' barriers).
-// Each thread evaluates h straight into its FFT input slots (element
-// t + TPR i); the twiddles come from the spectrum-shape table (built once
-// per workspace), fetched a stage ahead.
+// spectrum workgroup (t = thread in the row, r = thread in the group of
+// kSetupThreads that shares the LDS area lds); J null: the row computes on
+// zeros and stores nothing (it still takes part in the barriers).  Each
+// thread evaluates h straight into its FFT input slots (element t + TPR i).
+// The twiddles come from the spectrum-shape table (built once per
+// workspace): staged in LDS (SpecShape::TW_LDS, loads issued before h is
+// evaluated) or read from global memory a stage ahead.
 // Store of a complex value; WT: written through to memory at system scope
 // (a relaxed atomic store), so that no dirty copy stays in the writer's
 // XCD cache when other XCDs read it in the same launch.
@@ -156,24 +261,57 @@ __device__ __forceinline__ void gst_c(float2* p, unsigned i, float2 v) {
 }
 
 template <int L, bool WT = false>
-__device__ __forceinline__ void spectrum_row(const AxisJob* J, const float2* tw, void* lds, int g, int t) {
+__device__ __forceinline__ void spectrum_row(const AxisJob* J, const float2* tw, void* lds, int g, int t, int r) {
   using P = SpecPlan<L>;
+  using Sh = SpecShape<L>;
   constexpr int TPR = P::TPR;
   constexpr int R = P::R;
+  constexpr int NT = Sh::TW_N / 2;  // table entries as float4 pairs
+  static_assert(!Sh::TW_LDS || Sh::TW_N % 2 == 0, "tables are copied two entries at a time");
+  float2* const tws = reinterpret_cast<float2*>(static_cast<char*>(lds) + Sh::GS * row_lds_bytes<L, kSpecSplit>());
+  float4 twr[Sh::TW_LDS ? CopyShare<NT, kSetupThreads>::KA : 1];
+  if constexpr (Sh::TW_LDS) copy_load<NT, kSetupThreads, CopyShare<NT, kSetupThreads>::KA>(twr, tw, r);
   float2* Hg = nullptr;
   float2 v[R];
+  // The job's fields are read once (into scalar registers when a transform
+  // spans whole wavefronts, so that every lane of one works on the same job),
+  // and its output pointer is kept for the end.
+  AxisJob Jv{};
   if (J) {
-    // The job's fields are read once (scalar loads when a transform spans
-    // whole wavefronts), and its output pointer is kept for the end.
-    const AxisJob Jv = *J;
+    if constexpr (TPR >= 64) Jv = load_uniform(J);
+    else Jv = *J;
     Hg = Jv.H;
+  }
+  if constexpr (TPR == kSetupThreads) {
+    // One transform per group: h depends on the lag's square only, so the
+    // group evaluates it once per |lag| < max(n0, n1) into the exchange row
+    // (not in use yet) and every thread picks its entries from there.
+    float2* const e = static_cast<float2*>(lds);
+    const int M = Jv.n0 > Jv.n1 ? Jv.n0 : Jv.n1;
+    if (J)
+      for (int m = r; m < M; m += kSetupThreads) e[m] = kernel_lag(Jv, m);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int idx = t + TPR * i;
+      const int k = idx < Jv.n1 ? idx : idx - L;
+      v[i] = (J && k >= -(Jv.n0 - 1)) ? e[k < 0 ? -k : k] : make_float2(0.f, 0.f);
+    }
+  } else if (J) {
 #pragma unroll
     for (int i = 0; i < R; ++i) v[i] = kernel_value(Jv, t + TPR * i);
   } else {
 #pragma unroll
     for (int i = 0; i < R; ++i) v[i] = make_float2(0.f, 0.f);
   }
-  fft_row<P, false, kSplit, kTwGlobal>(v, static_cast<char*>(lds) + g * row_lds_bytes<L, kSplit>(), t, tw);
+  if constexpr (Sh::TW_LDS) {
+    copy_store<NT, kSetupThreads>(tws, twr, r);
+    __syncthreads();
+    fft_row<P, false, kSpecSplit, kTwShared>(v, static_cast<char*>(lds) + g * row_lds_bytes<L, kSpecSplit>(), t, tws);
+  } else {
+    if constexpr (TPR == kSetupThreads) __syncthreads();  // every lag read before the exchanges write
+    fft_row<P, false, kSpecSplit, kTwGlobal>(v, static_cast<char*>(lds) + g * row_lds_bytes<L, kSpecSplit>(), t, tw);
+  }
   if (!Hg) return;
   const float inv = 1.0f / (float)L;
 #pragma unroll
@@ -188,7 +326,7 @@ __device__ __forceinline__ void setup_spectrum(const SetupArgs& A, const SetupRo
   const int g = TPR >= 64 ? __builtin_amdgcn_readfirstlane(threadIdx.x / TPR) : threadIdx.x / TPR;
   const int t = threadIdx.x - g * TPR;
   const int k = rb * GS + g;
-  spectrum_row<L>(k < Ro.c ? &A.axis[Ro.b + k] : nullptr, Ro.tw, lds, g, t);
+  spectrum_row<L>(k < Ro.c ? &A.axis[Ro.b + k] : nullptr, Ro.tw, lds, g, t, (int)threadIdx.x);
 }
 
 // Stores through a buffer resource of a given extent in bytes: the hardware
@@ -390,37 +528,6 @@ __device__ __forceinline__ int opaque(int x) {
   return y;
 }
 
-// Global loads that are coherent across the XCDs (device-scope relaxed
-// atomic loads: they bypass the per-XCD caches' possibly stale lines).  The
-// persistent launch reads what other items of the same launch wrote, on any
-// XCD, through these; COH = false gives ordinary loads.
-template <bool COH>
-__device__ __forceinline__ float gld_c(const float* p, unsigned i) {
-  if constexpr (COH) {
-    return __builtin_bit_cast(float, __hip_atomic_load((g_u32*)p + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-  } else {
-    return gld(p, i);
-  }
-}
-template <bool COH>
-__device__ __forceinline__ float2 gld_c(const float2* p, unsigned i) {
-  if constexpr (COH) {
-    return __builtin_bit_cast(float2, __hip_atomic_load((g_u64*)p + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-  } else {
-    return gld(p, i);
-  }
-}
-template <bool COH>
-__device__ __forceinline__ float4 gld_c(const float4* p, unsigned i) {
-  if constexpr (COH) {
-    const float2 a = gld_c<true>(reinterpret_cast<const float2*>(p), 2 * i);
-    const float2 b = gld_c<true>(reinterpret_cast<const float2*>(p), 2 * i + 1);
-    return make_float4(a.x, a.y, b.x, b.y);
-  } else {
-    return gld(p, i);
-  }
-}
-
 // The padded, pre-chirped row (n >= 1).  The common case n = L/2 (the
 // paper's doubled grid) is straight-line code; otherwise loads go to a
 // clamped index (so they still issue back to back) and the padding is
@@ -565,41 +672,15 @@ struct SharedTables {
   static constexpr int src = on ? kTwShared : kTwGlobal;
 };
 
-// Cooperative copies into LDS at the start of a workgroup: the twiddle
-// table, the job's H and, for slots that run several transforms of the job
-// (PRE), the first L/2 entries of its pre-chirp when it has one.  Every
-// thread issues all of its loads before its first LDS write, so that their
-// latencies overlap; a thread past the end of a table reloads its last
-// entry instead of skipping the load, which keeps the loads branch-free.
-template <int N, int THREADS>
-struct CopyShare {
-  static constexpr int K = N > 0 ? (N + THREADS - 1) / THREADS : 0;
-  static constexpr int KA = K > 0 ? K : 1;  // register array size
-};
-template <int N, int THREADS, int KA, bool COH = false>
-__device__ __forceinline__ void copy_load(float4 (&r)[KA], const float2* src, int tid) {
-  const float4* s4 = reinterpret_cast<const float4*>(src);
-#pragma unroll
-  for (int k = 0; k < CopyShare<N, THREADS>::K; ++k) {
-    const int e = tid + k * THREADS;
-    r[k] = gld_c<COH>(s4, (unsigned)(e < N ? e : N - 1));
-  }
-}
-template <int N, int THREADS, int KA>
-__device__ __forceinline__ void copy_store(float2* dst, const float4 (&r)[KA], int tid) {
-  float4* d4 = reinterpret_cast<float4*>(dst);
-#pragma unroll
-  for (int k = 0; k < CopyShare<N, THREADS>::K; ++k) {
-    const int e = tid + k * THREADS;
-    if (N % THREADS == 0 || e < N) d4[e] = r[k];
-  }
-}
-template <int L, int THREADS, bool PRE, int NPRE = L / 2, bool COH = false>
+// Cooperative copies into LDS at the start of a workgroup (see CopyShare):
+// the twiddle table, the job's H and, for slots that run several transforms
+// of the job (PRE), the first L/2 entries of its pre-chirp when it has one.
+template <int L, int THREADS, bool PRE, int NPRE = L / 2, bool COH = false, bool HCOPY = true>
 __device__ __forceinline__ void stage_tables(float2* tws, float2* hs, float2* ps, const float2* __restrict__ tw,
                                              const float2* __restrict__ H, const float2* __restrict__ pre, int tid) {
   static_assert(SharedTables<L>::tw_n % 2 == 0, "tables are copied two entries at a time");
   constexpr int NT = SharedTables<L>::tw_n / 2;
-  constexpr int NH = L / 2;
+  constexpr int NH = HCOPY ? L / 2 : 0;
   constexpr int NP = PRE ? NPRE / 2 : 0;
   float4 a[CopyShare<NT, THREADS>::KA];
   float4 b[CopyShare<NH, THREADS>::KA];
@@ -614,6 +695,14 @@ __device__ __forceinline__ void stage_tables(float2* tws, float2* hs, float2* ps
   if constexpr (PRE) {
     if (pre) copy_store<NP, THREADS>(ps, c, tid);
   }
+}
+// The kernel spectrum H alone into LDS (its copy deferred by stage_tables).
+template <int L, int THREADS, bool COH>
+__device__ __forceinline__ void stage_spectrum(float2* hs, const float2* __restrict__ H, int tid) {
+  constexpr int NH = L / 2;
+  float4 b[CopyShare<NH, THREADS>::KA];
+  copy_load<NH, THREADS, CopyShare<NH, THREADS>::KA, COH>(b, H, tid);
+  copy_store<NH, THREADS>(hs, b, tid);
 }
 
 // A camera sample resized along x (see TileJob): row n of a frame of ns
@@ -945,7 +1034,9 @@ struct ColLds {
   using S = PassShape<L, GC, P>;
   static constexpr bool PF = VAR >= 1 && P > 1;
   static constexpr int CIN = FastIn<L>::RIN * FastIn<L>::TPR;  // rows of the fast kernels' one staging chunk
-  static constexpr int PRE_BYTES = PF ? CIN * 8 : 0;
+  // The pre-chirp copy, then (kernels that evaluate it themselves) the
+  // colscale factors of the tile's GC columns.
+  static constexpr int PRE_BYTES = PF ? CIN * 8 + GC * 8 : 0;
   static constexpr int STAGE_BYTES = S::NS * ((CIN > L / 2 ? CIN : L / 2) + 9) * 8;
   static constexpr int XCH_BYTES =
       S::NS * row_lds_bytes<L, kSplit>() > STAGE_BYTES ? S::NS * row_lds_bytes<L, kSplit>() : STAGE_BYTES;
@@ -955,13 +1046,21 @@ struct ColLds {
 // RM: a persistent launch's real-hologram column tiles read the hologram
 // itself, row-major (RowJob::in_fmt), and turn each round's columns around
 // in an LDS area after the tile's own (kColRmBytes); no column-major copy.
+// SELF (slots of several columns only): the tile evaluates the pre-chirp of
+// its columns and their colscale factors itself from the view's axis jobs
+// (RowJob::ax_pre, ax_scale) instead of reading the chirp tables, so that a
+// persistent launch's column tiles wait for nothing but the kernel spectrum;
+// with DEFER they wait for it (dep(), a call every thread makes) only once
+// their first columns' forward transforms are done, and copy it then.
 template <int L>
 constexpr int col_rm_bytes() {
   return 8 * (FastIn<L>::RIN * FastIn<L>::TPR + 4) * 4;
 }
-template <int L, int GC, int VAR, int P, bool COH = false, bool RM = false, typename TAIL = NoTail>
+template <int L, int GC, int VAR, int P, bool COH = false, bool RM = false, bool SELF = false,
+          bool DEFER = false, typename TAIL = NoTail, typename DEP = NoTail>
 __device__ __forceinline__ void col_body(const PassArgs& args, const float2* __restrict__ tw, const int tile,
-                                         unsigned char* __restrict__ lds, const int tid0, const TAIL& tail = TAIL{}) {
+                                         unsigned char* __restrict__ lds, const int tid0, const TAIL& tail = TAIL{},
+                                         const DEP& dep = DEP{}) {
   using S = PassShape<L, GC, P>;
   constexpr int TPR = S::TPR;
   constexpr int R = L / TPR;
@@ -990,6 +1089,9 @@ __device__ __forceinline__ void col_body(const PassArgs& args, const float2* __r
   float2* ps = reinterpret_cast<float2*>(lds + T::bytes);
   unsigned char* xbuf = lds + T::bytes + PRE_BYTES;
   float2* st = reinterpret_cast<float2*>(xbuf);
+  float2* const csl = ps + ColLds<L, GC, VAR, P>::CIN;  // SELF: colscale of the tile's columns
+  static_assert(!SELF || (PF && (RIN * TPR) % THREADS == 0), "self-evaluated chirps: slots of several columns");
+  static_assert(!DEFER || SELF, "a deferred spectrum goes with self-evaluated chirps");
 
   const int jid = find_job(args, tile);
   const RowJob& J = args.jobs[jid];
@@ -1037,12 +1139,28 @@ __device__ __forceinline__ void col_body(const PassArgs& args, const float2* __r
       if (real_in) load_row<TPR, R, true>(v, static_cast<const float*>(in) + off, pre, n_in, t);
       else load_row<TPR, R, false>(v, static_cast<const float2*>(in) + off, pre, n_in, t);
     }
-    if (colscale) csn = gld_c<COH>(colscale, (unsigned)cl);
+    if constexpr (!SELF) {
+      if (colscale) csn = gld_c<COH>(colscale, (unsigned)cl);
+    }
   };
+  // SELF: the chirps are evaluated before any load is in flight (they need
+  // many registers of their own).
+  if constexpr (SELF) {
+    if (pre) {
+      const AxisJob ay = load_uniform(args.axis + J.ax_pre);
+#pragma unroll
+      for (int k = 0; k < RIN * TPR / THREADS; ++k) ps[tid0 + k * THREADS] = pre_value(ay, tid0 + k * THREADS);
+    }
+    if (colscale && tid0 < GC) {
+      const int c = c0 + tid0;
+      csl[tid0] = pre_value(load_uniform(args.axis + J.ax_scale), c < ncols ? c : ncols - 1);
+    }
+    sched_fence();
+  }
   load(0, t, tid0);
 
   if constexpr (T::on) {
-    stage_tables<L, THREADS, PF, RIN * TPR, COH>(tws, hs, ps, tw, H, pre, tid0);
+    stage_tables<L, THREADS, PF && !SELF, RIN * TPR, COH, !DEFER>(tws, hs, ps, tw, H, pre, tid0);
     __syncthreads();
   }
   const float2* twx = T::on ? tws : tw;
@@ -1084,7 +1202,8 @@ __device__ __forceinline__ void col_body(const PassArgs& args, const float2* __r
       float2* out = out0 + cb + gs;
       float2 cs;
       if constexpr (PF) {
-        cs = csn;
+        if constexpr (SELF) cs = csl[p * NS + g];
+        else cs = csn;
         if constexpr (RM) {
           // The round's columns turned around: slot g takes column g.
 #pragma unroll
@@ -1110,6 +1229,13 @@ __device__ __forceinline__ void col_body(const PassArgs& args, const float2* __r
       }
       fft_row<PassPlan<L>, false, kSplit, T::src, HALF && PRUNE>(v, buf, tl, twx);
       sched_fence();
+      if constexpr (DEFER) {
+        if (p == 0) {
+          dep();
+          stage_spectrum<L, THREADS, COH>(hs, H, tid);
+          __syncthreads();
+        }
+      }
 #pragma unroll
       for (int i = 0; i < R; ++i) v[i] = cmul(v[i], T::on ? hs[tl + TPR * i] : gld(H, (unsigned)(tl + TPR * i)));
       sched_fence();

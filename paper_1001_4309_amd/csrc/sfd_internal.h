@@ -69,6 +69,10 @@ struct RowJob {
   // at the grid's width; 8, 16: camera samples, 33: float32 camera samples,
   // resized from in_ld samples per row as in TileJob).
   int32_t in_fmt;
+  // Column pass: the batch's axis jobs (PassArgs::axis) of the view's y axis
+  // (its pre-chirp) and x axis (colscale), for kernels that evaluate those
+  // chirps themselves instead of reading the tables (persistent launches).
+  int32_t ax_pre, ax_scale;
   int32_t pad_;
 
   // Epilogue reductions (row kernel, kReduce): over the row's outputs V(m),
@@ -102,6 +106,7 @@ constexpr int kMaxJobsPerLaunch = 256;
 
 struct PassArgs {
   const RowJob* jobs;
+  const AxisJob* axis;  // the batch's axis jobs (see RowJob::ax_pre), or nullptr
   int32_t njobs;
   int32_t total_tiles;
   int32_t tile_prefix[kMaxJobsPerLaunch + 1];
@@ -219,7 +224,7 @@ struct PersistArgs {
   int32_t total;          // items over all segments
   int32_t grid;           // workgroups of the launch
   int32_t nview;
-  int32_t wait_setup;     // column tiles wait for their view's setup item (0 when tables are kept)
+  int32_t wait_setup;     // tiles wait for their view's setup items (0 when tables are kept)
   int32_t ncopy;
   int32_t nstrips;        // strip items (all copies)
   int32_t pad_;
@@ -233,10 +238,11 @@ struct PersistArgs {
 // a counter that workgroups poll shares no line with one they advance):
 // [0] ticket, [1] workgroups that left, [2] error word (set when a
 // dependency wait gave up; never reset by the kernel), then per view its
-// setup and column-tile counters, then one counter per strip item.
+// spectra, chirp-table and column-tile counters, then one counter per strip
+// item.
 constexpr int kSyncStride = 64;
 constexpr int kSyncTicket = 0, kSyncExit = 1, kSyncErr = 2, kSyncHead = 3;
-__host__ __device__ inline int persist_sync_counters(int nview, int nstrips) { return kSyncHead + 2 * nview + nstrips; }
+__host__ __device__ inline int persist_sync_counters(int nview, int nstrips) { return kSyncHead + 3 * nview + nstrips; }
 __host__ __device__ inline int persist_sync_words(int nview, int nstrips) {
   return kSyncStride * persist_sync_counters(nview, nstrips);
 }

@@ -108,11 +108,10 @@ template <int L>
 __device__ __forceinline__ void spectrum_half(const AxisJob* J, const float2* tw, unsigned char* lds, int tid) {
   // (spectra written through: later items read them on other XCDs)
   constexpr int TPR = SpecPlan<L>::TPR;
-  constexpr int GS = kSetupThreads / TPR;  // rows per half
   const int half = tid / kSetupThreads, r = tid - half * kSetupThreads;
   const int g = TPR >= 64 ? uniform(r / TPR) : r / TPR;
   const int t = r - g * TPR;
-  spectrum_row<L, true>(g == 0 ? J : nullptr, tw, lds + half * GS * row_lds_bytes<L, kSplit>(), g, t);
+  spectrum_row<L, true>(g == 0 ? J : nullptr, tw, lds + half * SpecShape<L>::BYTES, g, t, r);
 }
 __device__ __forceinline__ void spectra_pass(int L, const AxisJob* jx, const AxisJob* jy, const float2* tw,
                                              unsigned char* lds, int tid) {
@@ -211,13 +210,18 @@ __device__ __forceinline__ void persist_strip(const TileJob* Jp, int c0, unsigne
 // CPLX: the kernel instance for complex holograms (column specialisation 1);
 // the real-hologram instance holds specialisations 2 and 3.  Keeping them
 // apart keeps each instance's register need that of its largest body.
-template <int L, bool CPLX, typename TAIL>
-__device__ __forceinline__ void persist_col(const Segment& sg, int tile, unsigned char* lds, int tid, const TAIL& tail) {
+// Column tiles evaluate their pre-chirp and colscale factors themselves
+// (col_body's SELF), so they depend only on their view's spectra item, and
+// real-hologram tiles wait for it (dep) only before their first spectrum
+// multiply (DEFER).
+template <int L, bool CPLX, typename TAIL, typename DEP>
+__device__ __forceinline__ void persist_col(const Segment& sg, int tile, unsigned char* lds, int tid, const TAIL& tail,
+                                            const DEP& dep) {
   if constexpr (CPLX) {
-    col_body<L, kPG, 1, kPP, true, false>(*sg.args, sg.tw, tile, lds, tid, tail);
+    col_body<L, kPG, 1, kPP, true, false, true>(*sg.args, sg.tw, tile, lds, tid, tail);
   } else {
-    if (sg.var == 2) col_body<L, kPG, 2, kPP, true, true>(*sg.args, sg.tw, tile, lds, tid, tail);
-    else col_body<L, kPG, 3, kPP, true, true>(*sg.args, sg.tw, tile, lds, tid, tail);
+    if (sg.var == 2) col_body<L, kPG, 2, kPP, true, true, true, true>(*sg.args, sg.tw, tile, lds, tid, tail, dep);
+    else col_body<L, kPG, 3, kPP, true, true, true, true>(*sg.args, sg.tw, tile, lds, tid, tail, dep);
   }
 }
 template <int L, typename TAIL>
@@ -235,8 +239,9 @@ __global__ void __launch_bounds__(kPersistThreads) persist_kernel(const PersistA
   const int total = A.total;
   const int nview = A.nview;
   // Counter c is sync[c * kSyncStride].
-  uint32_t* const setup_done = sync + kSyncHead * kSyncStride;
-  uint32_t* const col_done = setup_done + nview * kSyncStride;
+  uint32_t* const spec_done = sync + kSyncHead * kSyncStride;
+  uint32_t* const tab_done = spec_done + nview * kSyncStride;
+  uint32_t* const col_done = tab_done + nview * kSyncStride;
   uint32_t* const strip_done = col_done + nview * kSyncStride;
   if (threadIdx.x == 0) s_ticket = (int)sync_add(&sync[kSyncTicket * kSyncStride], 1u);
   for (;;) {
@@ -265,7 +270,7 @@ __global__ void __launch_bounds__(kPersistThreads) persist_kernel(const PersistA
         // Items 0 .. nview-1: spectra of view i; nview .. 2 nview - 1: tables.
         const int v = local < nview ? local : local - nview;
         persist_setup(A, v, local < nview ? 0 : 1, lds, tid);
-        signal_count(&setup_done[v * kSyncStride]);
+        signal_count(local < nview ? &spec_done[v * kSyncStride] : &tab_done[v * kSyncStride]);
         break;
       }
       case kItemStrip: {
@@ -284,18 +289,22 @@ __global__ void __launch_bounds__(kPersistThreads) persist_kernel(const PersistA
         const int view = J.view;
         const int nsp = (A.tiles[0].nx + kStripW - 1) / kStripW;
         const int strip = J.copy * nsp + (local - PA.tile_prefix[jid]);
-        // Real holograms are read in place (no strips): only the setup.
+        // Complex holograms: the strip and the spectra before the tile
+        // starts.  Real holograms are read in place (no strips), and the
+        // spectra are waited for inside the tile (dep).
         if (A.nstrips > 0)
           wait_counts(sync, &strip_done[strip * kSyncStride], 1u,
-                      A.wait_setup ? &setup_done[view * kSyncStride] : nullptr, 2u);
-        else if (A.wait_setup)
-          wait_counts(sync, &setup_done[view * kSyncStride], 2u, nullptr, 0u);
+                      A.wait_setup ? &spec_done[view * kSyncStride] : nullptr, 1u);
+        uint32_t* const spec = A.wait_setup ? &spec_done[view * kSyncStride] : nullptr;
+        const auto dep = [&]() {
+          if (spec) wait_counts(sync, spec, 1u, nullptr, 0u);
+        };
         switch (sg.L) {
-          case 2048: persist_col<2048, CPLX>(sg, local, lds, tid, tail); break;
-          case 1792: persist_col<1792, CPLX>(sg, local, lds, tid, tail); break;
-          case 1536: persist_col<1536, CPLX>(sg, local, lds, tid, tail); break;
-          case 1280: persist_col<1280, CPLX>(sg, local, lds, tid, tail); break;
-          default: persist_col<1024, CPLX>(sg, local, lds, tid, tail); break;
+          case 2048: persist_col<2048, CPLX>(sg, local, lds, tid, tail, dep); break;
+          case 1792: persist_col<1792, CPLX>(sg, local, lds, tid, tail, dep); break;
+          case 1536: persist_col<1536, CPLX>(sg, local, lds, tid, tail, dep); break;
+          case 1280: persist_col<1280, CPLX>(sg, local, lds, tid, tail, dep); break;
+          default: persist_col<1024, CPLX>(sg, local, lds, tid, tail, dep); break;
         }
         signal_count(&col_done[view * kSyncStride]);
         break;
@@ -303,7 +312,10 @@ __global__ void __launch_bounds__(kPersistThreads) persist_kernel(const PersistA
       default: {
         const PassArgs& PA = *sg.args;
         const int view = PA.jobs[find_job(PA, local)].view;
-        wait_counts(sync, &col_done[view * kSyncStride], (uint32_t)A.col_tiles[view], nullptr, 0u);
+        // The spectra are in (the column tiles waited for them); the post-chirp
+        // comes from the view's tables item.
+        wait_counts(sync, &col_done[view * kSyncStride], (uint32_t)A.col_tiles[view],
+                    A.wait_setup ? &tab_done[view * kSyncStride] : nullptr, 1u);
         switch (sg.L) {
           case 2048: persist_row<2048>(sg, local, lds, tid, tail); break;
           case 1792: persist_row<1792>(sg, local, lds, tid, tail); break;
