@@ -114,34 +114,44 @@ def pass_variant(w, plan, kind: str) -> int:
     return 2 if plan.outputs == "intensity" else 3
 
 
-def traffic_file(config: int) -> str:
-    return os.path.join(ROOT, "profiles", f"pass_kernels_traffic_config{config}.txt")
+def traffic_file(config: int, tag: str) -> str:
+    return os.path.join(ROOT, "profiles", f"{tag}_traffic_config{config}.txt")
+
+
+def _summaries(kind: str, config: int):
+    """(header fields, {kernel: fields}) of every committed summary of this
+    kind and workload whose kernel sources match the current ones."""
+    import glob
+
+    out = []
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", f"*_{kind}_config{config}.txt"))):
+        fields, kernels = {}, {}
+        for line in open(path):
+            line = line.strip()
+            if line.startswith("kernel:"):
+                k, _, rest = line[len("kernel:"):].partition("|")
+                kernels[k.strip()] = dict(kv.split("=") for kv in rest.split())
+            elif ":" in line and not line.startswith("#"):
+                a, _, b = line.partition(":")
+                fields[a.strip()] = b.strip()
+        if fields.get("source-sha256") == kernel_source_hash():
+            out.append((fields, kernels))
+    return out
 
 
 def read_traffic(config: int, name: str):
     """HBM bytes per launch of kernel ``name`` from the committed counter
-    summary, or None when there is none or the kernel sources have changed
+    summaries, or None when there is none or the kernel sources have changed
     since the counters were taken."""
-    path = traffic_file(config)
-    if not os.path.exists(path):
-        return None
-    fields, kernels = {}, {}
-    for line in open(path):
-        line = line.strip()
-        if line.startswith("kernel:"):
-            k, _, rest = line[len("kernel:"):].partition("|")
-            kernels[k.strip()] = dict(kv.split("=") for kv in rest.split())
-        elif ":" in line and not line.startswith("#"):
-            a, _, b = line.partition(":")
-            fields[a.strip()] = b.strip()
-    if fields.get("source-sha256") != kernel_source_hash() or name not in kernels:
-        return None
-    k = kernels[name]
-    return (float(k["fetch_kib"]) * float(fields["fetch-factor"]) +
-            float(k["write_kib"]) * float(fields["write-factor"])) * 1024.0
+    for fields, kernels in _summaries("traffic", config):
+        if name in kernels:
+            k = kernels[name]
+            return (float(k["fetch_kib"]) * float(fields["fetch-factor"]) +
+                    float(k["write_kib"]) * float(fields["write-factor"])) * 1024.0
+    return None
 
 
-def summarize_pmc(fetch_dir: str, write_dir: str, config: int, copy_mib: int, command: str) -> None:
+def summarize_pmc(fetch_dir: str, write_dir: str, config: int, copy_mib: int, command: str, tag: str) -> None:
     """Write the per-kernel traffic summary from two rocprofv3 --pmc runs
     (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch).  The factors scale the
     counters to bytes: a plain device copy of ``copy_mib`` MiB per run reads
@@ -182,7 +192,7 @@ def summarize_pmc(fetch_dir: str, write_dir: str, config: int, copy_mib: int, co
         (fk, n), (wk, _) = fetch[k], write[k]
         lines.append(f"kernel: {k} | fetch_kib={fk:.1f} write_kib={wk:.1f} dispatches={n} "
                      f"hbm_mib={(fk * ff + wk * wf) / 1024:.2f}")
-    with open(traffic_file(config), "w") as fh:
+    with open(traffic_file(config, tag), "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
@@ -310,31 +320,62 @@ def event_stats(plan, holo, outs, n: int):
     torch.cuda.synchronize()
     t = sorted(a.elapsed_time(b) * 1e3 for a, b in ev)
     return {"calls": n, "median_us": t[n // 2], "p10_us": t[n // 10], "p90_us": t[(9 * n) // 10],
-            "how": "hipEvent pair around each call (graph replay) on the launch stream"}
+            "how": "hipEvent pair around each call on the launch stream (one direct launch of the persistent "
+                   "kernel, or one graph replay of the pass schedule)"}
 
 
-def counters_file(config: int) -> str:
-    return os.path.join(ROOT, "profiles", f"valu_counters_config{config}.txt")
+def counters_file(config: int, tag: str) -> str:
+    return os.path.join(ROOT, "profiles", f"{tag}_counters_config{config}.txt")
+
+
+def _pmc_per_kernel(d: str):
+    """{kernel: {counter: mean per dispatch}} from rocprofv3 --pmc CSV output
+    (each dispatch's counter summed over its instances)."""
+    import csv
+    import glob
+
+    acc = {}
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        for row in csv.DictReader(open(f)):
+            name = row["Kernel_Name"].replace("void ", "").replace("sfd::", "").split("(")[0]
+            key = row.get("Dispatch_Id") or row.get("Correlation_Id")
+            per = acc.setdefault(name, {}).setdefault(row["Counter_Name"], {})
+            per[key] = per.get(key, 0.0) + float(row["Counter_Value"])
+    return {k: {c: sum(v.values()) / len(v) for c, v in cs.items()} for k, cs in acc.items()}
+
+
+def summarize_counters(dirs, config: int, command: str, tag: str) -> None:
+    """Write the VALU / LDS counter summary of rocprofv3 --pmc runs (one
+    directory per counter pass) for every kernel they saw."""
+    per = {}
+    for d in dirs:
+        for k, cs in _pmc_per_kernel(d).items():
+            per.setdefault(k, {}).update(cs)
+    lines = [f"# rocprofv3 --pmc counters per dispatch (mean over dispatches), workload config {config}",
+             f"# command: {command}",
+             "# valu_busy = SQ_INSTS_VALU * 4 / (1024 SIMDs * GRBM_GUI_ACTIVE / 8 XCDs): the share of the",
+             "#   kernel's cycles the 1024 SIMDs spend issuing VALU instructions (a wave64 instruction",
+             "#   occupies a 16-lane SIMD for 4 cycles); GRBM_GUI_ACTIVE counts busy cycles summed over the 8 XCDs",
+             f"source-sha256: {kernel_source_hash()}"]
+    for k in sorted(per):
+        cs = per[k]
+        if "copyBuffer" in k or "elementwise" in k or "SQ_INSTS_VALU" not in cs:
+            continue
+        if cs.get("GRBM_GUI_ACTIVE"):
+            cs["valu_busy"] = cs["SQ_INSTS_VALU"] * 4.0 / (1024.0 * cs["GRBM_GUI_ACTIVE"] / 8.0)
+        lines.append(f"kernel: {k} | " + " ".join(f"{c}={v:.4g}" for c, v in sorted(cs.items())))
+    with open(counters_file(config, tag), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 def read_counters(config: int, name: str):
     """VALU and LDS counter figures of kernel ``name`` from the committed
-    summary (see profiles/), or None when absent or stale."""
-    path = counters_file(config)
-    if not os.path.exists(path):
-        return None
-    fields, kernels = {}, {}
-    for line in open(path):
-        line = line.strip()
-        if line.startswith("kernel:"):
-            k, _, rest = line[len("kernel:"):].partition("|")
-            kernels[k.strip()] = {a: float(b) for a, b in (kv.split("=") for kv in rest.split())}
-        elif ":" in line and not line.startswith("#"):
-            a, _, b = line.partition(":")
-            fields[a.strip()] = b.strip()
-    if fields.get("source-sha256") != kernel_source_hash() or name not in kernels:
-        return None
-    return kernels[name]
+    summaries (see profiles/), or None when absent or stale."""
+    for _, kernels in _summaries("counters", config):
+        if name in kernels:
+            return {a: float(b) for a, b in kernels[name].items()}
+    return None
 
 
 def measure(w, dev, args, steps: int, warmup: int, config: int, tune: bool = True, schedule: str = ""):
@@ -391,7 +432,7 @@ def measure(w, dev, args, steps: int, warmup: int, config: int, tune: bool = Tru
     per_step = n_launch / prof_steps
     flops, nbytes = costs[dom][1] / per_step, costs[dom][0] / per_step
     if dom == "persist":
-        dom_name = "persist_kernel"
+        dom_name = f"persist_kernel<{'true' if plan.complex_input else 'false'}>"
     else:
         lx0, ly0 = plan.lengths(0)
         dom_L = lx0 if dom == "pass_x" else ly0
@@ -414,6 +455,17 @@ def measure(w, dev, args, steps: int, warmup: int, config: int, tune: bool = Tru
                 "frac_of_fp32_vector_peak": frac_alu, "frac_of_hbm_peak": frac_hbm,
                 "hbm_GBps": hbm, "fp32_TFLOPs": alu,
                 "counters": read_counters(config, dom_name)}
+    cnt = roofline["counters"]
+    if cnt and "SQ_INSTS_VALU" in cnt:
+        # Measured evidence for the bound: the share of cycles the SIMDs
+        # spent issuing VALU instructions (counters) against the share of the
+        # HBM peak the kernel's measured traffic reached.
+        roofline["valu_insts_per_nominal_flop"] = cnt["SQ_INSTS_VALU"] * 64.0 / flops
+        if "valu_busy" in cnt:
+            hbm_meas = (roofline["traffic"] or nbytes) / avg_s / 1e9 / HBM_PEAK_GBPS
+            roofline["valu_busy"] = cnt["valu_busy"]
+            roofline["hbm_busy"] = hbm_meas
+            roofline["bound_from_counters"] = "alu" if cnt["valu_busy"] >= hbm_meas else "hbm"
     step_bytes = costs["pass_x"][0] + costs["pass_y"][0]
     res = {"workload": w.name, "views_per_step": nv, "views_per_s": nv / sec, "ms_per_step": sec * 1e3,
            "per_call": stats, "launch_mode": mode, "length_policy": plan.length_policy(), "schedule": sched,
@@ -541,13 +593,19 @@ def main():
                     help="tile widths to use instead of autotuning, e.g. col2048=4,row2048=4")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the traffic summary of two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="PMC_DIR",
+                    help="write the VALU / LDS counter summary of rocprofv3 --pmc runs and exit")
     ap.add_argument("--pmc-command", default="", help="command recorded in the traffic summary")
+    ap.add_argument("--profile-tag", default="sfd_kernels", help="file name prefix of a written summary")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (calibrates traffic counters)")
     args = ap.parse_args()
     if args.summarize_pmc:
         summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.config, args.calib_copy_mib,
-                      args.pmc_command)
+                      args.pmc_command, args.profile_tag)
+        return
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters, args.config, args.pmc_command, args.profile_tag)
         return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -654,7 +712,9 @@ def main():
         "config": {"workload": w.name, "holograms": len(w.holograms), "views_per_step": nv,
                    "hologram": [g.ny, g.nx], "views": [[v.grid.ny, v.grid.nx] for v in w.views],
                    "padded_lengths": main_res["lengths"], "phase": "fp64-reduced", "output": "intensity",
-                   "schedule": main_res["schedule"], "launch": "hip-graph replay",
+                   "schedule": main_res["schedule"],
+                   "launch": ("one persistent kernel, launched directly" if main_res["launch_mode"] == "persistent"
+                              else "hip-graph replay of setup, column and row passes"),
                    "launch_mode": main_res["launch_mode"], "length_policy": main_res["length_policy"]},
         "roofline": main_res["roofline"],
         "per_call": main_res["per_call"],

@@ -675,11 +675,11 @@ struct SharedTables {
 // Cooperative copies into LDS at the start of a workgroup (see CopyShare):
 // the twiddle table, the job's H and, for slots that run several transforms
 // of the job (PRE), the first L/2 entries of its pre-chirp when it has one.
-template <int L, int THREADS, bool PRE, int NPRE = L / 2, bool COH = false, bool HCOPY = true>
+template <int L, int THREADS, bool PRE, int NPRE = L / 2, bool COH = false, bool HCOPY = true, bool TWCOPY = true>
 __device__ __forceinline__ void stage_tables(float2* tws, float2* hs, float2* ps, const float2* __restrict__ tw,
                                              const float2* __restrict__ H, const float2* __restrict__ pre, int tid) {
   static_assert(SharedTables<L>::tw_n % 2 == 0, "tables are copied two entries at a time");
-  constexpr int NT = SharedTables<L>::tw_n / 2;
+  constexpr int NT = TWCOPY ? SharedTables<L>::tw_n / 2 : 0;
   constexpr int NH = HCOPY ? L / 2 : 0;
   constexpr int NP = PRE ? NPRE / 2 : 0;
   float4 a[CopyShare<NT, THREADS>::KA];
@@ -812,7 +812,10 @@ struct NoTail {
 // is hoisted out of its item loop).  The same holds for col_body.
 // COH: read what other items of a persistent launch wrote (the input, H,
 // the pre- and post-chirps) with loads coherent across XCDs (gld_c).
-template <int L, int GR, int VAR, int P, bool COH = false, typename TAIL = NoTail>
+// TW_STAGED: the caller has already put the twiddle table into the tile's
+// LDS tables (a persistent launch fetches it while it waits for the view's
+// column tiles).
+template <int L, int GR, int VAR, int P, bool COH = false, bool TW_STAGED = false, typename TAIL = NoTail>
 __device__ __forceinline__ void row_body(const PassArgs& args, const float2* __restrict__ tw, const int tile,
                                          unsigned char* __restrict__ lds, const int tid, const TAIL& tail = TAIL{}) {
   using S = PassShape<L, GR, P>;
@@ -890,6 +893,7 @@ __device__ __forceinline__ void row_body(const PassArgs& args, const float2* __r
       else load_row<TPR, R, false>(v, static_cast<const float2*>(in) + off, pre, n_in, t);
     }
   };
+  static_assert(!TW_STAGED || T::on, "staged twiddles go with LDS tables");
   // PF: rows of the tile by their index in it (valid below tile_rows).
   int r_cur = row0, r_next = 0;
   if constexpr (PF) {
@@ -901,7 +905,7 @@ __device__ __forceinline__ void row_body(const PassArgs& args, const float2* __r
   }
 
   if constexpr (T::on) {
-    stage_tables<L, S::THREADS, PF, RIN * TPR, COH>(tws, hs, ps, tw, H, pre, tid);
+    stage_tables<L, S::THREADS, PF, RIN * TPR, COH, true, !TW_STAGED>(tws, hs, ps, tw, H, pre, tid);
     __syncthreads();
   }
   const float2* twx = T::on ? tws : tw;
@@ -1035,8 +1039,8 @@ struct ColLds {
   static constexpr bool PF = VAR >= 1 && P > 1;
   static constexpr int CIN = FastIn<L>::RIN * FastIn<L>::TPR;  // rows of the fast kernels' one staging chunk
   // The pre-chirp copy, then (kernels that evaluate it themselves) the
-  // colscale factors of the tile's GC columns.
-  static constexpr int PRE_BYTES = PF ? CIN * 8 + GC * 8 : 0;
+  // colscale factors of the tile's GC columns and a flag word.
+  static constexpr int PRE_BYTES = PF ? CIN * 8 + GC * 8 + 16 : 0;
   static constexpr int STAGE_BYTES = S::NS * ((CIN > L / 2 ? CIN : L / 2) + 9) * 8;
   static constexpr int XCH_BYTES =
       S::NS * row_lds_bytes<L, kSplit>() > STAGE_BYTES ? S::NS * row_lds_bytes<L, kSplit>() : STAGE_BYTES;
@@ -1049,9 +1053,11 @@ struct ColLds {
 // SELF (slots of several columns only): the tile evaluates the pre-chirp of
 // its columns and their colscale factors itself from the view's axis jobs
 // (RowJob::ax_pre, ax_scale) instead of reading the chirp tables, so that a
-// persistent launch's column tiles wait for nothing but the kernel spectrum;
-// with DEFER they wait for it (dep(), a call every thread makes) only once
-// their first columns' forward transforms are done, and copy it then.
+// persistent launch's column tiles wait for nothing but the kernel spectrum.
+// DEFER: the first thread asks dep.ready() at the start whether the spectrum
+// is in; if so it is copied with the other tables, otherwise the tile waits
+// for it (dep(), a call every thread makes) only once its first columns'
+// forward transforms are done, and copies it then.
 template <int L>
 constexpr int col_rm_bytes() {
   return 8 * (FastIn<L>::RIN * FastIn<L>::TPR + 4) * 4;
@@ -1143,6 +1149,10 @@ __device__ __forceinline__ void col_body(const PassArgs& args, const float2* __r
       if (colscale) csn = gld_c<COH>(colscale, (unsigned)cl);
     }
   };
+  bool r0 = false;
+  if constexpr (DEFER) {
+    if (tid0 == 0) r0 = dep.ready();
+  }
   // SELF: the chirps are evaluated before any load is in flight (they need
   // many registers of their own).
   if constexpr (SELF) {
@@ -1159,8 +1169,18 @@ __device__ __forceinline__ void col_body(const PassArgs& args, const float2* __r
   }
   load(0, t, tid0);
 
+  bool ready = true;  // the spectrum is copied with the other tables
+  if constexpr (DEFER) {
+    int* const rdy = reinterpret_cast<int*>(csl + GC);
+    if (tid0 == 0) *rdy = r0 ? 1 : 0;
+    __syncthreads();
+    ready = uniform(*rdy) != 0;
+  }
   if constexpr (T::on) {
     stage_tables<L, THREADS, PF && !SELF, RIN * TPR, COH, !DEFER>(tws, hs, ps, tw, H, pre, tid0);
+    if constexpr (DEFER) {
+      if (ready) stage_spectrum<L, THREADS, COH>(hs, H, tid0);
+    }
     __syncthreads();
   }
   const float2* twx = T::on ? tws : tw;
@@ -1230,7 +1250,7 @@ __device__ __forceinline__ void col_body(const PassArgs& args, const float2* __r
       fft_row<PassPlan<L>, false, kSplit, T::src, HALF && PRUNE>(v, buf, tl, twx);
       sched_fence();
       if constexpr (DEFER) {
-        if (p == 0) {
+        if (p == 0 && !ready) {
           dep();
           stage_spectrum<L, THREADS, COH>(hs, H, tid);
           __syncthreads();

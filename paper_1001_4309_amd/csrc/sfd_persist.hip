@@ -210,6 +210,18 @@ __device__ __forceinline__ void persist_strip(const TileJob* Jp, int c0, unsigne
 // CPLX: the kernel instance for complex holograms (column specialisation 1);
 // the real-hologram instance holds specialisations 2 and 3.  Keeping them
 // apart keeps each instance's register need that of its largest body.
+// A column tile's dependency on its view's spectra item (col_body's DEFER):
+// ready() asks without waiting, the call waits (spec null: nothing to wait
+// for, the tables are kept from an earlier call).
+struct SpecDep {
+  uint32_t* sync;
+  const uint32_t* spec;
+  __device__ bool ready() const { return !spec || sync_load(spec) >= 1u; }
+  __device__ void operator()() const {
+    if (spec) wait_counts(sync, spec, 1u, nullptr, 0u);
+  }
+};
+
 // Column tiles evaluate their pre-chirp and colscale factors themselves
 // (col_body's SELF), so they depend only on their view's spectra item, and
 // real-hologram tiles wait for it (dep) only before their first spectrum
@@ -224,10 +236,44 @@ __device__ __forceinline__ void persist_col(const Segment& sg, int tile, unsigne
     else col_body<L, kPG, 3, kPP, true, true, true, true>(*sg.args, sg.tw, tile, lds, tid, tail, dep);
   }
 }
+// A row tile's twiddle table (pairs of entries, at most kTwStageK per
+// thread), fetched by the persistent kernel while it waits for the view's
+// column tiles: loads, then (after the wait) LDS stores.
+constexpr int kTwStageK = (SharedTables<2048>::tw_n / 2 + kPersistThreads - 1) / kPersistThreads;
+__device__ __forceinline__ int twiddle_pairs(int L) {
+  switch (L) {
+    case 2048: return SharedTables<2048>::tw_n / 2;
+    case 1792: return SharedTables<1792>::tw_n / 2;
+    case 1536: return SharedTables<1536>::tw_n / 2;
+    case 1280: return SharedTables<1280>::tw_n / 2;
+    default: return SharedTables<1024>::tw_n / 2;
+  }
+}
+static_assert(SharedTables<1792>::tw_n <= SharedTables<2048>::tw_n && SharedTables<1536>::tw_n <= SharedTables<2048>::tw_n &&
+                  SharedTables<1280>::tw_n <= SharedTables<2048>::tw_n && SharedTables<1024>::tw_n <= SharedTables<2048>::tw_n,
+              "the 2048 table is the longest");
+__device__ __forceinline__ void stage_load(float4 (&a)[kTwStageK], const float2* tw, int n, int tid) {
+  const float4* s4 = reinterpret_cast<const float4*>(tw);
+#pragma unroll
+  for (int k = 0; k < kTwStageK; ++k) {
+    const int e = tid + k * kPersistThreads;
+    a[k] = gld(s4, (unsigned)(e < n ? e : n - 1));
+  }
+}
+__device__ __forceinline__ void stage_store(float2* tws, const float4 (&a)[kTwStageK], int n, int tid) {
+  float4* d4 = reinterpret_cast<float4*>(tws);
+#pragma unroll
+  for (int k = 0; k < kTwStageK; ++k) {
+    const int e = tid + k * kPersistThreads;
+    if (e < n) d4[e] = a[k];
+  }
+}
+
+// Row tiles find their twiddle table already in LDS.
 template <int L, typename TAIL>
 __device__ __forceinline__ void persist_row(const Segment& sg, int tile, unsigned char* lds, int tid, const TAIL& tail) {
-  if (sg.var == 2) row_body<L, kPG, 2, kPP, true>(*sg.args, sg.tw, tile, lds, tid, tail);
-  else row_body<L, kPG, 1, kPP, true>(*sg.args, sg.tw, tile, lds, tid, tail);
+  if (sg.var == 2) row_body<L, kPG, 2, kPP, true, true>(*sg.args, sg.tw, tile, lds, tid, tail);
+  else row_body<L, kPG, 1, kPP, true, true>(*sg.args, sg.tw, tile, lds, tid, tail);
 }
 
 template <bool CPLX>
@@ -295,10 +341,7 @@ __global__ void __launch_bounds__(kPersistThreads) persist_kernel(const PersistA
         if (A.nstrips > 0)
           wait_counts(sync, &strip_done[strip * kSyncStride], 1u,
                       A.wait_setup ? &spec_done[view * kSyncStride] : nullptr, 1u);
-        uint32_t* const spec = A.wait_setup ? &spec_done[view * kSyncStride] : nullptr;
-        const auto dep = [&]() {
-          if (spec) wait_counts(sync, spec, 1u, nullptr, 0u);
-        };
+        const SpecDep dep{sync, A.wait_setup ? &spec_done[view * kSyncStride] : nullptr};
         switch (sg.L) {
           case 2048: persist_col<2048, CPLX>(sg, local, lds, tid, tail, dep); break;
           case 1792: persist_col<1792, CPLX>(sg, local, lds, tid, tail, dep); break;
@@ -312,10 +355,16 @@ __global__ void __launch_bounds__(kPersistThreads) persist_kernel(const PersistA
       default: {
         const PassArgs& PA = *sg.args;
         const int view = PA.jobs[find_job(PA, local)].view;
-        // The spectra are in (the column tiles waited for them); the post-chirp
-        // comes from the view's tables item.
+        // The view's column tiles (and with them its spectra, which they
+        // waited for) and, for the post-chirp, its tables item: waited for
+        // inside the tile, once its twiddle loads are in flight.
+        // The twiddle loads are in flight while the first thread polls.
+        float4 twa[kTwStageK];
+        const int ntw = twiddle_pairs(sg.L);
+        stage_load(twa, sg.tw, ntw, tid);
         wait_counts(sync, &col_done[view * kSyncStride], (uint32_t)A.col_tiles[view],
                     A.wait_setup ? &tab_done[view * kSyncStride] : nullptr, 1u);
+        stage_store(reinterpret_cast<float2*>(lds), twa, ntw, tid);
         switch (sg.L) {
           case 2048: persist_row<2048>(sg, local, lds, tid, tail); break;
           case 1792: persist_row<1792>(sg, local, lds, tid, tail); break;
