@@ -338,15 +338,22 @@ struct sfd_plan_s {
   int raw_nx = 0;                     // sfd_set_raw_input: camera samples per hologram row (0: none)
   int raw_bits = 32;                  // and their size
   void* tw_ready_ws = nullptr;        // workspace whose twiddle tables are current
-  size_t desc_off = 0, desc_bytes = 0;
+  // Two forward descriptor slots (desc_off, desc_off2) of desc_bytes each: a
+  // caller that alternates between two inputs (the streaming loop's two
+  // hologram buffers) finds both images resident and uploads nothing.
+  size_t desc_off = 0, desc_off2 = 0, desc_bytes = 0;
+  int fwd_slot = 0;  // the forward slot of the last call
   size_t ws_bytes = 0;
 
   // Descriptor upload state.
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
   hipEvent_t upload_event = nullptr;
-  std::vector<unsigned char> last_desc[2];  // forward, backward descriptor images
-  void* last_ws[2] = {nullptr, nullptr};
+  std::vector<unsigned char> last_desc[3];  // forward, backward, second forward descriptor images
+  void* last_ws[3] = {nullptr, nullptr, nullptr};
+  void forget_descs() {
+    for (auto& d : last_desc) d.clear();
+  }
 
   // Backward (adjoint and z-derivative) workspace layout, SFD_IN_C64 plans.
   struct BwdLayout {
@@ -392,29 +399,27 @@ struct sfd_plan_s {
     return it != m.end() ? it->second : sfd::rows_per_tile(L, col);
   }
 
-  // Recorded forward launch sequence (batched plans): valid for graph_ws.
+  // Recorded forward launch sequence (batched plans), per forward
+  // descriptor slot, with [0] and without [1] the tables and spectra
+  // (SFD_REUSE_TABLES): valid for graph_ws.
   hipStream_t cap_stream = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  hipGraphExec_t gexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   void* graph_ws = nullptr;
 
-  // The same sequence without the tables and spectra (SFD_REUSE_TABLES).
-  hipGraph_t graph_r = nullptr;
-  hipGraphExec_t gexec_r = nullptr;
   // SFD_REUSE_TABLES: the workspace whose tables and spectra hold the
   // distances tables_z.
   void* tables_ws = nullptr;
   std::vector<double> tables_z;
 
   void drop_graph() {
-    if (gexec) (void)hipGraphExecDestroy(gexec);
-    if (graph) (void)hipGraphDestroy(graph);
-    if (gexec_r) (void)hipGraphExecDestroy(gexec_r);
-    if (graph_r) (void)hipGraphDestroy(graph_r);
-    gexec = nullptr;
-    graph = nullptr;
-    gexec_r = nullptr;
-    graph_r = nullptr;
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) {
+        if (gexec[a][b]) (void)hipGraphExecDestroy(gexec[a][b]);
+        if (graph[a][b]) (void)hipGraphDestroy(graph[a][b]);
+        gexec[a][b] = nullptr;
+        graph[a][b] = nullptr;
+      }
     graph_ws = nullptr;
   }
 
@@ -754,9 +759,9 @@ int persist_segments(const sfd_plan_s* P, const CallDescs& D, bool tables) {
 // workspace address, so the image only changes with the plan's schedule,
 // the call's tables flag and the call's pointers.
 void pack_persist(const sfd_plan_s* P, CallDescs* D, char* ws, bool tables, std::vector<unsigned char>* img,
-                  size_t off_axis, size_t off_tiles, size_t off_rows) {
+                  size_t off_axis, size_t off_tiles, size_t off_rows, size_t base_off) {
   const int V = (int)P->views.size();
-  char* dbase = ws + P->desc_off;
+  char* dbase = ws + base_off;
   const size_t off_pa = align_up(off_rows + sizeof(sfd::RowJob) * D->rows.size());
   const size_t off_pass = off_pa + align_up(sizeof(sfd::PersistArgs));
   const size_t off_ct = off_pass + align_up(sizeof(sfd::PassArgs) * sfd::kMaxSegments);
@@ -1423,6 +1428,8 @@ sfd_status sfd_plan(sfd_plan_t* plan, double wavelength, const sfd_grid* holo_gr
   P->desc_off = off;
   P->desc_bytes = desc_capacity(n_views, (int)ls.size(), (int)P->tiles.size());
   off += P->desc_bytes;
+  P->desc_off2 = off;
+  off += P->desc_bytes;
   for (TileLayout& T : P->tiles) {
     T.off = off;
     off += align_up((size_t)h.nx * col_ld(h.ny) * in_elem);
@@ -1603,8 +1610,8 @@ sfd_status sfd::reconstruct_impl(sfd_plan_s* plan, const void* holo, const doubl
       if (plan->tw_ready_ws == ws) plan->tw_ready_ws = nullptr;
       if (plan->sync_ready_ws == ws) plan->sync_ready_ws = nullptr;
       if (plan->tables_ws == ws) plan->tables_ws = nullptr;
-      if (plan->last_ws[0] == ws) plan->last_ws[0] = nullptr;
-      if (plan->last_ws[1] == ws) plan->last_ws[1] = nullptr;
+      for (auto& lw : plan->last_ws)
+        if (lw == ws) lw = nullptr;
       owner = plan->serial;
     }
   }
@@ -1620,32 +1627,53 @@ sfd_status sfd::reconstruct_impl(sfd_plan_s* plan, const void* holo, const doubl
   }
   CallDescs D;
   if ((st = build_descs(plan, holo, z_or_null, out, ws, &D)) != SFD_OK) return st;
-  std::vector<unsigned char> img;
+  std::vector<unsigned char> img0, img;
   size_t off_axis, off_tw, off_rows, off_tiles;
-  pack_descs(plan, D, &img, &off_axis, &off_tw, &off_rows, &off_tiles);
-  if (plan->persist) {
-    if (plan->persist_grid <= 0) {
-      plan->persist_grid = sfd::persist_resident_blocks();
-      if (plan->persist_grid <= 0) return fail(SFD_ERR_HIP, "occupancy query of the persistent kernel failed");
-    }
-    pack_persist(plan, &D, ws, tables, &img, off_axis, off_tiles, off_rows);
+  pack_descs(plan, D, &img0, &off_axis, &off_tw, &off_rows, &off_tiles);
+  if (plan->persist && plan->persist_grid <= 0) {
+    plan->persist_grid = sfd::persist_resident_blocks();
+    if (plan->persist_grid <= 0) return fail(SFD_ERR_HIP, "occupancy query of the persistent kernel failed");
   }
+  // Forward descriptor slot s (0, 1) at its offset, remembered as image idx.
+  auto slot_off = [&](int s) { return s == 0 ? plan->desc_off : plan->desc_off2; };
+  auto slot_idx = [](int s) { return s == 0 ? 0 : 2; };
+  auto make = [&](int s) {
+    img = img0;
+    if (plan->persist) pack_persist(plan, &D, ws, tables, &img, off_axis, off_tiles, off_rows, slot_off(s));
+  };
+  int slot = 0;
   if (no_alloc) {
-    // Kernel-argument copies instead of the pinned staging buffer (which the
-    // first upload would allocate).
+    // Slot 0, written by kernel-argument copies instead of the pinned staging
+    // buffer (which the first upload would allocate).
+    make(0);
     if (!(plan->last_ws[0] == ws && plan->last_desc[0] == img)) {
       img.resize((img.size() + 3) / 4 * 4, 0);
       SFD_HIP_TRY(sfd::launch_blit(ws + plan->desc_off, img.data(), img.size(), stream));
       plan->last_desc[0] = img;
       plan->last_ws[0] = ws;
     }
-  } else if ((st = upload(plan, 0, img, ws, plan->desc_off, stream)) != SFD_OK) {
-    return st;
+  } else {
+    // The last call's slot if its image is still there, else the other slot
+    // if its image is, else the other slot gets this image (so that two
+    // alternating images both stay resident).
+    const int cand[2] = {plan->fwd_slot, 1 - plan->fwd_slot};
+    bool found = false;
+    for (int c : cand) {
+      make(c);
+      slot = c;
+      if (plan->last_ws[slot_idx(c)] == ws && plan->last_desc[slot_idx(c)] == img) {
+        found = true;
+        break;
+      }
+    }
+    if (!found && (st = upload(plan, slot_idx(slot), img, ws, slot_off(slot), stream)) != SFD_OK) return st;
+    plan->fwd_slot = slot;
   }
-  const auto* d_axis = reinterpret_cast<const sfd::AxisJob*>(ws + plan->desc_off + off_axis);
-  const auto* d_tw = reinterpret_cast<const sfd::TwiddleJob*>(ws + plan->desc_off + off_tw);
-  const auto* d_rows = reinterpret_cast<const sfd::RowJob*>(ws + plan->desc_off + off_rows);
-  const auto* d_tiles = reinterpret_cast<const sfd::TileJob*>(ws + plan->desc_off + off_tiles);
+  const size_t sb = slot_off(slot);
+  const auto* d_axis = reinterpret_cast<const sfd::AxisJob*>(ws + sb + off_axis);
+  const auto* d_tw = reinterpret_cast<const sfd::TwiddleJob*>(ws + sb + off_tw);
+  const auto* d_rows = reinterpret_cast<const sfd::RowJob*>(ws + sb + off_rows);
+  const auto* d_tiles = reinterpret_cast<const sfd::TileJob*>(ws + sb + off_tiles);
 
   // The twiddle tables depend only on the transform shapes: built once per
   // workspace (which stays dedicated to the plan).  The persistent launch's
@@ -1681,8 +1709,8 @@ sfd_status sfd::reconstruct_impl(sfd_plan_s* plan, const void* holo, const doubl
     SFD_HIP_TRY(hipStreamIsCapturing(stream, &cs));
     if (cs == hipStreamCaptureStatusNone) {
       if (plan->graph_ws != ws) plan->drop_graph();
-      hipGraph_t& graph = tables ? plan->graph : plan->graph_r;
-      hipGraphExec_t& gexec = tables ? plan->gexec : plan->gexec_r;
+      hipGraph_t& graph = plan->graph[tables ? 0 : 1][slot];
+      hipGraphExec_t& gexec = plan->gexec[tables ? 0 : 1][slot];
       if (!gexec) {
         // Record on a private stream: the caller's stream is never put in
         // capture mode.
@@ -1920,7 +1948,7 @@ sfd_status sfd_set_launch(sfd_plan_t plan, int32_t mode) {
   if (want != plan->persist) {
     plan->persist = want;
     plan->drop_graph();
-    plan->last_desc[0].clear();  // the descriptor layout differs: upload on the next call
+    plan->forget_descs();  // the descriptor layout differs: upload on the next call
   }
   return SFD_OK;
 }
@@ -1935,7 +1963,7 @@ sfd_status sfd_set_length_policy(sfd_plan_t plan, int32_t smooth) {
   plan->persist_ok = persist_eligible(plan);
   plan->persist = was_persist && plan->persist_ok;
   plan->tables_ws = nullptr;     // spectra of other lengths
-  plan->last_desc[0].clear();
+  plan->forget_descs();
   apply_schedule(plan);          // also drops the recorded graphs
   return SFD_OK;
 }
@@ -2052,7 +2080,12 @@ sfd_status sfd_set_raw_input(sfd_plan_t plan, int32_t nx_raw, int32_t sample_bit
   if ((long)nx_raw * plan->holo.ny > (1L << 28)) return fail(SFD_ERR_UNSUPPORTED, "raw frame larger than 2^28 samples");
   plan->raw_nx = nx_raw;
   plan->raw_bits = nx_raw > 0 ? sample_bits : 32;
+  // Camera input has its own tuned schedule (it reads other data).
+  const size_t cut = plan->shape_sig.find(";raw");
+  if (cut != std::string::npos) plan->shape_sig.erase(cut);
+  if (nx_raw > 0) plan->shape_sig += ";raw" + std::to_string(nx_raw) + "/" + std::to_string(plan->raw_bits);
   plan->drop_graph();
+  plan->forget_descs();
   return SFD_OK;
 }
 
