@@ -268,6 +268,7 @@ def bench_backward(dev, steps: int, warmup: int):
     fields = torch.from_numpy(w.holograms).to(dev)
     outs = plan.new_outputs()
     nv = len(w.views)
+    plan.autotune(fields, reps=5, outs=outs)  # the backward's passes use the same tile widths
     res = plan.reconstruct(fields, outs=outs)
     gi = [2.0 * (res[v] - 0.5 * res[v].mean()) for v in range(nv)]
     torch.cuda.synchronize()
@@ -290,6 +291,8 @@ def bench_backward(dev, steps: int, warmup: int):
     torch.cuda.synchronize()
     fwd = (time.perf_counter() - t0) / steps
     return {"workload": w.name, "fields_per_step": nv, "ms_per_step": sec * 1e3,
+            "schedule": {f"{k[0]}{k[1]}": g for k, g in sorted(plan.schedule().items())},
+            "backward_over_forward": (sec - fwd) / fwd,
             "fields_per_s": nv / sec, "forward_ms": fwd * 1e3, "backward_ms": (sec - fwd) * 1e3,
             "what": "forward (intensity + field) and backward (field gradient + dL/dz), per 16-field batch"}
 

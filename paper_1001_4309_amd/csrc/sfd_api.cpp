@@ -509,7 +509,7 @@ size_t bwd_desc_capacity(int n_views, int n_holo, int n_lengths, int n_tiles) {
   return align_up(sizeof(sfd::AxisJob) * 6 * n_views) + align_up(sizeof(sfd::TwiddleJob) * 2 * n_lengths) +
          align_up(sizeof(sfd::TileJob) * (n_tiles + n_views)) + align_up(sizeof(sfd::RowJob) * 7 * n_views) +
          align_up(sizeof(sfd::GradZJob) * n_views) + align_up(sizeof(sfd::GatherJob) * n_holo) +
-         align_up(sizeof(void*) * n_views);
+         align_up(sizeof(void*) * n_views) + align_up(sizeof(sfd::SumJob) * n_views);
 }
 
 // Persistent launch descriptors after the row jobs: the launch arguments,
@@ -699,18 +699,20 @@ sfd_status build_descs(sfd_plan_s* P, const void* holo, const double* z, void* c
 // Kernel specialisation of a pass over row jobs [i, j) of length L (the
 // rule of launch_pass, see sfd_internal.h).
 int pass_var(const CallDescs& D, int i, int j, int L, bool col) {
-  bool fast = true, no_post = true, int_only = true, all_real = true, all_complex = true;
+  bool fast = true, no_post = true, int_only = true, all_real = true, all_complex = true, reduce = false;
   for (int k = i; k < j; ++k) {
     const sfd::RowJob& r = D.rows[k];
     const int F = sfd::fast_input(L);
-    fast = fast && r.n_in == F && r.n_out <= F && !(r.mode & sfd::kReduce);
+    // The reduction epilogue has a specialised row kernel (3), not a column one.
+    fast = fast && r.n_in == F && r.n_out <= F && (!col || !(r.mode & sfd::kReduce));
+    reduce = reduce || (r.mode & sfd::kReduce);
     no_post = no_post && !(r.mode & sfd::kUsePost);
     int_only = int_only && (r.mode & sfd::kOutIntensity) && !(r.mode & sfd::kOutField);
     all_real = all_real && (r.mode & sfd::kInReal);
     all_complex = all_complex && !(r.mode & sfd::kInReal);
   }
   if (fast && col) return all_complex ? 1 : !all_real ? 0 : no_post ? 2 : 3;
-  if (fast && all_complex) return no_post && int_only ? 2 : 1;
+  if (fast && all_complex) return reduce ? 3 : no_post && int_only ? 2 : 1;
   return 0;
 }
 
@@ -1150,6 +1152,7 @@ sfd_status run_backward(sfd_plan_s* P, void* const* grad_out, void* const* field
   // x pass (R4, stores A^H g, reduces S5) and, for dL/dz, R1 (S1, S2),
   // R2 (S3), R3 (S4).
   std::vector<std::pair<int, sfd::RowJob>> cols, rows;
+  std::vector<sfd::SumJob> sums;
   for (int v = 0; v < V; ++v) {
     const sfd_view& w = P->views[v];
     const sfd_plan_s::BwdLayout& B = P->blay[v];
@@ -1235,13 +1238,29 @@ sfd_status run_backward(sfd_plan_s* P, void* const* grad_out, void* const* field
           j.gref = static_cast<const float2*>(grad_out[v]);
         }
       };
-      // R1: u1 itself; S1 (weight 1) and S2 (weight x1^2 + y1^2).
-      sfd::RowJob r1 = row(B.wf, ldh, B.prexf, B.hxf, B.postxf, w.out.ny, h.nx, w.out.nx,
-                           sfd::kReduce | (from_i ? sfd::kRedIntensity : 0), B.p12);
-      gset(r1);
-      r1.wc[0][3] = 1.0;
-      r1.wc[1][2] = 1.0;
-      rows.push_back({L.lx, r1});
+      // S1 (weight 1) and S2 (weight x1^2 + y1^2): from the caller's field
+      // u1 when it is given (no transform), else from R1, u1 recomputed.
+      if (from_i) {
+        sfd::SumJob sj{};
+        sj.gi = static_cast<const float*>(grad_out[v]);
+        sj.u = static_cast<const float2*>(field_out[v]);
+        sj.partial = reinterpret_cast<double*>(ws + B.p12);
+        sj.nx = w.out.nx;
+        sj.ny = w.out.ny;
+        sj.ld = w.out.nx;
+        sj.nblocks = std::min(64, B.nt_r);
+        sj.xp = fx.p1;
+        sj.xa = fx.a1;
+        sj.yp = fy.p1;
+        sj.ya = fy.a1;
+        sums.push_back(sj);
+      } else {
+        sfd::RowJob r1 = row(B.wf, ldh, B.prexf, B.hxf, B.postxf, w.out.ny, h.nx, w.out.nx, sfd::kReduce, B.p12);
+        gset(r1);
+        r1.wc[0][3] = 1.0;
+        r1.wc[1][2] = 1.0;
+        rows.push_back({L.lx, r1});
+      }
       // R2: A(x0 u0); S3 (weight x1).
       sfd::RowJob r2 = row(B.wf, ldh, B.prexm, B.hxf, B.postxf, w.out.ny, h.nx, w.out.nx, sfd::kReduce, B.p3);
       gset(r2);
@@ -1280,6 +1299,7 @@ sfd_status run_backward(sfd_plan_s* P, void* const* grad_out, void* const* field
       j.p4 = reinterpret_cast<const double*>(ws + B.p4);
       j.p5 = reinterpret_cast<const double*>(ws + B.p5);
       j.n12 = j.n3 = j.n4 = B.nt_r;
+      if (from_i) j.n12 = std::min(64, B.nt_r);
       j.n5 = B.nt_a;
       j.k = k;
       j.z = z_or_null ? z_or_null[v] : P->views[v].z;
@@ -1296,7 +1316,8 @@ sfd_status run_backward(sfd_plan_s* P, void* const* grad_out, void* const* field
   size_t o_gz = o_rows + align_up(sizeof(sfd::RowJob) * 7 * V);
   size_t o_ga = o_gz + align_up(sizeof(sfd::GradZJob) * V);
   size_t o_src = o_ga + align_up(sizeof(sfd::GatherJob) * P->n_holo);
-  const size_t total = o_src + sizeof(void*) * V;
+  size_t o_sum = o_src + align_up(sizeof(void*) * V);
+  const size_t total = o_sum + sizeof(sfd::SumJob) * sums.size();
   if (total > P->bwd_desc_bytes) return fail(SFD_ERR_INTERNAL, "backward descriptor area too small");
   char* dbase = ws + P->bwd_desc_off;
   std::vector<sfd::GatherJob> ga;
@@ -1321,6 +1342,7 @@ sfd_status run_backward(sfd_plan_s* P, void* const* grad_out, void* const* field
   if (!gz.empty()) std::memcpy(img.data() + o_gz, gz.data(), sizeof(sfd::GradZJob) * gz.size());
   if (!ga.empty()) std::memcpy(img.data() + o_ga, ga.data(), sizeof(sfd::GatherJob) * ga.size());
   if (!srcs.empty()) std::memcpy(img.data() + o_src, srcs.data(), sizeof(void*) * srcs.size());
+  if (!sums.empty()) std::memcpy(img.data() + o_sum, sums.data(), sizeof(sfd::SumJob) * sums.size());
   sfd_status st = upload(P, 1, img, ws, P->bwd_desc_off, stream);
   if (st != SFD_OK) return st;
   const auto* d_axis = reinterpret_cast<const sfd::AxisJob*>(dbase + o_axis);
@@ -1340,6 +1362,9 @@ sfd_status run_backward(sfd_plan_s* P, void* const* grad_out, void* const* field
   if ((st = launch_rows(D, d_rows, D.n_pass_x, (int)D.rows.size() - D.n_pass_x, P, ws, stream,
                         SFD_KERNEL_PASS_X)) != SFD_OK)
     return st;
+  if (!sums.empty())
+    SFD_TIMED(P, SFD_KERNEL_OTHER, stream,
+              sfd::launch_sums(reinterpret_cast<const sfd::SumJob*>(dbase + o_sum), (int)sums.size(), 64, stream));
   if (want_z)
     SFD_TIMED(P, SFD_KERNEL_OTHER, stream,
               sfd::launch_gradz(reinterpret_cast<const sfd::GradZJob*>(dbase + o_gz), V, stream));

@@ -586,16 +586,18 @@ __device__ __forceinline__ void load_row(float2 (&v)[R], const void* in, const f
 // the rows it holds (row_accumulate), then across the wavefront and the
 // workgroup in a fixed order, one complex pair per tile into J.partial
 // (reduce_tile).
-template <int TPR, int R>
+// N: the slots that can hold outputs (the first N of the R).
+template <int TPR, int N, int R>
 __device__ __forceinline__ void row_accumulate(const RowJob& J, const float2 (&v)[R], int row, bool valid, int t,
                                                double (&a)[4]) {
+  static_assert(N <= R, "output slots are among the row's slots");
   if (valid) {
     const int n_out = J.n_out;
     const int mode = J.mode;
     const double Y = row * J.yp + J.ya;
     const int64_t base = (int64_t)row * J.red_ld;
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
+    for (int i = 0; i < N; ++i) {
       const int m = t + TPR * i;
       if (m < n_out) {
         float2 G, V;
@@ -781,7 +783,8 @@ __device__ __forceinline__ void apply_half(float2 (&v)[R], const float2 (&x)[RIN
 // small: 0 = any job; 1 = every job of the launch has an input of L/2
 // samples, a complex input, an output of at most L/2 and no reduction (half
 // loads, pruned transforms, no reduction epilogue); 2 = as 1, and the jobs
-// write only intensities.  P > 1: each slot runs several rows in turn.  In
+// write only intensities; 3 = as 1 with the reduction epilogue (over the
+// outputs of the first half).  P > 1: each slot runs several rows in turn.  In
 // the specialisations a slot (one wavefront) takes the rows of its tile one
 // at a time from a counter in LDS, so that a wavefront that gets more of its
 // SIMD takes more rows and the wavefronts of the workgroup finish together;
@@ -825,6 +828,7 @@ __device__ __forceinline__ void row_body(const PassArgs& args, const float2* __r
   constexpr int RB = row_lds_bytes<L, kSplit>();
   constexpr bool FAST = VAR >= 1;
   constexpr bool INT_ONLY = VAR == 2;
+  constexpr bool RED = VAR == 3;
   constexpr bool PF = FAST && P > 1;
   using T = SharedTables<L>;
   static_assert(P == 1 || (T::on && TPR <= 64), "slots of several transforms are single wavefronts with LDS tables");
@@ -1002,8 +1006,8 @@ __device__ __forceinline__ void row_body(const PassArgs& args, const float2* __r
           }
         }
       }
-      if constexpr (!HALF) {
-        if (mode & kReduce) row_accumulate<TPR, R>(J, v, row, valid, tl, acc);
+      if constexpr (!HALF || RED) {
+        if (mode & kReduce) row_accumulate<TPR, RL>(J, v, row, valid, tl, acc);
       }
       if constexpr (PF) {
         prev = row;
@@ -1015,7 +1019,7 @@ __device__ __forceinline__ void row_body(const PassArgs& args, const float2* __r
       tail();
       if (prev >= 0) flush(prev, t);
     }
-    if constexpr (!HALF) {
+    if constexpr (!HALF || RED) {
       if (mode & kReduce)
         reduce_tile<S::NW>(J, acc, tile - args.tile_prefix[jid], reinterpret_cast<double*>(xbuf + NS * RB));
     }

@@ -139,7 +139,7 @@ struct TileJob {
   int32_t nx_src;
   int32_t src_bits;
 };
-constexpr int kTrBlock = 32;  // square block one setup workgroup transposes
+constexpr int kTrBlock = 64;  // square block one setup workgroup transposes (16 loads in flight per thread)
 
 // z-derivative of one view from the reduction partials (see sfd_backward):
 //   dL/dz = Re[(i k - 1/z) S1 - (i pi / (lambda z^2)) (S2 - 2 S3 - 2 S4 + S5)]
@@ -153,6 +153,20 @@ struct GradZJob {
   int32_t n12, n3, n4, n5;  // tiles
   double k, z, lam;
   double* out;
+};
+
+// The first two z-derivative sums of a view straight from its forward field
+// u and dL/dI (gi), when the caller passes the field: with G = 2 gi u,
+// conj(G) u = 2 gi |u|^2 summed with weight 1 (S1) and X^2 + Y^2 (S2) over
+// the view grid (X = m xp + xa, Y = row yp + ya).  Block b of nblocks takes
+// rows [b ny / nblocks, (b + 1) ny / nblocks) and writes its two sums to
+// partial[b * 4 .. + 4] in the layout of the row kernel's tile partials.
+struct SumJob {
+  const float* gi;
+  const float2* u;
+  double* partial;
+  int32_t nx, ny, ld, nblocks;
+  double xp, xa, yp, ya;
 };
 
 // Sum of per-view adjoint results into a hologram's gradient (its real part
@@ -279,6 +293,7 @@ int persist_resident_blocks();
 hipError_t launch_blit(void* dst, const void* src, size_t bytes, hipStream_t s);
 
 hipError_t launch_gradz(const GradZJob* d_jobs, int njobs, hipStream_t s);
+hipError_t launch_sums(const SumJob* d_jobs, int njobs, int max_blocks, hipStream_t s);
 hipError_t launch_gather(const GatherJob* d_jobs, int njobs, int max_n, hipStream_t s);
 
 // Tile widths (transforms per workgroup) a pass supports at length L, the

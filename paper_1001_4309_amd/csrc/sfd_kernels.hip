@@ -185,6 +185,44 @@ __global__ void __launch_bounds__(256) gradz_kernel(const GradZJob* __restrict__
   }
 }
 
+// grid: x = block of the job (blocks past its nblocks return), y = jobs.
+// FP64 per thread, then across the block in a fixed order.
+__global__ void __launch_bounds__(256) sums_kernel(const SumJob* __restrict__ jobs) {
+  __shared__ double sh[16];
+  const SumJob& J = jobs[blockIdx.y];
+  const int b = blockIdx.x;
+  if (b >= J.nblocks) return;
+  const int r0 = (int)((int64_t)b * J.ny / J.nblocks), r1 = (int)((int64_t)(b + 1) * J.ny / J.nblocks);
+  double s1 = 0.0, s2 = 0.0;
+  const int n = (r1 - r0) * J.nx;
+  for (int e = threadIdx.x; e < n; e += 256) {
+    const int row = r0 + e / J.nx, m = e - (row - r0) * J.nx;
+    const int64_t at = (int64_t)row * J.ld + m;
+    const float2 u = J.u[at];
+    const double p = 2.0 * (double)J.gi[at] * ((double)u.x * u.x + (double)u.y * u.y);
+    const double X = m * J.xp + J.xa, Y = row * J.yp + J.ya;
+    s1 += p;
+    s2 += p * (X * X + Y * Y);
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    s1 += __shfl_xor(s1, off, 64);
+    s2 += __shfl_xor(s2, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sh[(threadIdx.x >> 6) * 2] = s1;
+    sh[(threadIdx.x >> 6) * 2 + 1] = s2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double* p = J.partial + (size_t)b * 4;
+    p[0] = sh[0] + sh[2] + sh[4] + sh[6];
+    p[1] = 0.0;
+    p[2] = sh[1] + sh[3] + sh[5] + sh[7];
+    p[3] = 0.0;
+  }
+}
+
 // grid: x covers the largest gradient, y = jobs.
 __global__ void __launch_bounds__(256) gather_kernel(const GatherJob* __restrict__ jobs) {
   const GatherJob& J = jobs[blockIdx.y];
@@ -202,6 +240,12 @@ __global__ void __launch_bounds__(256) gather_kernel(const GatherJob* __restrict
 hipError_t launch_gradz(const GradZJob* d_jobs, int njobs, hipStream_t s) {
   if (njobs <= 0) return hipSuccess;
   hipLaunchKernelGGL(gradz_kernel, dim3(njobs), dim3(256), 0, s, d_jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_sums(const SumJob* d_jobs, int njobs, int max_blocks, hipStream_t s) {
+  if (njobs <= 0 || max_blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(sums_kernel, dim3(max_blocks, njobs), dim3(256), 0, s, d_jobs);
   return hipGetLastError();
 }
 

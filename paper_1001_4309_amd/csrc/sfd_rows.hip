@@ -15,6 +15,7 @@ hipError_t launch_row_pass(int L, int G, int var, const PassArgs& a, const float
 #define SFD_LAUNCH_ROW(l, g, p)                   \
   if (L == l && G == g) {                         \
     if (var == 2) SFD_LAUNCH_V(l, g, p, 2);       \
+    else if (var == 3) SFD_LAUNCH_V(l, g, p, 3);  \
     else if (var == 1) SFD_LAUNCH_V(l, g, p, 1);  \
     else SFD_LAUNCH_V(l, g, p, 0);                \
     return hipGetLastError();                     \
