@@ -108,7 +108,12 @@ enum {
  * Errors: SFD_ERR_INVALID_ARG for non-finite or non-positive lambda or
  * pitches, z == 0 or non-finite, sizes < 1, holo index out of range, missing
  * or conflicting flags; SFD_ERR_UNSUPPORTED when a padded length would exceed
- * 8192 (the largest single-workgroup transform).
+ * 8192, i.e. N0 + N1 - 1 > 8192 on an axis.  The cap is deliberate: a row of
+ * 8192 complex values is the longest transform one workgroup holds in
+ * registers and LDS (256 threads x 32 values, a 66 KiB exchange row), which
+ * covers the paper's grids (L = 2048) and 4096^2 holograms; L = 16384 would
+ * need a transform split over workgroups (a four-step FFT through HBM) and is
+ * not built.
  */
 sfd_status sfd_plan(sfd_plan_t* plan, double wavelength, const sfd_grid* holo_grid,
                     int32_t n_holo, const sfd_view* views, int32_t n_views, uint32_t flags);

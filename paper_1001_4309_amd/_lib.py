@@ -6,7 +6,9 @@ import ctypes
 import os
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libsfd.so")
+# SFD_LIB_PATH: another build of the same library (the tests' sanitized host
+# build); the default is the in-tree libsfd.so.
+LIB_PATH = os.environ.get("SFD_LIB_PATH") or os.path.join(PKG, "libsfd.so")
 
 SFD_OK = 0
 SFD_ERR_INVALID_ARG = 1

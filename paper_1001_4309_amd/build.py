@@ -62,5 +62,34 @@ def build(verbose: bool = False, extra=None) -> str:
     return LIB
 
 
+SAN_LIB = os.path.join(PKG, "_build", "libsfd_san.so")
+
+
+def build_sanitized(verbose: bool = False) -> str:
+    """The library with its host code (sfd_api.cpp: planning, validation,
+    descriptors) built with AddressSanitizer and UndefinedBehaviorSanitizer,
+    linked with the kernel objects of the last build().  Loaded only by the
+    CPU tests of the boundary, with the sanitizer runtime preloaded."""
+    tmp = os.path.join(PKG, "_build")
+    obj = os.path.join(tmp, "sfd_api_san.o")
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined"]
+    cmd = [hipcc(), "--offload-arch=gfx950", "-O1", "-g", "-std=c++17", "-fPIC", "-I", os.path.join(ROOT, "include"),
+           "-I", CSRC] + san + ["-c", os.path.join(CSRC, "sfd_api.cpp"), "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("sanitized compile of sfd_api.cpp failed")
+    objs = [obj] + [os.path.join(tmp, src + ".o") for src in SOURCES if src != "sfd_api.cpp"]
+    r = subprocess.run([hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", SAN_LIB] + objs,
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("link of the sanitized library failed")
+    return SAN_LIB
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
