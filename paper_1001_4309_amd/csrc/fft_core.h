@@ -429,11 +429,16 @@ __device__ __forceinline__ int lds_ridx(int t, int i) {
 // transforms that run alone, where waiting for table reads would dominate.
 enum TwSrc { kTwGlobal = 0, kTwShared = 1, kTwCompute = 2, kTwPower = 3 };
 
+// When Ns divides TPR every butterfly of a thread has the same j mod Ns, so
+// one set of twiddles serves them all (SAME): loaded once, held once.
 template <int TPR, int R, int r, int Ns, int TWS = kTwGlobal>
 struct StageTw {
   static constexpr int nb = R / r;
   static constexpr bool any = Ns > 1;
-  float2 w[any ? nb : 1][any ? r - 1 : 1];
+  static constexpr bool SAME = any && TPR % Ns == 0 && TWS != kTwPower;
+  static constexpr int nq = SAME ? 1 : nb;
+  float2 w[any ? nq : 1][any ? r - 1 : 1];
+  __device__ __forceinline__ float2 get(int q, int k) const { return w[SAME ? 0 : q][k]; }
   __device__ __forceinline__ void load(int t, const float2* __restrict__ tw) {
     if constexpr (any && TWS == kTwPower) {
 #pragma unroll
@@ -460,7 +465,7 @@ struct StageTw {
       }
     } else if constexpr (any) {
 #pragma unroll
-      for (int q = 0; q < nb; ++q) {
+      for (int q = 0; q < nq; ++q) {
         const unsigned jm = (unsigned)(t + TPR * q) & (unsigned)(Ns - 1);
 #pragma unroll
         for (int k = 1; k < r; ++k) {
@@ -510,7 +515,7 @@ __device__ __forceinline__ void stage_compute(float2 (&v)[L / TPR], void* __rest
     for (int k = kin; k < r; ++k) b[k] = make_float2(0.f, 0.f);  // not read by dft_half_in
     if constexpr (Ns > 1) {
 #pragma unroll
-      for (int k = 1; k < kin; ++k) b[k] = INV ? cmulc(b[k], W.w[q][k - 1]) : cmul(b[k], W.w[q][k - 1]);
+      for (int k = 1; k < kin; ++k) b[k] = INV ? cmulc(b[k], W.get(q, k - 1)) : cmul(b[k], W.get(q, k - 1));
     }
     if constexpr (PRUNE == 1) dft_half_in<r, INV>(b);
     else if constexpr (PRUNE == 2) dft_low_out<r, INV>(b);
