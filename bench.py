@@ -290,7 +290,19 @@ def bench_backward(dev, steps: int, warmup: int):
         plan.reconstruct(fields, outs=outs)
     torch.cuda.synchronize()
     fwd = (time.perf_counter() - t0) / steps
-    return {"workload": w.name, "fields_per_step": nv, "ms_per_step": sec * 1e3,
+    # Algorithmic work: the forward is two passes of transforms, the backward
+    # six (the adjoint's two, and four for the z-moment fields of dL/dz).
+    fwd_fl = bwd_fl = 0.0
+    g = w.holo_grid
+    for v, view in enumerate(w.views):
+        lx, ly = plan.lengths(v)
+        fwd_fl += g.nx * row_flops(ly) + view.grid.ny * row_flops(lx)
+        bwd_fl += (view.grid.nx + 2 * g.nx) * row_flops(ly) + (g.ny + 2 * view.grid.ny) * row_flops(lx)
+    bwd_s = sec - fwd
+    extra = {"forward_TFLOPs": fwd_fl / fwd / 1e12, "backward_TFLOPs": bwd_fl / bwd_s / 1e12,
+             "backward_frac_of_fp32_vector_peak": bwd_fl / bwd_s / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
+             "algorithmic_gflop_forward": fwd_fl / 1e9, "algorithmic_gflop_backward": bwd_fl / 1e9}
+    return {**extra, "workload": w.name, "fields_per_step": nv, "ms_per_step": sec * 1e3,
             "schedule": {f"{k[0]}{k[1]}": g for k, g in sorted(plan.schedule().items())},
             "backward_over_forward": (sec - fwd) / fwd,
             "fields_per_s": nv / sec, "forward_ms": fwd * 1e3, "backward_ms": (sec - fwd) * 1e3,

@@ -185,7 +185,7 @@ struct GatherJob {
 // registers), pre/post chirp tables, FFT twiddle tables, hologram column
 // tiles.  The roles are independent of each other.
 enum : int32_t { kRoleSpectrum = 0, kRoleTables = 1, kRoleTwiddles = 2, kRoleTiles = 3 };
-constexpr int kMaxSetupRoles = 32;
+constexpr int kMaxSetupRoles = 64;  // SetupArgs stays well inside the 4 KiB kernel-argument space
 struct SetupRole {
   int32_t kind;
   int32_t first_block, nblocks;
@@ -202,6 +202,7 @@ struct SetupArgs {
   int32_t max_l;  // longest spectrum of the launch (0 if none)
   SetupRole roles[kMaxSetupRoles];
 };
+static_assert(sizeof(SetupArgs) <= 4096, "setup arguments are passed by value as kernel arguments");
 constexpr int kSetupThreads = 256;
 
 // Persistent launch: every stage of a batch in one launch.  Workgroups take

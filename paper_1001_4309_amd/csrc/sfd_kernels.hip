@@ -7,17 +7,22 @@
 // (step 2), FFT (step 4), multiply by the kernel spectrum (step 7), inverse
 // FFT (step 8), crop (step 9), then the post-chirp or |.|^2 (step 10, Eq. 5).
 //
+// This file holds the kernels around the passes; the pass bodies are in
+// sfd_device.h, instantiated as col_kernel (sfd_cols.hip), row_kernel
+// (sfd_rows.hip) and inside persist_kernel (sfd_persist.hip).
+//
 //  setup_kernel    everything a batch needs before the passes, by role:
 //                  kernel spectra FFT_L(h)/L per view and axis (steps 5-6,
 //                  per axis since h of Eq. 4 is separable), the pre/post
 //                  chirp tables of Eqs. (2)-(3) (phases reduced in FP64),
 //                  the FFT twiddle tables, and the column-major hologram
 //                  copies the column pass reads.
-//  col_kernel      the y transforms: G columns per workgroup, stores
-//                  leaving through LDS staging so that global accesses are
-//                  G elements wide; writes the N1y x N0x intermediate.
-//  row_kernel      the x transforms: one row per TPR threads, contiguous
-//                  loads and stores straight from registers.
+//  gradz_kernel    dL/dz of each view from its five FP64 sums.
+//  sums_kernel     the first two of those sums from the caller's forward
+//                  field and dL/dI.
+//  gather_kernel   per-hologram sums of the per-view adjoints.
+//  blit_kernel     descriptor images written from kernel arguments (the
+//                  no-allocation entry point).
 #include "sfd_device.h"
 
 namespace sfd {
