@@ -124,6 +124,32 @@ def test_z_override_and_repeated_calls():
     assert torch.equal(first, third)
 
 
+@pytest.mark.parametrize("persistent", [False, True])
+def test_alternating_inputs_keep_their_descriptors(persistent):
+    """Calls that cycle over several input buffers (two descriptor slots, a
+    recorded graph per slot): every call's result equals that of a fresh
+    plan on the same input, bit for bit, and the oracle's."""
+    w = workloads.config2()
+    r = np.random.default_rng(41)
+    base = np.ascontiguousarray(w.holograms).astype(np.float32)
+    holos = [torch.from_numpy((base * r.uniform(0.8, 1.2, base.shape)).astype(np.float32)).to(DEV)
+             for _ in range(3)]
+    ref_plan = _plan(w)
+    refs = [ref_plan.reconstruct(hh)[0].clone() for hh in holos]
+    p = _plan(w)
+    if persistent:
+        p.set_launch(True)
+    else:
+        p.set_launch(False)
+    for k in (0, 1, 0, 1, 2, 0, 2, 2, 1):
+        got = p.reconstruct(holos[k])[0]
+        torch.cuda.synchronize()
+        assert torch.equal(got, refs[k]), (persistent, k)
+    ref = oracle.intensity(oracle_field(workloads.Workload(w.name, w.wavelength, w.holo_grid,
+                                                          holos[2].cpu().numpy(), w.views), 0))
+    check(refs[2].cpu().numpy(), ref, "third input, view 0")
+
+
 def test_fp32_phase_variant_runs_and_is_reported():
     """The all-FP32 phase variant is a comparison path: its error is printed,
     and it must stay finite; the FP64-reduced default must meet the bar."""
