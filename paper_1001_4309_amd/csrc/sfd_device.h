@@ -606,10 +606,6 @@ __device__ __forceinline__ void row_accumulate(const RowJob& J, const float2 (&v
           V = (mode & kRedRealRef)
                   ? make_float2(gld(reinterpret_cast<const float*>(J.uref) + base, (unsigned)m), 0.f)
                   : gld(J.uref + base, (unsigned)m);
-        } else if (mode & kRedIntensity) {
-          const float gi = 2.0f * gld(J.giref + base, (unsigned)m);
-          G = make_float2(gi * v[i].x, gi * v[i].y);
-          V = v[i];
         } else if (J.giref) {
           const float gi = 2.0f * gld(J.giref + base, (unsigned)m);
           const float2 u = gld(J.uref + base, (unsigned)m);
@@ -619,15 +615,8 @@ __device__ __forceinline__ void row_accumulate(const RowJob& J, const float2 (&v
           G = gld(J.gref + base, (unsigned)m);
           V = v[i];
         }
-        double pr, pi;
-        if (mode & kRedIntensity) {
-          // conj(2 gi V) V = 2 gi |V|^2: real by construction.
-          pr = (double)G.x * V.x + (double)G.y * V.y;
-          pi = 0.0;
-        } else {
-          pr = (double)G.x * V.x + (double)G.y * V.y;
-          pi = (double)G.x * V.y - (double)G.y * V.x;
-        }
+        const double pr = (double)G.x * V.x + (double)G.y * V.y;
+        const double pi = (double)G.x * V.y - (double)G.y * V.x;
         const double X = m * J.xp + J.xa;
         const double r2 = X * X + Y * Y;
         const double w0 = J.wc[0][0] * X + J.wc[0][1] * Y + J.wc[0][2] * r2 + J.wc[0][3];

@@ -78,8 +78,7 @@ struct RowJob {
   // Epilogue reductions (row kernel, kReduce): over the row's outputs V(m),
   //   acc_k += conj(G) * w_k * V,  w_k = wc[k][0] X + wc[k][1] Y + wc[k][2] (X^2 + Y^2) + wc[k][3],
   // X = m xp + xa, Y = row yp + ya (coordinates of the output grid), with
-  // G = gref[row][m] or, when giref is set, G = 2 giref[row][m] uref[row][m]
-  // (kRedIntensity: G = 2 giref V, so conj(G) V = 2 giref |V|^2 exactly).
+  // G = gref[row][m] or, when giref is set, G = 2 giref[row][m] uref[row][m].
   // kRedSwap instead takes G = V and V = uref[row][m].  Each tile writes its
   // two complex FP64 sums to partial[tile * 4 .. + 4].
   const float2* gref;
@@ -98,7 +97,6 @@ enum : int32_t {
   kOutField = 16,
   kReduce = 32,
   kRedSwap = 64,
-  kRedIntensity = 128,
   kRedRealRef = 256,  // kRedSwap with a real reference: uref points to float32 values
 };
 
