@@ -172,7 +172,10 @@ sfd_status sfd_reconstruct(sfd_plan_t plan, const void* holo, const double* z_or
  *               Otherwise each is float32 dL/dI and g = 2 (dL/dI) u1 is formed
  *               on the device.
  *   field_out   NULL, or host array of n_views device pointers to the complex64
- *               fields u1 of the forward call (SFD_OUT_FIELD plan or saved)
+ *               fields u1 of the forward call (SFD_OUT_FIELD plan or saved) at
+ *               the same distances; the first two sums of dL/dz are then taken
+ *               from them directly (no forward pass is recomputed), so they
+ *               must be that call's fields
  *   holo        device, the forward's inputs (complex64, or float32 for a real
  *               plan; needed for dL/dz)
  *   z_or_null   as in sfd_reconstruct
