@@ -263,6 +263,28 @@ def test_autotune_keeps_results_and_seeds_new_plans():
     assert _plan(w).schedule() == sched
 
 
+def test_autotune_writes_the_schedule_cache(tmp_path, monkeypatch):
+    """With SFD_TUNE_CACHE set, a tuned schedule is written to the JSON file
+    under the plan's key (architecture, schedule version, shapes, flags),
+    with the tile widths, launch mode and length policy the plan now uses."""
+    import json
+
+    path = tmp_path / "schedule.json"
+    monkeypatch.setenv("SFD_TUNE_CACHE", str(path))
+    w = workloads.config1()
+    p = _plan(w)
+    sched = p.autotune(_holo(w), reps=2)
+    d = json.loads(path.read_text())
+    assert d["format"] == "sfd-schedule-cache"
+    entries = [e for k, e in d["entries"].items() if k.startswith("gfx950|") and "256x256/1/" in k]
+    assert len(entries) == 1, d["entries"].keys()
+    e = entries[0]
+    for (kind, L), g in sched.items():
+        assert e[kind][str(L)] == g
+    assert e["persist"] == (1 if p.launch_mode()[0] == "persistent" else 0)
+    assert e["smooth"] == sfd.sfd_length_policy(p.handle)
+
+
 def test_caller_captured_graph_replays():
     """A caller that captures a reconstruction into its own graph (the
     library then launches into the capture): every replay, with eager work
