@@ -8,7 +8,8 @@
 // output in natural order in the same slots, and an inverse transform can
 // start from a forward transform's output with no exchange in between.
 // Between stages the values go through LDS once (written in the stage's
-// output order, read back as t + TPR * i).
+// output order, read back as t + TPR * i), or, where they only move between
+// lanes 16 or 32 apart, through lane swaps in registers.
 //
 // When TPR <= 64 a row lives inside one wavefront, so an exchange needs only
 // wave-level ordering of the LDS accesses, no workgroup barrier.
@@ -573,6 +574,70 @@ __device__ __forceinline__ void stage_exchange(float2 (&v)[L / TPR], void* __res
   }
 }
 
+// Lane swaps.  v_permlane32_swap exchanges the upper 32 lanes of its first
+// operand with the lower 32 lanes of its second; v_permlane16_swap exchanges
+// the odd 16-lane rows of its first operand with the even rows of its second.
+// Either way, with a value bound for the lower lanes (lane bit clear) first
+// and one bound for the upper lanes second, every lane is left holding the
+// value that came from a lower lane first and the one from an upper lane
+// second.
+template <int D>
+__device__ __forceinline__ void swap_lanes(float2& x, float2& y) {
+  static_assert(D == 16 || D == 32, "lane swaps exist at distance 16 and 32");
+  const uint32_t ax = __float_as_uint(x.x), ay = __float_as_uint(x.y);
+  const uint32_t bx = __float_as_uint(y.x), by = __float_as_uint(y.y);
+  if constexpr (D == 32) {
+    const auto re = __builtin_amdgcn_permlane32_swap(ax, bx, false, false);
+    const auto im = __builtin_amdgcn_permlane32_swap(ay, by, false, false);
+    x = make_float2(__uint_as_float(re[0]), __uint_as_float(im[0]));
+    y = make_float2(__uint_as_float(re[1]), __uint_as_float(im[1]));
+  } else {
+    const auto re = __builtin_amdgcn_permlane16_swap(ax, bx, false, false);
+    const auto im = __builtin_amdgcn_permlane16_swap(ay, by, false, false);
+    x = make_float2(__uint_as_float(re[0]), __uint_as_float(im[0]));
+    y = make_float2(__uint_as_float(re[1]), __uint_as_float(im[1]));
+  }
+}
+
+// Exchange after stage (Ns, r) of a row of TPR <= 64 threads when Ns >= 16
+// and m = TPR / Ns divides r.  Butterfly q of thread t (j = t + TPR q) writes
+// output k to element (t - t mod Ns + TPR q) r + t mod Ns + Ns k, which is
+// lane t mod Ns + Ns (k mod m) of the row, slot (t / Ns)(r / m) + q r + k / m:
+// only the lane bits above Ns change, from the source group g = t / Ns to the
+// destination group k mod m.  One round of lane swaps per such bit (distance
+// Ns, and 2 Ns when m = 4) moves every value to its lane in registers, with
+// no LDS round trip and no wait; the values then sit by source group g.
+template <int TPR, int r, int Ns, bool SPLIT>
+constexpr bool kLaneSwap = SPLIT && TPR <= 64 && Ns >= 16 && Ns < TPR && TPR % Ns == 0 &&
+                           r % (TPR / Ns) == 0 && (r & (r - 1)) == 0;
+
+template <int TPR, int R, int r, int Ns>
+__device__ __forceinline__ void lane_swap_exchange(float2 (&v)[R]) {
+  constexpr int nb = R / r;
+  constexpr int m = TPR / Ns;
+  static_assert(m == 2 || m == 4, "one or two rounds of lane swaps");
+  float2 w[R];
+#pragma unroll
+  for (int q = 0; q < nb; ++q) {
+#pragma unroll
+    for (int kk = 0; kk < r / m; ++kk) {
+      float2 e[m];  // indexed by destination group, then by source group
+#pragma unroll
+      for (int c = 0; c < m; ++c) e[c] = v[q + (kk * m + c) * nb];
+#pragma unroll
+      for (int c = 0; c < m; c += 2) swap_lanes<Ns>(e[c], e[c + 1]);
+      if constexpr (m == 4) {
+        swap_lanes<2 * Ns>(e[0], e[2]);
+        swap_lanes<2 * Ns>(e[1], e[3]);
+      }
+#pragma unroll
+      for (int g = 0; g < m; ++g) w[g * (r / m) + q * r + kk] = e[g];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < R; ++i) v[i] = w[i];
+}
+
 // Stage (Ns, r) with its twiddles W already loaded; loads the next stage's
 // twiddles before this stage's exchange.
 template <int L, int TPR, bool INV, bool SPLIT, int TWS, bool HALF, int Ns, int OFF, int r, int... rest>
@@ -586,7 +651,12 @@ __device__ __forceinline__ void fft_stages(float2 (&v)[L / TPR], void* buf, int 
     constexpr int rn = Radices<rest...>::first;
     StageTw<TPR, L / TPR, rn, Ns * r, TWS> Wn;
     Wn.load(t, tw + next_off);
-    stage_exchange<L, TPR, r, Ns, SPLIT>(v, buf, t);
+    if constexpr (kLaneSwap<TPR, r, Ns, SPLIT>) {
+      lane_swap_exchange<TPR, L / TPR, r, Ns>(v);
+      __builtin_amdgcn_sched_barrier(0);
+    } else {
+      stage_exchange<L, TPR, r, Ns, SPLIT>(v, buf, t);
+    }
     fft_stages<L, TPR, INV, SPLIT, TWS, HALF, Ns * r, next_off, rest...>(v, buf, t, tw, Wn);
   }
 }
