@@ -25,6 +25,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace sfd {
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
@@ -440,6 +442,8 @@ struct StageTw {
   static constexpr int nq = SAME ? 1 : nb;
   float2 w[any ? nq : 1][any ? r - 1 : 1];
   __device__ __forceinline__ float2 get(int q, int k) const { return w[SAME ? 0 : q][k]; }
+  __device__ __forceinline__ void begin(int) {}
+  __device__ __forceinline__ void end(int) {}
   __device__ __forceinline__ void load(int t, const float2* __restrict__ tw) {
     if constexpr (any && TWS == kTwPower) {
 #pragma unroll
@@ -485,6 +489,41 @@ struct StageTw {
   }
 };
 
+// Twiddles of one stage fetched per butterfly, one butterfly ahead, so that
+// two butterflies' worth are held at a time instead of the whole stage's.
+// Used after a lane-swap exchange, which leaves no LDS round trip to hide a
+// whole stage's twiddle loads behind and so gains nothing from loading them
+// early.
+template <int TPR, int R, int r, int Ns, int TWS>
+struct StageTwStream {
+  static_assert(TWS == kTwGlobal || TWS == kTwShared, "streamed twiddles come from a table");
+  static constexpr int nb = R / r;
+  float2 cur[r - 1], nxt[r - 1];
+  const float2* tw;
+  int t;
+  __device__ __forceinline__ void fetch(float2 (&w)[r - 1], int q) const {
+    const unsigned jm = (unsigned)(t + TPR * q) & (unsigned)(Ns - 1);
+#pragma unroll
+    for (int k = 1; k < r; ++k)
+      w[k - 1] = TWS == kTwShared ? tw[(k - 1) * Ns + (int)jm] : gld(tw, (unsigned)((k - 1) * Ns) + jm);
+  }
+  __device__ __forceinline__ void load(int t_, const float2* tw_) {
+    t = t_;
+    tw = tw_;
+    fetch(cur, 0);
+  }
+  __device__ __forceinline__ void begin(int q) {
+    if (q + 1 < nb) fetch(nxt, q + 1);
+  }
+  __device__ __forceinline__ float2 get(int, int k) const { return cur[k]; }
+  __device__ __forceinline__ void end(int q) {
+    if (q + 1 < nb) {
+#pragma unroll
+      for (int k = 0; k < r - 1; ++k) cur[k] = nxt[k];
+    }
+  }
+};
+
 // Butterflies of one Stockham stage.  v[i] holds element t + TPR * i of the
 // stage input.  The outputs stay in v (butterfly q's output k in slot
 // q + k nb, which for the last stage is natural order) unless the exchange
@@ -493,9 +532,8 @@ struct StageTw {
 // half of a forward transform's first stage); 2 = only the lower half of
 // every butterfly's outputs is needed (the cropped half of an inverse
 // transform's last stage; the slots of the upper half are left as they are).
-template <int L, int TPR, int r, int Ns, bool INV, bool LAST, bool SPLIT, int TWS, int PRUNE = 0>
-__device__ __forceinline__ void stage_compute(float2 (&v)[L / TPR], void* __restrict__ buf, int t,
-                                              const StageTw<TPR, L / TPR, r, Ns, TWS>& W) {
+template <int L, int TPR, int r, int Ns, bool INV, bool LAST, bool SPLIT, int PRUNE, class TWH>
+__device__ __forceinline__ void stage_compute(float2 (&v)[L / TPR], void* __restrict__ buf, int t, TWH& W) {
   constexpr int R = L / TPR;
   constexpr int nb = R / r;
   static_assert(R % r == 0, "radix must divide the values per thread");
@@ -508,6 +546,7 @@ __device__ __forceinline__ void stage_compute(float2 (&v)[L / TPR], void* __rest
 #pragma unroll
   for (int q = 0; q < nb; ++q) {
     const int j = t + TPR * q;
+    W.begin(q);
     float2 b[r];
     constexpr int kin = PRUNE == 1 ? r / 2 : r;
 #pragma unroll
@@ -521,6 +560,7 @@ __device__ __forceinline__ void stage_compute(float2 (&v)[L / TPR], void* __rest
     if constexpr (PRUNE == 1) dft_half_in<r, INV>(b);
     else if constexpr (PRUNE == 2) dft_low_out<r, INV>(b);
     else dft<r, INV>(b);
+    W.end(q);
     if constexpr (nb > 1) sched_fence();
     if constexpr (LAST || SPLIT) {
       constexpr int kout = PRUNE == 2 ? r / 2 : r;
@@ -638,32 +678,37 @@ __device__ __forceinline__ void lane_swap_exchange(float2 (&v)[R]) {
   for (int i = 0; i < R; ++i) v[i] = w[i];
 }
 
-// Stage (Ns, r) with its twiddles W already loaded; loads the next stage's
-// twiddles before this stage's exchange.
-template <int L, int TPR, bool INV, bool SPLIT, int TWS, bool HALF, int Ns, int OFF, int r, int... rest>
-__device__ __forceinline__ void fft_stages(float2 (&v)[L / TPR], void* buf, int t, const float2* tw,
-                                           const StageTw<TPR, L / TPR, r, Ns, TWS>& W) {
+// Stage (Ns, r) with its twiddles W already loaded (or, streamed, their
+// first butterfly's); loads the next stage's before this stage's exchange.
+template <int L, int TPR, bool INV, bool SPLIT, int TWS, bool HALF, int Ns, int OFF, int r, int... rest, class TWH>
+__device__ __forceinline__ void fft_stages(float2 (&v)[L / TPR], void* buf, int t, const float2* tw, TWH& W) {
   constexpr bool last = sizeof...(rest) == 0;
   constexpr int prune = !HALF ? 0 : (!INV && Ns == 1) ? 1 : (INV && last) ? 2 : 0;
-  stage_compute<L, TPR, r, Ns, INV, last, SPLIT, TWS, prune>(v, buf, t, W);
+  stage_compute<L, TPR, r, Ns, INV, last, SPLIT, prune>(v, buf, t, W);
   if constexpr (!last) {
     constexpr int next_off = OFF + (Ns > 1 ? (r - 1) * Ns : 0);
     constexpr int rn = Radices<rest...>::first;
-    StageTw<TPR, L / TPR, rn, Ns * r, TWS> Wn;
-    Wn.load(t, tw + next_off);
     if constexpr (kLaneSwap<TPR, r, Ns, SPLIT>) {
+      using Full = StageTw<TPR, L / TPR, rn, Ns * r, TWS>;
+      using Stream = StageTwStream<TPR, L / TPR, rn, Ns * r, TWS>;
+      constexpr bool stream = !Full::SAME && Full::nq > 1 && (TWS == kTwGlobal || TWS == kTwShared);
+      std::conditional_t<stream, Stream, Full> Wn;
+      Wn.load(t, tw + next_off);
       lane_swap_exchange<TPR, L / TPR, r, Ns>(v);
       __builtin_amdgcn_sched_barrier(0);
+      fft_stages<L, TPR, INV, SPLIT, TWS, HALF, Ns * r, next_off, rest...>(v, buf, t, tw, Wn);
     } else {
+      StageTw<TPR, L / TPR, rn, Ns * r, TWS> Wn;
+      Wn.load(t, tw + next_off);
       stage_exchange<L, TPR, r, Ns, SPLIT>(v, buf, t);
+      fft_stages<L, TPR, INV, SPLIT, TWS, HALF, Ns * r, next_off, rest...>(v, buf, t, tw, Wn);
     }
-    fft_stages<L, TPR, INV, SPLIT, TWS, HALF, Ns * r, next_off, rest...>(v, buf, t, tw, Wn);
   }
 }
 
 template <class P, bool INV, bool SPLIT, int TWS, bool HALF, int r0, int... Rs>
 __device__ __forceinline__ void fft_run(Radices<r0, Rs...>, float2 (&v)[P::R], void* buf, int t, const float2* tw) {
-  const StageTw<P::TPR, P::R, r0, 1, TWS> W0{};  // the first stage has no twiddles
+  StageTw<P::TPR, P::R, r0, 1, TWS> W0{};  // the first stage has no twiddles
   fft_stages<P::L, P::TPR, INV, SPLIT, TWS, HALF, 1, 0, r0, Rs...>(v, buf, t, tw, W0);
 }
 
