@@ -163,9 +163,33 @@ __device__ __forceinline__ void dft_odd(float2 (&a)[N]) {
   for (int i = 0; i < N; ++i) a[i] = out[i];
 }
 
+// Split-radix combination (Duhamel and Hollmann, 1984): with E the DFT of
+// the even samples, O1 and O3 those of the samples 1 and 3 mod 4, w the
+// N-th root of unity of the transform's sign, and for k < N/4
+//   s = w^k O1[k] + w^{3k} O3[k],  d = w^k O1[k] - w^{3k} O3[k],
+// X[k] = E[k] + s, X[k + N/2] = E[k] - s, and X[k + N/4], X[k + 3N/4] =
+// E[k + N/4] -/+ i d (forward; the signs swap for the inverse), since
+// w^{N/4} = -i (forward) and w^{3N/4} = +i.
+template <int N, bool INV, int K = 0>
+__device__ __forceinline__ void split_combine(float2 (&out)[N], const float2 (&e)[N / 2], const float2 (&o1)[N / 4],
+                                              const float2 (&o3)[N / 4]) {
+  if constexpr (K < N / 4) {
+    const float2 p = mul_w<N, K, INV>(o1[K]);
+    const float2 q = mul_w<N, 3 * K, INV>(o3[K]);
+    const float2 sm = cadd(p, q), df = csub(p, q);
+    const float2 jd = INV ? make_float2(-df.y, df.x) : make_float2(df.y, -df.x);
+    out[K] = cadd(e[K], sm);
+    out[K + N / 2] = csub(e[K], sm);
+    out[K + N / 4] = cadd(e[K + N / 4], jd);
+    out[K + 3 * N / 4] = csub(e[K + N / 4], jd);
+    split_combine<N, INV, K + 1>(out, e, o1, o3);
+  }
+}
+
 // In-place length-N DFT of a register array (natural order in and out):
-// radix-2 decimation in time for even N, down to a length-4 kernel, or to
-// an odd length (3, 5, 7) evaluated from its symmetric pairs.
+// split-radix decimation in time for N divisible by 4 (except 8), radix 2
+// for other even N, down to a length-4 kernel, or to an odd length (3, 5, 7)
+// evaluated from its symmetric pairs.
 template <int N, bool INV>
 __device__ __forceinline__ void dft(float2 (&a)[N]) {
   if constexpr (N == 1) {
@@ -184,7 +208,8 @@ __device__ __forceinline__ void dft(float2 (&a)[N]) {
     a[2] = csub(t0, t2);
     a[1] = cadd(t1, t3);
     a[3] = csub(t1, t3);
-  } else {
+  } else if constexpr (N % 4 != 0 || N == 8) {
+    // Radix 2 (for N = 8 it takes fewer instructions than the split form).
     float2 e[N / 2], o[N / 2];
 #pragma unroll
     for (int i = 0; i < N / 2; ++i) {
@@ -194,12 +219,28 @@ __device__ __forceinline__ void dft(float2 (&a)[N]) {
     dft<N / 2, INV>(e);
     dft<N / 2, INV>(o);
     combine<N, INV>(a, e, o);
+  } else {
+    // Split radix: the even samples as one half-length DFT, the samples
+    // 1 mod 4 and 3 mod 4 as two quarter-length DFTs (see split_combine).
+    float2 e[N / 2], o1[N / 4], o3[N / 4];
+#pragma unroll
+    for (int i = 0; i < N / 2; ++i) e[i] = a[2 * i];
+#pragma unroll
+    for (int i = 0; i < N / 4; ++i) {
+      o1[i] = a[4 * i + 1];
+      o3[i] = a[4 * i + 3];
+    }
+    dft<N / 2, INV>(e);
+    dft<N / 4, INV>(o1);
+    dft<N / 4, INV>(o3);
+    split_combine<N, INV>(a, e, o1, o3);
   }
 }
 
-// Length-N DFT whose inputs N/2..N-1 are zero (they are not read): split by
-// output parity, X[2m] = DFT_{N/2}(a)[m] and X[2m+1] = DFT_{N/2}(a w^j)[m],
-// which drops the first level of additions.
+// Length-N DFT whose inputs N/2..N-1 are zero (they are not read).  Powers
+// of two from 16: split radix, whose three parts have zero upper halves of
+// their own.  Otherwise split by output parity, X[2m] = DFT_{N/2}(a)[m] and
+// X[2m+1] = DFT_{N/2}(a w^j)[m], which drops the first level of additions.
 template <int N, bool INV, int J = 0>
 __device__ __forceinline__ void twist_half(float2 (&hi)[N / 2], const float2 (&a)[N]) {
   if constexpr (J < N / 2) {
@@ -211,6 +252,20 @@ template <int N, bool INV>
 __device__ __forceinline__ void dft_half_in(float2 (&a)[N]) {
   if constexpr (N == 1) {
     return;
+  } else if constexpr (N >= 16 && (N & (N - 1)) == 0) {
+    // Split radix with each part's own zero upper half.
+    float2 e[N / 2], o1[N / 4], o3[N / 4];
+#pragma unroll
+    for (int i = 0; i < N / 4; ++i) e[i] = a[2 * i];
+#pragma unroll
+    for (int i = 0; i < N / 8; ++i) {
+      o1[i] = a[4 * i + 1];
+      o3[i] = a[4 * i + 3];
+    }
+    dft_half_in<N / 2, INV>(e);
+    dft_half_in<N / 4, INV>(o1);
+    dft_half_in<N / 4, INV>(o3);
+    split_combine<N, INV>(a, e, o1, o3);
   } else {
     float2 lo[N / 2], hi[N / 2];
 #pragma unroll
