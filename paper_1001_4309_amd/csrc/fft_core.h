@@ -631,8 +631,9 @@ __device__ __forceinline__ void stage_compute(float2 (&v)[L / TPR], void* __rest
 
 // Exchange after a stage: outputs (in LDS, or in v for SPLIT) are reloaded as
 // element t + TPR * i of the next stage's input.
+// An inactive row (active false) only meets the exchange's barriers.
 template <int L, int TPR, int r, int Ns, bool SPLIT>
-__device__ __forceinline__ void stage_exchange(float2 (&v)[L / TPR], void* __restrict__ buf, int t) {
+__device__ __forceinline__ void stage_exchange(float2 (&v)[L / TPR], void* __restrict__ buf, int t, bool active) {
   constexpr int R = L / TPR;
   constexpr int nb = R / r;
   constexpr bool WAVE = TPR <= 64;
@@ -640,31 +641,41 @@ __device__ __forceinline__ void stage_exchange(float2 (&v)[L / TPR], void* __res
   float* fbuf = static_cast<float*>(buf);
   if constexpr (!SPLIT) {
     lds_sync<WAVE>();
+    if (active) {
 #pragma unroll
-    for (int i = 0; i < R; ++i) v[i] = cbuf[lds_ridx<TPR>(t, i)];
+      for (int i = 0; i < R; ++i) v[i] = cbuf[lds_ridx<TPR>(t, i)];
+    }
     lds_sync<WAVE>();
   } else {
     // Real parts, then imaginary parts, through a float buffer of L slots.
+    if (active) {
 #pragma unroll
-    for (int q = 0; q < nb; ++q) {
-      const int wb = lds_wbase<r, Ns>(t + TPR * q);
+      for (int q = 0; q < nb; ++q) {
+        const int wb = lds_wbase<r, Ns>(t + TPR * q);
 #pragma unroll
-      for (int k = 0; k < r; ++k) fbuf[wb + lds_woff<r, Ns>(k)] = v[q + k * nb].x;
+        for (int k = 0; k < r; ++k) fbuf[wb + lds_woff<r, Ns>(k)] = v[q + k * nb].x;
+      }
     }
     lds_sync<WAVE>();
     // In place: every old real part is already in LDS.
+    if (active) {
 #pragma unroll
-    for (int i = 0; i < R; ++i) v[i].x = fbuf[lds_ridx<TPR>(t, i)];
-    lds_sync<WAVE>();
-#pragma unroll
-    for (int q = 0; q < nb; ++q) {
-      const int wb = lds_wbase<r, Ns>(t + TPR * q);
-#pragma unroll
-      for (int k = 0; k < r; ++k) fbuf[wb + lds_woff<r, Ns>(k)] = v[q + k * nb].y;
+      for (int i = 0; i < R; ++i) v[i].x = fbuf[lds_ridx<TPR>(t, i)];
     }
     lds_sync<WAVE>();
+    if (active) {
 #pragma unroll
-    for (int i = 0; i < R; ++i) v[i].y = fbuf[lds_ridx<TPR>(t, i)];
+      for (int q = 0; q < nb; ++q) {
+        const int wb = lds_wbase<r, Ns>(t + TPR * q);
+#pragma unroll
+        for (int k = 0; k < r; ++k) fbuf[wb + lds_woff<r, Ns>(k)] = v[q + k * nb].y;
+      }
+    }
+    lds_sync<WAVE>();
+    if (active) {
+#pragma unroll
+      for (int i = 0; i < R; ++i) v[i].y = fbuf[lds_ridx<TPR>(t, i)];
+    }
     lds_sync<WAVE>();
   }
 }
@@ -736,10 +747,11 @@ __device__ __forceinline__ void lane_swap_exchange(float2 (&v)[R]) {
 // Stage (Ns, r) with its twiddles W already loaded (or, streamed, their
 // first butterfly's); loads the next stage's before this stage's exchange.
 template <int L, int TPR, bool INV, bool SPLIT, int TWS, bool HALF, int Ns, int OFF, int r, int... rest, class TWH>
-__device__ __forceinline__ void fft_stages(float2 (&v)[L / TPR], void* buf, int t, const float2* tw, TWH& W) {
+__device__ __forceinline__ void fft_stages(float2 (&v)[L / TPR], void* buf, int t, const float2* tw, TWH& W,
+                                           bool active) {
   constexpr bool last = sizeof...(rest) == 0;
   constexpr int prune = !HALF ? 0 : (!INV && Ns == 1) ? 1 : (INV && last) ? 2 : 0;
-  stage_compute<L, TPR, r, Ns, INV, last, SPLIT, prune>(v, buf, t, W);
+  if (active) stage_compute<L, TPR, r, Ns, INV, last, SPLIT, prune>(v, buf, t, W);
   if constexpr (!last) {
     constexpr int next_off = OFF + (Ns > 1 ? (r - 1) * Ns : 0);
     constexpr int rn = Radices<rest...>::first;
@@ -747,24 +759,27 @@ __device__ __forceinline__ void fft_stages(float2 (&v)[L / TPR], void* buf, int 
       using Full = StageTw<TPR, L / TPR, rn, Ns * r, TWS>;
       using Stream = StageTwStream<TPR, L / TPR, rn, Ns * r, TWS>;
       constexpr bool stream = !Full::SAME && Full::nq > 1 && (TWS == kTwGlobal || TWS == kTwShared);
-      std::conditional_t<stream, Stream, Full> Wn;
-      Wn.load(t, tw + next_off);
-      lane_swap_exchange<TPR, L / TPR, r, Ns>(v);
+      std::conditional_t<stream, Stream, Full> Wn{};
+      if (active) {
+        Wn.load(t, tw + next_off);
+        lane_swap_exchange<TPR, L / TPR, r, Ns>(v);
+      }
       __builtin_amdgcn_sched_barrier(0);
-      fft_stages<L, TPR, INV, SPLIT, TWS, HALF, Ns * r, next_off, rest...>(v, buf, t, tw, Wn);
+      fft_stages<L, TPR, INV, SPLIT, TWS, HALF, Ns * r, next_off, rest...>(v, buf, t, tw, Wn, active);
     } else {
-      StageTw<TPR, L / TPR, rn, Ns * r, TWS> Wn;
-      Wn.load(t, tw + next_off);
-      stage_exchange<L, TPR, r, Ns, SPLIT>(v, buf, t);
-      fft_stages<L, TPR, INV, SPLIT, TWS, HALF, Ns * r, next_off, rest...>(v, buf, t, tw, Wn);
+      StageTw<TPR, L / TPR, rn, Ns * r, TWS> Wn{};
+      if (active) Wn.load(t, tw + next_off);
+      stage_exchange<L, TPR, r, Ns, SPLIT>(v, buf, t, active);
+      fft_stages<L, TPR, INV, SPLIT, TWS, HALF, Ns * r, next_off, rest...>(v, buf, t, tw, Wn, active);
     }
   }
 }
 
 template <class P, bool INV, bool SPLIT, int TWS, bool HALF, int r0, int... Rs>
-__device__ __forceinline__ void fft_run(Radices<r0, Rs...>, float2 (&v)[P::R], void* buf, int t, const float2* tw) {
+__device__ __forceinline__ void fft_run(Radices<r0, Rs...>, float2 (&v)[P::R], void* buf, int t, const float2* tw,
+                                        bool active) {
   StageTw<P::TPR, P::R, r0, 1, TWS> W0{};  // the first stage has no twiddles
-  fft_stages<P::L, P::TPR, INV, SPLIT, TWS, HALF, 1, 0, r0, Rs...>(v, buf, t, tw, W0);
+  fft_stages<P::L, P::TPR, INV, SPLIT, TWS, HALF, 1, 0, r0, Rs...>(v, buf, t, tw, W0, active);
 }
 
 // Forward (INV = false) or unnormalised inverse (INV = true) FFT of one row
@@ -774,9 +789,11 @@ __device__ __forceinline__ void fft_run(Radices<r0, Rs...>, float2 (&v)[P::R], v
 // HALF: a forward transform whose input's upper half (elements L/2..L-1) is
 // zero, or an inverse transform of which only the lower half of the output
 // is used; the first (forward) or last (inverse) stage skips that half.
+// active false: the row computes nothing and only meets the barriers of a
+// transform whose row spans several wavefronts (v is left as it was).
 template <class P, bool INV, bool SPLIT, int TWS = kTwGlobal, bool HALF = false>
-__device__ __forceinline__ void fft_row(float2 (&v)[P::R], void* buf, int t, const float2* tw) {
-  fft_run<P, INV, SPLIT, TWS, HALF>(typename P::Rad{}, v, buf, t, tw);
+__device__ __forceinline__ void fft_row(float2 (&v)[P::R], void* buf, int t, const float2* tw, bool active = true) {
+  fft_run<P, INV, SPLIT, TWS, HALF>(typename P::Rad{}, v, buf, t, tw, active);
 }
 
 // Twiddle table entry e of a shape's table (layout of TwInfo), evaluated in FP64

@@ -784,7 +784,7 @@ void pack_persist(const sfd_plan_s* P, CallDescs* D, char* ws, bool tables, std:
     g.tw = tw;
     t += count;
   };
-  if (tables) add(sfd::kItemSetup, 2 * V, 0, 0, nullptr, nullptr);  // spectra, then tables, per view
+  if (tables) add(sfd::kItemSetup, 3 * V, 0, 0, nullptr, nullptr);  // y spectra, x spectra, tables, per view
   if (P->nstrips > 0) add(sfd::kItemStrip, P->nstrips, 0, 0, nullptr, nullptr);
   const auto* d_rows = reinterpret_cast<const sfd::RowJob*>(dbase + off_rows);
   const auto* d_pass = reinterpret_cast<const sfd::PassArgs*>(dbase + off_pass);

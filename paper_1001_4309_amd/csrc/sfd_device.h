@@ -242,8 +242,8 @@ struct SpecShape {
 
 // One kernel spectrum H = FFT_L(h) / L by the TPR threads of row g of a
 // spectrum workgroup (t = thread in the row, r = thread in the group of
-// kSetupThreads that shares the LDS area lds); J null: the row computes on
-// zeros and stores nothing (it still takes part in the barriers).  Each
+// kSetupThreads that shares the LDS area lds); J null: the row computes and
+// stores nothing (it still takes part in the barriers and the table copy).  Each
 // thread evaluates h straight into its FFT input slots (element t + TPR i).
 // The twiddles come from the spectrum-shape table (built once per
 // workspace): staged in LDS (SpecShape::TW_LDS, loads issued before h is
@@ -260,7 +260,9 @@ __device__ __forceinline__ void gst_c(float2* p, unsigned i, float2 v) {
   }
 }
 
-template <int L, bool WT = false>
+// LAGS: the group's h values are already in its exchange row (evaluated by
+// the caller with more threads; kSetupThreads-wide transforms only).
+template <int L, bool WT = false, bool LAGS = false>
 __device__ __forceinline__ void spectrum_row(const AxisJob* J, const float2* tw, void* lds, int g, int t, int r) {
   using P = SpecPlan<L>;
   using Sh = SpecShape<L>;
@@ -288,7 +290,7 @@ __device__ __forceinline__ void spectrum_row(const AxisJob* J, const float2* tw,
     // (not in use yet) and every thread picks its entries from there.
     float2* const e = static_cast<float2*>(lds);
     const int M = Jv.n0 > Jv.n1 ? Jv.n0 : Jv.n1;
-    if (J)
+    if (J && !LAGS)
       for (int m = r; m < M; m += kSetupThreads) e[m] = kernel_lag(Jv, m);
     __syncthreads();
 #pragma unroll
@@ -307,10 +309,12 @@ __device__ __forceinline__ void spectrum_row(const AxisJob* J, const float2* tw,
   if constexpr (Sh::TW_LDS) {
     copy_store<NT, kSetupThreads>(tws, twr, r);
     __syncthreads();
-    fft_row<P, false, kSpecSplit, kTwShared>(v, static_cast<char*>(lds) + g * row_lds_bytes<L, kSpecSplit>(), t, tws);
+    fft_row<P, false, kSpecSplit, kTwShared>(v, static_cast<char*>(lds) + g * row_lds_bytes<L, kSpecSplit>(), t, tws,
+                                             J != nullptr);
   } else {
     if constexpr (TPR == kSetupThreads) __syncthreads();  // every lag read before the exchanges write
-    fft_row<P, false, kSpecSplit, kTwGlobal>(v, static_cast<char*>(lds) + g * row_lds_bytes<L, kSpecSplit>(), t, tw);
+    fft_row<P, false, kSpecSplit, kTwGlobal>(v, static_cast<char*>(lds) + g * row_lds_bytes<L, kSpecSplit>(), t, tw,
+                                             J != nullptr);
   }
   if (!Hg) return;
   const float inv = 1.0f / (float)L;

@@ -207,13 +207,14 @@ constexpr int kSetupThreads = 256;
 // items from a ticket counter in the order of the segments below (each item
 // depends only on items with smaller tickets, so the launch cannot deadlock
 // whatever number of its workgroups are resident):
-//   kItemSetup  two per view: its kernel spectra Hx, Hy (half of the
-//               workgroup each), and its pre/post chirp tables;
+//   kItemSetup  three per view: its kernel spectrum Hy, its kernel
+//               spectrum Hx, and its pre/post chirp tables;
 //   kItemStrip  kStripW columns of a hologram rewritten column-major (the
 //               copy the column pass reads, see TileJob);
-//   kItemCol    a column-pass tile; waits for its view's setup item and the
-//               strip holding its columns;
-//   kItemRow    a row-pass tile; waits for every column tile of its view.
+//   kItemCol    a column-pass tile; waits for its view's Hy and the strip
+//               holding its columns;
+//   kItemRow    a row-pass tile; waits for every column tile of its view,
+//               its Hx and its chirp tables.
 // Completion counters live in the workspace (PersistSync).  The last
 // workgroup to leave resets them to zero, so every launch, and every replay
 // of a graph holding it, starts from zero without a memset.
@@ -251,8 +252,8 @@ struct PersistArgs {
 // a counter that workgroups poll shares no line with one they advance):
 // [0] ticket, [1] workgroups that left, [2] error word (set when a
 // dependency wait gave up; never reset by the kernel), then per view its
-// spectra, chirp-table and column-tile counters, then one counter per strip
-// item.
+// Hy counter (target 1), its Hx and chirp-table counter (target 2) and its
+// column-tile counter, then one counter per strip item.
 constexpr int kSyncStride = 64;
 constexpr int kSyncTicket = 0, kSyncExit = 1, kSyncErr = 2, kSyncHead = 3;
 __host__ __device__ inline int persist_sync_counters(int nview, int nstrips) { return kSyncHead + 3 * nview + nstrips; }

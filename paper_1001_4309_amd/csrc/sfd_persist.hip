@@ -99,48 +99,45 @@ __device__ __forceinline__ void signal_count(uint32_t* p) {
   if (threadIdx.x == 0) sync_add(p, 1u);
 }
 
-// Setup item of view v: the kernel spectra Hx, Hy with the setup kernel's
-// transform shape (the two launch modes then give bit-identical results),
-// the first half of the workgroup on x and the second on y (one after the
-// other when their lengths differ: every barrier of a transform shape is then
-// met by the whole workgroup), then the pre/post chirp tables of both axes.
+// Spectrum item: one kernel spectrum (one axis of one view) with the setup
+// kernel's transform shape (the two launch modes then give bit-identical
+// results), written through (later items read it on other XCDs).  The
+// first half of the workgroup runs the transform; the second half helps
+// evaluate h where the shape evaluates it once per lag, and then only meets
+// the transform's barriers, so each SIMD runs one transform's wavefront.
 template <int L>
-__device__ __forceinline__ void spectrum_half(const AxisJob* J, const float2* tw, unsigned char* lds, int tid) {
-  // (spectra written through: later items read them on other XCDs)
+__device__ __forceinline__ void spectrum_item(const AxisJob* J, const float2* tw, unsigned char* lds, int tid) {
   constexpr int TPR = SpecPlan<L>::TPR;
   const int half = tid / kSetupThreads, r = tid - half * kSetupThreads;
   const int g = TPR >= 64 ? uniform(r / TPR) : r / TPR;
   const int t = r - g * TPR;
-  spectrum_row<L, true>(g == 0 ? J : nullptr, tw, lds + half * SpecShape<L>::BYTES, g, t, r);
-}
-__device__ __forceinline__ void spectra_pass(int L, const AxisJob* jx, const AxisJob* jy, const float2* tw,
-                                             unsigned char* lds, int tid) {
-  const AxisJob* J = tid < kSetupThreads ? jx : jy;
-  switch (L) {
-    case 2048: spectrum_half<2048>(J, tw, lds, tid); break;
-    case 1792: spectrum_half<1792>(J, tw, lds, tid); break;
-    case 1536: spectrum_half<1536>(J, tw, lds, tid); break;
-    case 1280: spectrum_half<1280>(J, tw, lds, tid); break;
-    default: spectrum_half<1024>(J, tw, lds, tid); break;
+  if constexpr (TPR == kSetupThreads) {
+    const AxisJob Jv = load_uniform(J);
+    const int M = Jv.n0 > Jv.n1 ? Jv.n0 : Jv.n1;
+    float2* const e = reinterpret_cast<float2*>(lds);  // the first half's exchange row
+    for (int m = tid; m < M; m += kPersistThreads) e[m] = kernel_lag(Jv, m);
+    spectrum_row<L, true, true>(half == 0 ? J : nullptr, tw, lds + half * SpecShape<L>::BYTES, g, t, r);
+  } else {
+    spectrum_row<L, true>(half == 0 && g == 0 ? J : nullptr, tw, lds + half * SpecShape<L>::BYTES, g, t, r);
   }
 }
 
-// Setup items of view v, two per view so that they run side by side: part 0
-// builds the kernel spectra, part 1 the chirp tables of both axes (each
-// axis's fields read once).
+// Setup items of view v, three per view so that they run side by side:
+// part 0 its y spectrum (what its column tiles wait for), part 1 its x
+// spectrum, part 2 the chirp tables of both axes (each axis's fields read
+// once).
 __device__ __forceinline__ void persist_setup(const PersistArgs& A, int v, int part, unsigned char* lds, int tid) {
   const AxisJob* X = &A.axis[2 * v];
   const AxisJob* Y = &A.axis[2 * v + 1];
-  if (part == 0) {
-    const int lx = X->L, ly = Y->L;
-    const float2* twx = A.tw_view[2 * v];
-    const float2* twy = A.tw_view[2 * v + 1];
-    if (lx == ly) {
-      spectra_pass(lx, X, Y, twx, lds, tid);
-    } else {
-      spectra_pass(lx, X, nullptr, twx, lds, tid);
-      __syncthreads();
-      spectra_pass(ly, nullptr, Y, twy, lds, tid);
+  if (part < 2) {
+    const AxisJob* J = part == 0 ? Y : X;
+    const float2* tw = A.tw_view[2 * v + (part == 0 ? 1 : 0)];
+    switch (J->L) {
+      case 2048: spectrum_item<2048>(J, tw, lds, tid); break;
+      case 1792: spectrum_item<1792>(J, tw, lds, tid); break;
+      case 1536: spectrum_item<1536>(J, tw, lds, tid); break;
+      case 1280: spectrum_item<1280>(J, tw, lds, tid); break;
+      default: spectrum_item<1024>(J, tw, lds, tid); break;
     }
     return;
   }
@@ -313,10 +310,12 @@ __global__ void __launch_bounds__(kPersistThreads) persist_kernel(const PersistA
     };
     switch (sg.kind) {
       case kItemSetup: {
-        // Items 0 .. nview-1: spectra of view i; nview .. 2 nview - 1: tables.
-        const int v = local < nview ? local : local - nview;
-        persist_setup(A, v, local < nview ? 0 : 1, lds, tid);
-        signal_count(local < nview ? &spec_done[v * kSyncStride] : &tab_done[v * kSyncStride]);
+        // Items 0 .. nview-1: y spectrum of view i (its column tiles wait
+        // for spec_done); nview .. 2 nview - 1: x spectrum, then the chirp
+        // tables (its row tiles wait for both on tab_done).
+        const int part = local / nview, v = local - part * nview;
+        persist_setup(A, v, part, lds, tid);
+        signal_count(part == 0 ? &spec_done[v * kSyncStride] : &tab_done[v * kSyncStride]);
         break;
       }
       case kItemStrip: {
@@ -363,7 +362,7 @@ __global__ void __launch_bounds__(kPersistThreads) persist_kernel(const PersistA
         const int ntw = twiddle_pairs(sg.L);
         stage_load(twa, sg.tw, ntw, tid);
         wait_counts(sync, &col_done[view * kSyncStride], (uint32_t)A.col_tiles[view],
-                    A.wait_setup ? &tab_done[view * kSyncStride] : nullptr, 1u);
+                    A.wait_setup ? &tab_done[view * kSyncStride] : nullptr, 2u);
         stage_store(reinterpret_cast<float2*>(lds), twa, ntw, tid);
         switch (sg.L) {
           case 2048: persist_row<2048>(sg, local, lds, tid, tail); break;
