@@ -453,9 +453,15 @@ constexpr int row_lds_bytes() {
 }
 
 // Padded LDS index of stage output k of a butterfly, split as a runtime base
-// (per butterfly) plus a compile-time offset.  With power-of-two radices that
-// divide 32 the split is exact: pad(A + jm + k Ns) = wbase + woff(k) with
-// A = (j - jm) r (see the derivation checked in the tests of this layout).
+// (per butterfly) plus a compile-time offset: pad(A + jm + k Ns) = wbase +
+// woff(k) with A = (j - jm) r, a multiple of Ns r.  Exact for power-of-two
+// Ns and r:
+// - Ns a multiple of 32: k Ns is a multiple of 32, so its padding separates;
+// - Ns r a multiple of 32 (Ns < 32): A is a multiple of 32, and jm plus
+//   k Ns mod 32 stays below 32 (jm < Ns, and Ns divides 32), so the padding
+//   of A + jm + k Ns is A/32 + floor(k Ns / 32);
+// - Ns r below 32: A mod 32 + jm + k Ns < A mod 32 + Ns r <= 32, so the
+//   padding is A/32 alone.
 template <int r, int Ns>
 __device__ __forceinline__ int lds_wbase(int j) {
   const int jm = j & (Ns - 1);
