@@ -1150,21 +1150,32 @@ __device__ __forceinline__ void col_body(const PassArgs& args, const float2* __r
   if constexpr (DEFER) {
     if (tid0 == 0) r0 = dep.ready();
   }
-  // SELF: the chirps are evaluated before any load is in flight (they need
-  // many registers of their own).
+  // SELF: the twiddle table's loads (and the spectrum's, when it is not
+  // deferred) and the first columns' loads are issued before the chirps are
+  // evaluated, so that their latency overlaps that evaluation.
+  constexpr int NTW = T::tw_n / 2, NH = L / 2;
+  float4 twr[SELF ? CopyShare<NTW, THREADS>::KA : 1];
+  float4 hr[SELF && !DEFER ? CopyShare<NH, THREADS>::KA : 1];
   if constexpr (SELF) {
+    // Both axis jobs first: their loads (a chain behind the row job's) then
+    // overlap each other and the loads below.
+    const AxisJob ay = load_uniform(args.axis + J.ax_pre);
+    const AxisJob ax = load_uniform(args.axis + J.ax_scale);
+    copy_load<NTW, THREADS>(twr, tw, tid0);
+    if constexpr (!DEFER) copy_load<NH, THREADS, CopyShare<NH, THREADS>::KA, COH>(hr, H, tid0);
+    load(0, t, tid0);
     if (pre) {
-      const AxisJob ay = load_uniform(args.axis + J.ax_pre);
 #pragma unroll
       for (int k = 0; k < RIN * TPR / THREADS; ++k) ps[tid0 + k * THREADS] = pre_value(ay, tid0 + k * THREADS);
     }
     if (colscale && tid0 < GC) {
       const int c = c0 + tid0;
-      csl[tid0] = pre_value(load_uniform(args.axis + J.ax_scale), c < ncols ? c : ncols - 1);
+      csl[tid0] = pre_value(ax, c < ncols ? c : ncols - 1);
     }
     sched_fence();
+  } else {
+    load(0, t, tid0);
   }
-  load(0, t, tid0);
 
   bool ready = true;  // the spectrum is copied with the other tables
   if constexpr (DEFER) {
@@ -1174,7 +1185,12 @@ __device__ __forceinline__ void col_body(const PassArgs& args, const float2* __r
     ready = uniform(*rdy) != 0;
   }
   if constexpr (T::on) {
-    stage_tables<L, THREADS, PF && !SELF, RIN * TPR, COH, !DEFER>(tws, hs, ps, tw, H, pre, tid0);
+    if constexpr (SELF) {
+      copy_store<NTW, THREADS>(tws, twr, tid0);
+      if constexpr (!DEFER) copy_store<NH, THREADS>(hs, hr, tid0);
+    } else {
+      stage_tables<L, THREADS, PF, RIN * TPR, COH, !DEFER>(tws, hs, ps, tw, H, pre, tid0);
+    }
     if constexpr (DEFER) {
       if (ready) stage_spectrum<L, THREADS, COH>(hs, H, tid0);
     }
