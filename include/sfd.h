@@ -315,12 +315,14 @@ enum {
  *                          pass, with the tile widths of sfd_set_schedule.
  *   SFD_LAUNCH_PERSISTENT  one launch per call.  Its workgroups take work
  *                          items in a fixed order from a ticket counter: per
- *                          view a setup item (spectra and chirp tables), the
+ *                          view three setup items (its y kernel spectrum, its
+ *                          x kernel spectrum, its chirp tables), the
  *                          hologram copies in strips of 16 columns, the
  *                          column tiles, the row tiles.  An item waits on
  *                          completion counters for the items it reads (a
- *                          column tile for its view's setup and its strip, a
- *                          row tile for every column tile of its view), and
+ *                          column tile for its view's y spectrum and its
+ *                          strip, a row tile for every column tile of its
+ *                          view, its x spectrum and its tables), and
  *                          those always hold smaller tickets, so the launch
  *                          completes however many of its workgroups are
  *                          resident.  The counters live in the workspace; the

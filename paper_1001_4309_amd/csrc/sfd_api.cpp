@@ -590,7 +590,7 @@ sfd_status build_descs(sfd_plan_s* P, const void* holo, const double* z, void* c
     }
   }
   // The setup launch groups the spectra by length; the persistent launch's
-  // setup items take a view's two axis jobs at 2v and 2v + 1.
+  // setup items find a view's two axis jobs at 2v (x) and 2v + 1 (y).
   if (!(P->flags & SFD_PER_VIEW_LAUNCH) && !P->persist)
     std::stable_sort(ax.begin(), ax.end(), [](const AxisTmp& a, const AxisTmp& b) { return a.L < b.L; });
   D->axis.clear();

@@ -207,7 +207,7 @@ __device__ __forceinline__ void persist_strip(const TileJob* Jp, int c0, unsigne
 // CPLX: the kernel instance for complex holograms (column specialisation 1);
 // the real-hologram instance holds specialisations 2 and 3.  Keeping them
 // apart keeps each instance's register need that of its largest body.
-// A column tile's dependency on its view's spectra item (col_body's DEFER):
+// A column tile's dependency on its view's y-spectrum item (col_body's DEFER):
 // ready() asks without waiting, the call waits (spec null: nothing to wait
 // for, the tables are kept from an earlier call).
 struct SpecDep {
@@ -220,7 +220,7 @@ struct SpecDep {
 };
 
 // Column tiles evaluate their pre-chirp and colscale factors themselves
-// (col_body's SELF), so they depend only on their view's spectra item, and
+// (col_body's SELF), so they depend only on their view's y-spectrum item, and
 // real-hologram tiles wait for it (dep) only before their first spectrum
 // multiply (DEFER).
 template <int L, bool CPLX, typename TAIL, typename DEP>
