@@ -251,11 +251,25 @@ def cpu_baseline(w, seconds: float):
                                f"(numpy FFT, one thread), {dt_fft:.2f} s"}
 
 
-def bench_backward(dev, steps: int, warmup: int):
+def apply_schedule(plan, schedule: str) -> None:
+    """A --schedule string (launch=..., lengths=..., col<L>=G, row<L>=G) onto a plan."""
+    for item in schedule.split(","):
+        key, g = item.split("=")
+        if key == "launch":
+            plan.set_launch(g == "persistent")
+        elif key == "lengths":
+            plan.set_lengths(0 if g == "pow2" else
+                             sum({"1280": 1, "1536": 2, "1792": 4}[x] for x in g.split(":")[1].split("+")))
+        else:
+            plan.set_schedule(int(key[3:]), key.startswith("col"), int(g))
+
+
+def bench_backward(dev, steps: int, warmup: int, schedule: str = ""):
     """Forward (intensity and field) plus backward (field gradient and dL/dz)
     of the differentiation workload: 16 complex 1024^2 fields, one view each,
     L = 2048.  The loss gradient dL/dI = 2 (I - T) is formed once, outside the
-    timed region; the timed step is the two library calls."""
+    timed region; the timed step is the two library calls.  schedule: tile
+    widths to use instead of autotuning (as --schedule)."""
     import numpy as np
     import torch
 
@@ -268,7 +282,10 @@ def bench_backward(dev, steps: int, warmup: int):
     fields = torch.from_numpy(w.holograms).to(dev)
     outs = plan.new_outputs()
     nv = len(w.views)
-    plan.autotune(fields, reps=5, outs=outs)  # the backward's passes use the same tile widths
+    if schedule:
+        apply_schedule(plan, schedule)
+    else:
+        plan.autotune(fields, reps=5, outs=outs)  # the backward's passes use the same tile widths
     res = plan.reconstruct(fields, outs=outs)
     gi = [2.0 * (res[v] - 0.5 * res[v].mean()) for v in range(nv)]
     torch.cuda.synchronize()
@@ -407,15 +424,7 @@ def measure(w, dev, args, steps: int, warmup: int, config: int, tune: bool = Tru
     outs = plan.new_outputs()
     nv = len(w.views)
     if schedule:
-        for item in schedule.split(","):
-            key, g = item.split("=")
-            if key == "launch":
-                plan.set_launch(g == "persistent")
-            elif key == "lengths":
-                plan.set_lengths(0 if g == "pow2" else
-                                 sum({"1280": 1, "1536": 2, "1792": 4}[x] for x in g.split(":")[1].split("+")))
-            else:
-                plan.set_schedule(int(key[3:]), key.startswith("col"), int(g))
+        apply_schedule(plan, schedule)
     elif tune:
         plan.autotune(holo, reps=10, outs=outs)
     sched = {f"{k[0]}{k[1]}": g for k, g in sorted(plan.schedule().items())}
@@ -616,6 +625,9 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tile widths")
     ap.add_argument("--no-backward", action="store_true", help="skip the forward + backward measurement")
     ap.add_argument("--no-streaming", action="store_true", help="skip the real-time loop measurement")
+    ap.add_argument("--backward-only", action="store_true",
+                    help="only the forward + backward measurement (config 4), printed as one JSON line; "
+                         "--schedule then fixes its tile widths instead of autotuning")
     ap.add_argument("--schedule", default="",
                     help="tile widths to use instead of autotuning, e.g. col2048=4,row2048=4")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -659,6 +671,12 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy: {args.calib_copy_mib} MiB read + {args.calib_copy_mib} MiB written")
         del a, b
+    if args.backward_only:
+        backward = bench_backward(dev, max(1, args.steps), max(1, args.warmup), args.schedule)
+        log(f"forward + backward: {backward['ms_per_step']:.3f} ms per 16 fields "
+            f"({backward['fields_per_s']:.0f} fields/s; forward {backward['forward_ms']:.3f} ms)")
+        print(json.dumps({"backward": backward}), flush=True)
+        return
     tune = not args.no_autotune
     w = workloads.CONFIGS[args.config]()
     nv = len(w.views)

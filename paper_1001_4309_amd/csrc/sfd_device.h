@@ -633,6 +633,82 @@ __device__ __forceinline__ void row_accumulate(const RowJob& J, const float2 (&v
     }
   }
 }
+
+// row_accumulate for the fast kernels' N = RIN output slots: every reference
+// load of the row is issued first (branch-free: entries past n_out read the
+// last one and are not accumulated), so that one wait covers them all; then
+// the same products and sums in the same order.
+template <int TPR, int N, int R>
+__device__ __forceinline__ void row_accumulate_batched(const RowJob& J, const float2 (&v)[R], int row, bool valid,
+                                                       int t, double (&a)[4]) {
+  static_assert(N <= R, "output slots are among the row's slots");
+  if (!valid) return;
+  const int n_out = J.n_out;
+  const int mode = J.mode;
+  const bool gi = J.giref != nullptr;
+  const int64_t base = (int64_t)row * J.red_ld;
+  float2 A[N];
+  float B[N];
+  if (mode & kRedSwap) {
+    if (mode & kRedRealRef) {
+      const float* u = reinterpret_cast<const float*>(J.uref) + base;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const int m = t + TPR * i;
+        A[i] = make_float2(gld(u, (unsigned)(m < n_out ? m : n_out - 1)), 0.f);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const int m = t + TPR * i;
+        A[i] = gld(J.uref + base, (unsigned)(m < n_out ? m : n_out - 1));
+      }
+    }
+  } else if (gi) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const int m = t + TPR * i;
+      const unsigned mc = (unsigned)(m < n_out ? m : n_out - 1);
+      A[i] = gld(J.uref + base, mc);
+      B[i] = gld(J.giref + base, mc);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const int m = t + TPR * i;
+      A[i] = gld(J.gref + base, (unsigned)(m < n_out ? m : n_out - 1));
+    }
+  }
+  const double Y = row * J.yp + J.ya;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const int m = t + TPR * i;
+    if (m < n_out) {
+      float2 G, V;
+      if (mode & kRedSwap) {
+        G = v[i];
+        V = A[i];
+      } else if (gi) {
+        const float g2 = 2.0f * B[i];
+        G = make_float2(g2 * A[i].x, g2 * A[i].y);
+        V = v[i];
+      } else {
+        G = A[i];
+        V = v[i];
+      }
+      const double pr = (double)G.x * V.x + (double)G.y * V.y;
+      const double pi = (double)G.x * V.y - (double)G.y * V.x;
+      const double X = m * J.xp + J.xa;
+      const double r2 = X * X + Y * Y;
+      const double w0 = J.wc[0][0] * X + J.wc[0][1] * Y + J.wc[0][2] * r2 + J.wc[0][3];
+      const double w1 = J.wc[1][0] * X + J.wc[1][1] * Y + J.wc[1][2] * r2 + J.wc[1][3];
+      a[0] += w0 * pr;
+      a[1] += w0 * pi;
+      a[2] += w1 * pr;
+      a[3] += w1 * pi;
+    }
+  }
+}
 template <int NW>
 __device__ __forceinline__ void reduce_tile(const RowJob& J, double (&a)[4], int tile, double* sbuf) {
 #pragma unroll
@@ -999,7 +1075,9 @@ __device__ __forceinline__ void row_body(const PassArgs& args, const float2* __r
           }
         }
       }
-      if constexpr (!HALF || RED) {
+      if constexpr (RED && HALF) {
+        if (mode & kReduce) row_accumulate_batched<TPR, RL>(J, v, row, valid, tl, acc);
+      } else if constexpr (!HALF) {
         if (mode & kReduce) row_accumulate<TPR, RL>(J, v, row, valid, tl, acc);
       }
       if constexpr (PF) {
